@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused multilayer thin-film LBM step on one MI355X.
+
+Default workload: 3 layers on a 1024 x 1024 periodic film, FP32 storage and
+arithmetic (the paper's three-layer spinodal-rupture setting, Sec. IV.E),
+inputs resident in HBM.  One "step" is one full lattice Boltzmann time step
+of every layer (moments, pressures, friction, force, collision, streaming).
+
+Prints one JSON line with
+  value     layer-lattice updates per second (LU/s) of the whole job,
+  roofline  achieved HBM bandwidth of the step kernel from algorithmic bytes
+            (read 9 + write 9 populations per layer-node update) over its
+            event-timed launch duration, against the 8 TB/s peak,
+  cpu_baseline  the FP64 oracle on this host's cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2409_16659_amd/csrc/step_kernel.hpp", "paper_2409_16659_amd/csrc/mlfilm.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, launch):
+    """HBM bytes per launch from rocprofv3 counters, if they were taken on
+    the current kernel source in this launch shape; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(workload)
+    if not ent or ent.get("kernel_digest") != kernel_digest() or list(ent.get("launch", [])) != list(launch):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(film, h0, budget_s: float):
+    import oracle
+
+    o = oracle.Oracle(film)
+    o.init(h0)
+    o.step(1)  # warm-up (page faults, thread start)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    lu = film["n_layers"] * film["nx"] * film["ny"] * n
+    return {"value": lu / el, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{n} FP64 steps of the same {film['nx']}x{film['ny']} {film['n_layers']}-layer film "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="film3_2d_1024")
+    ap.add_argument("--precision", default=None, help="override the workload's storage precision")
+    ap.add_argument("--block-w", type=int, default=0)
+    ap.add_argument("--seg-h", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU-baseline budget; 0 disables it")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_16659_amd import inputs, mlfilm
+
+    if not os.path.exists(mlfilm._build.lib_path()):
+        mlfilm._build.build()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    film, h0, spec = inputs.workload(args.workload)
+    prec = args.precision or spec["precision"]
+    n_lu = film["n_layers"] * film["nx"] * film["ny"]
+    bytes_per_lu = 18 * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16dev": 2, "bf16dev": 2}[prec]
+
+    g = mlfilm.Film(film, prec, check_every=-1)
+    g.set_launch(args.block_w, args.seg_h)
+    launch = g.get_launch()
+    g.init(h0)
+    print(f"[bench] {args.workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
+          f"launch={launch} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(g.stream)
+    g.step(args.steps)
+    ev1.record(g.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    # guard: the state must still be valid after the timed steps
+    m = g.mass()
+    assert np.all(np.isfinite(m))
+
+    value = n_lu * args.steps / wall
+    achieved = bytes_per_lu * n_lu / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, launch)
+    out = {
+        "metric": "layer-lattice updates/s & % HBM roofline; surrogate/batched speedup @1e-3 L2",
+        "value": value,
+        "unit": "LU/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32"}.get(prec, "f32"),
+        "data": "synthetic",
+        "config": {"workload": args.workload, "layers": film["n_layers"], "nx": film["nx"], "ny": film["ny"],
+                   "storage": prec, "lattice": "D2Q9", "tau": film["tau"], "launch": list(launch)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_lu": bytes_per_lu, "kernel_ms": kern_ms},
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(film, h0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * mlfilm.h -- C ABI of libmlfilm, an MI355X (gfx950) implementation of the
+ * N-layer thin-film shallow-water lattice Boltzmann time step of
+ * Richter, Malgaretti & Harting, "Modeling of thin liquid films with
+ * arbitrary many layers" (arXiv 2409.16659).
+ *
+ * One step (Sec. III with the pressures and friction of Sec. II), for every
+ * lattice node x and layer i = 1..N:
+ *   h_i = sum_k f_ki, q_i = h_i U_i = sum_k c_k f_ki         (moments)
+ *   z_i = z_{i-1} + h_i, z_0 = 0                              (Sec. II, Fig. 1)
+ *   Delta_i = p_i - p_{i+1} = Lambda_i + Pi_i  (Eqs. Laplace_pressure,
+ *             disjoining_pressure, wetting_potential); p_i = sum_{j>=i} Delta_j
+ *   F_i = -h_i grad p_i + 2 mu_i h_i a_i        (Eq. force; friction from the
+ *             boundary conditions Eqs. no_slip, flux, viscous_boundary)
+ *   f_ki(x + c_k, t+1) = f_ki - (f_ki - f^eq_ki)/tau + w_k c_k.F_i / c_s^2
+ *                                              (Eqs. BGK, equilibrium_distribution)
+ * on a periodic D2Q9 lattice (c_s^2 = 1/3, dx = dt = 1).  The gradient and
+ * Laplacian, which the paper does not state, are the isotropic 9-point
+ * lattice stencils.
+ *
+ * Conventions for every function:
+ *  - Return MLF_OK or a negative mlf_status; no exception crosses the ABI.
+ *    mlf_last_error() gives a text for the last failure on a handle.
+ *  - Device memory belongs to the caller: the library never allocates or
+ *    frees device memory.  The caller sizes the two population buffers and
+ *    the scratch buffer with mlf_query_sizes() and keeps them alive until
+ *    mlf_destroy().  Host arrays are caller-owned and only read or written
+ *    during the call.
+ *  - Work is issued on the stream given to mlf_create (a hipStream_t; NULL
+ *    is the default stream).  mlf_step is asynchronous except for the guard
+ *    polls; every call that returns host data synchronises the stream.
+ *  - Fields are [N][ny][nx] row-major (x fastest).  Populations are stored
+ *    structure-of-arrays, plane (i, k) of ny rows of `pitch` elements.
+ *  - A handle is not thread-safe.
+ */
+#ifndef MLFILM_H
+#define MLFILM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLF_MAX_LAYERS 4
+#define MLF_MAX_PAIRS (MLF_MAX_LAYERS * (MLF_MAX_LAYERS + 1) / 2)
+
+typedef enum {
+  MLF_OK = 0,
+  MLF_EINVAL = -1,        /* bad argument (sizes, pointers, parameters)        */
+  MLF_EUNSUPPORTED = -2,  /* valid but not implemented on this path            */
+  MLF_EDEVICE = -3,       /* a HIP runtime call failed                          */
+  MLF_ENONFINITE = -4,    /* a layer height or flux became NaN/Inf              */
+  MLF_ENONPOSITIVE = -5,  /* a layer height became <= 0                         */
+  MLF_EUNSTABLE = -6      /* explicit friction would be unstable (see below)    */
+} mlf_status;
+
+/* Storage of the populations.  Arithmetic is FP64 for MLF_F64 and FP32
+ * otherwise.  All formats store the rest population as a deviation from the
+ * rest-state equilibrium h_ref_i (f_0 - h_ref_i), the moving ones as they
+ * are; h_ref_i is the per-layer mean of the initial heights. */
+typedef enum {
+  MLF_F64 = 0,
+  MLF_F32 = 1,
+  MLF_F16 = 2,  /* IEEE half storage of deviations, FP32 arithmetic */
+  MLF_BF16 = 3  /* bfloat16 storage of deviations, FP32 arithmetic  */
+} mlf_precision;
+
+typedef struct mlf_params {
+  int32_t n_layers;   /* N, 1..MLF_MAX_LAYERS                                  */
+  int32_t nx, ny;     /* periodic grid, >= 1 each (ny == 1: pseudo-1D film)     */
+  int32_t precision;  /* mlf_precision                                          */
+  double tau;         /* BGK relaxation time (> 0.5); 1 selects the fast path   */
+  double hstar;       /* precursor thickness h* > 0, Eq. (wetting_potential)    */
+  int32_t exp_a;      /* wetting exponents a > b >= 1 (the paper's n > m)       */
+  int32_t exp_b;
+  double gamma[MLF_MAX_LAYERS];  /* gamma_{i,i+1}, i = 1..N (gamma_N: layer N / gas) */
+  double mu[MLF_MAX_LAYERS];     /* viscosities mu_1..mu_N > 0                   */
+  double slip[MLF_MAX_LAYERS];   /* slip lengths beta_i; must be 0 (no slip)     */
+  /* spreading coefficients S_lk packed l-major: l = 0..N-1, k = 1..N-l, i.e.
+   * S_01..S_0N, S_11..S_1(N-1), ..., S_(N-1)1 (Eq. spreading_parameters). */
+  double spread[MLF_MAX_PAIRS];
+  int32_t check_every;   /* guard poll interval in steps; 0: only at the end of mlf_step */
+  int32_t allow_unstable;/* nonzero: skip the friction-stiffness check in mlf_init */
+} mlf_params;
+
+typedef struct mlf_handle mlf_handle;
+
+/* Byte sizes of each of the two population buffers and of the scratch
+ * buffer for these parameters.  Pure host function.  EINVAL on bad params. */
+mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes);
+
+/* Row pitch (elements) used for the population planes. */
+mlf_status mlf_query_pitch(const mlf_params* p, int32_t* pitch);
+
+/* Bind parameters, caller-owned device buffers (pop_a, pop_b of pop_bytes,
+ * scratch of scratch_bytes, all 256-byte aligned) and a stream.  Validates
+ * the parameters (EINVAL / EUNSUPPORTED) and uploads nothing yet. */
+mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scratch,
+                      void* stream, mlf_handle** out);
+
+/* Initial state f = f^eq(h, U) (populations at equilibrium; U = 0 when ux/uy
+ * are NULL).  h, ux, uy: host FP64 [N][ny][nx].  The per-layer reference
+ * heights h_ref_i become the means of h_i.  Checks h > 0 and finite
+ * (ENONPOSITIVE / ENONFINITE) and, unless allow_unstable, that the explicit
+ * friction is stable: every eigenvalue of -K (friction = K q) with each layer
+ * at h* or at h_ref must stay below 2 (else EUNSTABLE).  Resets the step
+ * counter.  Synchronises. */
+mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const double* uy);
+
+/* As mlf_init with device FP64 arrays (ux/uy may be NULL). */
+mlf_status mlf_init_device(mlf_handle* h, const double* hgt, const double* ux, const double* uy);
+
+/* Advance nsteps >= 0 steps.  Asynchronous, except that every check_every
+ * steps (and at the end) the device guard flag is read back: a height that
+ * became non-positive or non-finite returns ENONPOSITIVE / ENONFINITE (the
+ * state is then undefined; reload a checkpoint). */
+mlf_status mlf_step(mlf_handle* h, int64_t nsteps);
+
+/* Heights h_i and velocities U_i = q_i / h_i (moment definition, no
+ * half-force shift) in FP64, host arrays [N][ny][nx]; any may be NULL. */
+mlf_status mlf_read(mlf_handle* h, double* hgt, double* ux, double* uy);
+
+/* As mlf_read into device FP64 arrays; asynchronous on the stream. */
+mlf_status mlf_read_device(mlf_handle* h, double* hgt, double* ux, double* uy);
+
+/* Per-layer mass sum_x h_i in FP64 (device reduction in a fixed order),
+ * host array [N].  Synchronises. */
+mlf_status mlf_layer_mass(mlf_handle* h, double* mass);
+
+/* Absolute populations f_ki in FP64, host [N][9][ny][nx] (read) or set
+ * from such an array (write; keeps h_ref).  Synchronise. */
+mlf_status mlf_read_populations(mlf_handle* h, double* f);
+mlf_status mlf_write_populations(mlf_handle* h, const double* f);
+
+/* Checkpoint.  mlf_save with blob == NULL stores the needed size in *bytes;
+ * otherwise writes the state (parameters digest, step counter, h_ref and
+ * the raw population buffer) into blob of *bytes.  mlf_load restores it on a
+ * handle with identical parameters (else EINVAL).  Synchronise. */
+mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes);
+mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
+
+/* Launch shape of the step kernel: block_w threads (64, 128, 256 or 512)
+ * each owning one column of a strip of block_w columns, and seg_h rows per
+ * workgroup (>= 1).  Results do not depend on the shape.  0 = default. */
+mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h);
+mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h);
+
+int64_t mlf_steps_done(const mlf_handle* h);
+const char* mlf_last_error(const mlf_handle* h);
+mlf_status mlf_destroy(mlf_handle* h);
+
+/* ---- host helpers (no device work) ---------------------------------- */
+
+/* Spreading coefficients from a full symmetric tension table
+ * g[(N+2)*(N+2)] (index 0 = substrate, N+1 = gas), Eq. (spreading_parameters):
+ * S_l1 = g_{l,l+2} - g_{l,l+1} - g_{l+1,l+2},
+ * S_lk = g_{l,l+k+1} + g_{l+1,l+k} - g_{l,l+k} - g_{l+1,l+k+1} (k >= 2);
+ * written packed as in mlf_params.spread. */
+mlf_status mlf_spreading_from_tensions(int32_t n_layers, const double* g, double* spread);
+
+/* Friction matrix K (row-major N x N, friction = K q) of one node with
+ * thicknesses h[N] and viscosities mu[N], from the boundary conditions of
+ * Sec. II.A.2 (no slip), and the largest eigenvalue of -K. */
+mlf_status mlf_friction_matrix(int32_t n_layers, const double* h, const double* mu,
+                               double* K, double* max_rate);
+
+/* Library version string. */
+const char* mlf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,49 @@
+"""Build ``libmlfilm.so`` (HIP, gfx950) in-tree with hipcc.
+
+Usage: ``python -m paper_2409_16659_amd.build [-v]``.  The library is always
+rebuilt; callers that only need it loaded use :func:`lib_path`.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libmlfilm.so")
+SOURCES = [os.path.join(CSRC, "mlfilm.hip")]
+HEADERS = [os.path.join(CSRC, "step_kernel.hpp"), os.path.join(ROOT, "include", "mlfilm.h")]
+ARCH = os.environ.get("MLF_OFFLOAD_ARCH", "gfx950")
+
+# Packed FP32 instructions are disabled for all device code; -O3 would
+# otherwise form them from scalar float code.
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if cand and (os.path.isabs(cand) and os.path.exists(cand) or not os.path.isabs(cand)):
+            return cand
+    return "hipcc"
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-o", LIB + ".tmp", *SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def lib_path() -> str:
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,857 @@
+// mlfilm.hip -- C ABI of libmlfilm (declared in include/mlfilm.h): parameter
+// handling, the fused step launch, initialisation, read-back, FP64 per-layer
+// mass reduction and checkpoints.  All device memory is caller-owned.
+#include "../../include/mlfilm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "step_kernel.hpp"
+
+using mlf::kMaxLayers;
+using mlf::kQ;
+
+namespace {
+
+constexpr size_t kFlagOff = 0;          // int guard flag
+constexpr size_t kRedOutOff = 256;      // double[64] reduction results
+constexpr size_t kPartOff = 1024;       // double partials[kRedBlocks][kMaxLayers]
+constexpr int kRedBlocks = 512;
+constexpr size_t kStageOff = 64 * 1024; // staging for host <-> device fields
+constexpr size_t kStageBytes = 16u << 20;
+constexpr size_t kScratchBytes = kStageOff + kStageBytes;
+constexpr int kPitchAlign = 64;  // elements
+// x-components of the D2Q9 velocities; plane k stores the population of
+// node x at column x - kCx[k] (see step_kernel.hpp)
+constexpr int kCx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+
+size_t elem_size(int precision) {
+  switch (precision) {
+    case MLF_F64: return 8;
+    case MLF_F32: return 4;
+    default: return 2;
+  }
+}
+
+int pitch_of(const mlf_params* p) { return (p->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
+
+int pair_index(int n, int l, int k) {  // packed S_lk, l-major, k = 1..n-l
+  int idx = 0;
+  for (int j = 0; j < l; ++j) idx += n - j;
+  return idx + (k - 1);
+}
+
+mlf_status validate(const mlf_params* p, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return MLF_EINVAL;
+  };
+  if (!p) return bad("null parameters");
+  if (p->n_layers < 1 || p->n_layers > MLF_MAX_LAYERS) return bad("n_layers must be 1..4");
+  if (p->nx < 1 || p->ny < 1) return bad("nx, ny must be >= 1");
+  if (p->precision < MLF_F64 || p->precision > MLF_BF16) return bad("unknown precision");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return bad("tau must be > 0.5");
+  if (!(p->hstar > 0.0) || !std::isfinite(p->hstar)) return bad("hstar must be > 0");
+  if (!(p->exp_a > p->exp_b && p->exp_b >= 1) || p->exp_a > 64) return bad("need 64 >= exp_a > exp_b >= 1");
+  for (int i = 0; i < p->n_layers; ++i) {
+    if (!(p->mu[i] > 0.0) || !std::isfinite(p->mu[i])) return bad("mu must be > 0");
+    if (!std::isfinite(p->gamma[i])) return bad("gamma must be finite");
+  }
+  int np = p->n_layers * (p->n_layers + 1) / 2;
+  for (int j = 0; j < np; ++j)
+    if (!std::isfinite(p->spread[j])) return bad("spread must be finite");
+  size_t plane = (size_t)pitch_of(p) * (size_t)p->ny;
+  if (plane * kQ * (size_t)p->n_layers > (size_t)1 << 40) return bad("grid too large");
+  // the step kernel addresses one layer (nine planes) through a buffer
+  // descriptor with 32-bit offsets and masks lanes with offset 2^31
+  if (plane * kQ * elem_size(p->precision) > (size_t)0x80000000u) {
+    if (why) *why = "one layer of populations exceeds 2 GiB";
+    return MLF_EUNSUPPORTED;
+  }
+  for (int i = 0; i < p->n_layers; ++i)
+    if (p->slip[i] != 0.0) {
+      if (why) *why = "slip lengths other than 0 are not supported";
+      return MLF_EUNSUPPORTED;
+    }
+  if (p->precision == MLF_F16 || p->precision == MLF_BF16) {
+    if (why) *why = "16-bit storage is not available in this build";
+    return MLF_EUNSUPPORTED;
+  }
+  return MLF_OK;
+}
+
+// Friction matrix K (friction = K q) of one node from the interface-velocity
+// form of the boundary conditions (no slip): column j is the response to a
+// unit flux in layer j.
+void friction_matrix(int n, const double* h, const double* mu, double* K) {
+  double g[kMaxLayers + 1];
+  for (int i = 0; i < n; ++i) g[i] = mu[i] / h[i];
+  g[n] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double U[kMaxLayers] = {0, 0, 0, 0}, v[kMaxLayers], c[kMaxLayers];
+    U[j] = 1.0 / h[j];
+    for (int i = 0; i < n; ++i) {
+      double diag = 2.0 * (g[i] + g[i + 1]);
+      double rhs = 3.0 * (g[i] * U[i] + (i + 1 < n ? g[i + 1] * U[i + 1] : 0.0));
+      double m = (i == 0) ? diag : diag - g[i] * c[i - 1];
+      c[i] = g[i + 1] / m;
+      v[i] = (i == 0 ? rhs : rhs - g[i] * v[i - 1]) / m;
+    }
+    for (int i = n - 2; i >= 0; --i) v[i] -= c[i] * v[i + 1];
+    for (int i = 0; i < n; ++i) K[i * n + j] = 6.0 * g[i] * ((i > 0 ? v[i - 1] : 0.0) + v[i] - 2.0 * U[i]);
+  }
+}
+
+// Largest eigenvalue of -K.  The eigenvalues are real and positive (P K^-1 T
+// is symmetric), so power iteration converges to it.
+double max_rate(int n, const double* K) {
+  double v[kMaxLayers] = {1, 1, 1, 1}, lam = 0.0;
+  for (int it = 0; it < 2000; ++it) {
+    double w[kMaxLayers] = {0, 0, 0, 0}, nrm = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) w[i] -= K[i * n + j] * v[j];
+    for (int i = 0; i < n; ++i) nrm = std::max(nrm, std::fabs(w[i]));
+    if (nrm == 0.0) return 0.0;
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < n; ++i) {
+      num += w[i] * v[i];
+      den += v[i] * v[i];
+    }
+    lam = num / den;
+    for (int i = 0; i < n; ++i) v[i] = w[i] / nrm;
+  }
+  return lam;
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t hsh = 1469598103934665603ull) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    hsh ^= p[i];
+    hsh *= 1099511628211ull;
+  }
+  return hsh;
+}
+
+uint64_t params_digest(const mlf_params* p) {
+  mlf_params q = *p;
+  q.check_every = 0;
+  q.allow_unstable = 0;
+  return fnv1a(&q, sizeof(q));
+}
+
+struct BlobHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t precision;
+  int32_t n_layers, nx, ny, pitch;
+  int64_t steps;
+  double hbar[kMaxLayers];
+  uint64_t digest;
+  uint64_t payload;
+};
+
+// ---------------------------------------------------------------- kernels --
+// Populations at equilibrium f^eq(h, U) (Eq. equilibrium_distribution), rest
+// population stored as deviation from hbar, for rows [ya, yb).
+template <typename S>
+__global__ void init_kernel(S* __restrict__ f, const double* __restrict__ hs, const double* __restrict__ uxs,
+                            const double* __restrict__ uys, long long lstride, int yoff, int ya, int yb, int nx,
+                            int pitch, long long plane, int nl, double h0, double h1, double h2, double h3) {
+  const double hb[4] = {h0, h1, h2, h3};
+  long long n = (long long)(yb - ya) * nx;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n * nl;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / n);
+    const long long rem = t % n;
+    const int y = ya + (int)(rem / nx), x = (int)(rem % nx);
+    const long long si = i * lstride + (long long)(y - yoff) * nx + x;
+    const double h = hs[si], ux = uxs ? uxs[si] : 0.0, uy = uys ? uys[si] : 0.0;
+    const double uu = ux * ux + uy * uy;
+    const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+    const int cy[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
+    // plane k keeps at column x - c_kx the population of node x
+    S* o = f + (long long)(i * 9) * plane + (long long)y * pitch;
+    o[x] = S((h - hb[i]) - h * (2.0 / 3.0) * uu);
+    for (int k = 1; k < 9; ++k) {
+      const double cu = cx[k] * ux + cy[k] * uy;
+      o[(long long)k * plane + mlf::wrap(x - cx[k], nx)] = S(w[k] * h * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+  }
+}
+
+// h = hbar + sum_k f_k, U = q / h in FP64 for rows [ya, yb).
+template <typename S>
+__global__ void read_kernel(const S* __restrict__ f, double* __restrict__ ho, double* __restrict__ uxo,
+                            double* __restrict__ uyo, long long lstride, int yoff, int ya, int yb, int nx,
+                            int pitch, long long plane, int nl, double h0, double h1, double h2, double h3) {
+  const double hb[4] = {h0, h1, h2, h3};
+  long long n = (long long)(yb - ya) * nx;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n * nl;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / n);
+    const long long rem = t % n;
+    const int y = ya + (int)(rem / nx), x = (int)(rem % nx);
+    const S* b = f + (long long)(i * 9) * plane + (long long)y * pitch;
+    const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+    double v[9];
+    for (int k = 0; k < 9; ++k) v[k] = double(b[(long long)k * plane + mlf::wrap(x - cx[k], nx)]);
+    const double dh = v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7] + v[8];
+    const double qx = (v[1] + v[2] + v[8]) - (v[4] + v[5] + v[6]);
+    const double qy = (v[2] + v[3] + v[4]) - (v[6] + v[7] + v[8]);
+    const double h = hb[i] + dh;
+    const long long di = i * lstride + (long long)(y - yoff) * nx + x;
+    if (ho) ho[di] = h;
+    if (uxo) uxo[di] = qx / h;
+    if (uyo) uyo[di] = qy / h;
+  }
+}
+
+// Block sums of sum_k f_ki (FP64) per layer: partials[blockIdx.x][i].
+template <typename S>
+__global__ void __launch_bounds__(256) mass_partials(const S* __restrict__ f, double* __restrict__ part, int nx,
+                                                     int ny, int pitch, long long plane, int nl) {
+  __shared__ double red[256 / 64][kMaxLayers];
+  double acc[kMaxLayers] = {0, 0, 0, 0};
+  const long long n = (long long)nx * ny;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const int y = (int)(t / nx), x = (int)(t % nx);
+    for (int i = 0; i < nl; ++i) {
+      const S* b = f + (long long)(i * 9) * plane + (long long)y * pitch + x;
+      double s = 0.0;
+      for (int k = 0; k < 9; ++k) s += double(b[(long long)k * plane]);
+      acc[i] += s;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = 0; i < nl; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nl) {
+    double s = 0.0;
+    for (int j = 0; j < (int)(blockDim.x >> 6); ++j) s += red[j][threadIdx.x];
+    part[blockIdx.x * kMaxLayers + threadIdx.x] = s;
+  }
+}
+
+// Sum of a FP64 field per layer (used for the reference heights of device
+// inputs): partials[blockIdx.x][i].
+__global__ void __launch_bounds__(256) field_partials(const double* __restrict__ a, double* __restrict__ part,
+                                                      long long n, int nl) {
+  __shared__ double red[256 / 64][kMaxLayers];
+  double acc[kMaxLayers] = {0, 0, 0, 0};
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    for (int i = 0; i < nl; ++i) acc[i] += a[i * n + t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = 0; i < nl; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nl) {
+    double s = 0.0;
+    for (int j = 0; j < (int)(blockDim.x >> 6); ++j) s += red[j][threadIdx.x];
+    part[blockIdx.x * kMaxLayers + threadIdx.x] = s;
+  }
+}
+
+// Final fixed-order sum of the partials; one thread per layer.
+__global__ void finish_partials(const double* __restrict__ part, double* __restrict__ out, int nblocks, int nl) {
+  const int i = threadIdx.x;
+  if (i < nl) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[b * kMaxLayers + i];
+    out[i] = s;
+  }
+}
+
+}  // namespace
+
+struct mlf_handle {
+  mlf_params p;
+  void* pop[2];
+  int cur;
+  unsigned char* scratch;
+  hipStream_t stream;
+  int pitch;
+  size_t plane;
+  size_t pop_bytes;
+  double hbar[kMaxLayers];
+  int64_t steps;
+  int block_w, seg_h;
+  bool initialised;
+  std::string err;
+};
+
+namespace {
+
+mlf_status fail(mlf_handle* h, mlf_status st, const std::string& m) {
+  if (h) h->err = m;
+  return st;
+}
+
+mlf_status hip_check(mlf_handle* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MLF_OK;
+  return fail(h, MLF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                              \
+  do {                                                            \
+    mlf_status _s = hip_check(h, (call), #call);                  \
+    if (_s != MLF_OK) return _s;                                  \
+  } while (0)
+
+int* flag_ptr(mlf_handle* h) { return reinterpret_cast<int*>(h->scratch + kFlagOff); }
+double* redout_ptr(mlf_handle* h) { return reinterpret_cast<double*>(h->scratch + kRedOutOff); }
+double* part_ptr(mlf_handle* h) { return reinterpret_cast<double*>(h->scratch + kPartOff); }
+unsigned char* stage_ptr(mlf_handle* h) { return h->scratch + kStageOff; }
+
+void default_launch(const mlf_params* p, int* bw, int* sh) {
+  int w = p->nx + 4;
+  *bw = w <= 64 ? 64 : (w <= 128 ? 128 : 256);
+  *sh = std::max(1, std::min(p->ny, 12));
+}
+
+template <typename C>
+mlf::StepConsts<C> make_consts(const mlf_handle* h) {
+  const mlf_params& p = h->p;
+  mlf::StepConsts<C> k;
+  std::memset(&k, 0, sizeof(k));
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.pitch = h->pitch;
+  k.plane = (long long)h->plane;
+  const int W = h->block_w;
+  // strips of equal width wout <= W - 4 (lanes cover two halo columns on each
+  // side); recomputing nstrip from wout guarantees no empty strip
+  k.nstrip = (p.nx + (W - 4) - 1) / (W - 4);
+  k.wout = (p.nx + k.nstrip - 1) / k.nstrip;
+  k.nstrip = (p.nx + k.wout - 1) / k.wout;
+  k.seg_h = h->seg_h;
+  k.nseg = (p.ny + k.seg_h - 1) / k.seg_h;
+  const int n = p.n_layers;
+  double z[kMaxLayers + 1];
+  z[0] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    k.hbar[i] = C(h->hbar[i]);
+    z[i + 1] = z[i] + h->hbar[i];
+    k.gamma[i] = C(p.gamma[i]);
+    k.mu[i] = C(p.mu[i]);
+  }
+  for (int l = 0; l < n; ++l)
+    for (int kk = 1; kk <= n - l; ++kk) {
+      k.dbar[l][kk - 1] = C(z[l + kk] - z[l]);
+      k.spread[l][kk - 1] = C(p.spread[pair_index(n, l, kk)]);
+    }
+  for (int kk = 1; kk <= kMaxLayers; ++kk) k.khs[kk - 1] = C(kk * p.hstar);
+  const double a = p.exp_a, b = p.exp_b;
+  k.ca = C(a / (a - b));
+  k.cb = C(b / (a - b));
+  k.cab = C(a * b / (a - b));
+  k.omega = C(1.0 / p.tau);
+  k.ea = p.exp_a;
+  k.eb = p.exp_b;
+  k.flag = flag_ptr(const_cast<mlf_handle*>(h));
+  return k;
+}
+
+template <typename S, typename C, int NL, bool T1, int EA, int EB>
+hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
+  mlf::StepConsts<C> kc = make_consts<C>(h);
+  // grid padded to a multiple of the XCD count (tile_of_block)
+  const int ntiles = kc.nstrip * kc.nseg;
+  const int nblocks = (ntiles + mlf::kXcds - 1) / mlf::kXcds * mlf::kXcds;
+  dim3 grid((unsigned)nblocks), block((unsigned)h->block_w);
+  size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
+  hipLaunchKernelGGL((mlf::step_kernel<S, C, NL, T1, EA, EB>), grid, block, lds, h->stream,
+                     static_cast<const S*>(src), static_cast<S*>(dst), kc);
+  return hipGetLastError();
+}
+
+template <typename S, typename C, bool T1, int EA, int EB>
+hipError_t launch_t(const mlf_handle* h, const void* src, void* dst) {
+  switch (h->p.n_layers) {
+    case 1: return launch_nl<S, C, 1, T1, EA, EB>(h, src, dst);
+    case 2: return launch_nl<S, C, 2, T1, EA, EB>(h, src, dst);
+    case 3: return launch_nl<S, C, 3, T1, EA, EB>(h, src, dst);
+    default: return launch_nl<S, C, 4, T1, EA, EB>(h, src, dst);
+  }
+}
+
+template <typename S, typename C>
+hipError_t launch_sc(const mlf_handle* h, const void* src, void* dst) {
+  const bool t1 = h->p.tau == 1.0;
+  const bool e93 = h->p.exp_a == 9 && h->p.exp_b == 3;
+  if (t1 && e93) return launch_t<S, C, true, 9, 3>(h, src, dst);
+  if (t1) return launch_t<S, C, true, 0, 0>(h, src, dst);
+  if (e93) return launch_t<S, C, false, 9, 3>(h, src, dst);
+  return launch_t<S, C, false, 0, 0>(h, src, dst);
+}
+
+hipError_t launch_step(const mlf_handle* h, const void* src, void* dst) {
+  if (h->p.precision == MLF_F64) return launch_sc<double, double>(h, src, dst);
+  return launch_sc<float, float>(h, src, dst);
+}
+
+unsigned grid_for(long long n) {
+  long long g = (n + 255) / 256;
+  return (unsigned)std::max(1LL, std::min(g, 8192LL));
+}
+
+mlf_status launch_init(mlf_handle* h, const double* hs, const double* uxs, const double* uys, long long lstride,
+                       int yoff, int ya, int yb) {
+  const mlf_params& p = h->p;
+  const long long n = (long long)(yb - ya) * p.nx * p.n_layers;
+  if (p.precision == MLF_F64)
+    hipLaunchKernelGGL(init_kernel<double>, dim3(grid_for(n)), dim3(256), 0, h->stream,
+                       static_cast<double*>(h->pop[h->cur]), hs, uxs, uys, lstride, yoff, ya, yb, p.nx, h->pitch,
+                       (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  else
+    hipLaunchKernelGGL(init_kernel<float>, dim3(grid_for(n)), dim3(256), 0, h->stream,
+                       static_cast<float*>(h->pop[h->cur]), hs, uxs, uys, lstride, yoff, ya, yb, p.nx, h->pitch,
+                       (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  HIPCHK(hipGetLastError());
+  return MLF_OK;
+}
+
+mlf_status launch_read(mlf_handle* h, double* ho, double* uxo, double* uyo, long long lstride, int yoff, int ya,
+                       int yb) {
+  const mlf_params& p = h->p;
+  const long long n = (long long)(yb - ya) * p.nx * p.n_layers;
+  if (p.precision == MLF_F64)
+    hipLaunchKernelGGL(read_kernel<double>, dim3(grid_for(n)), dim3(256), 0, h->stream,
+                       static_cast<const double*>(h->pop[h->cur]), ho, uxo, uyo, lstride, yoff, ya, yb, p.nx,
+                       h->pitch, (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  else
+    hipLaunchKernelGGL(read_kernel<float>, dim3(grid_for(n)), dim3(256), 0, h->stream,
+                       static_cast<const float*>(h->pop[h->cur]), ho, uxo, uyo, lstride, yoff, ya, yb, p.nx,
+                       h->pitch, (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  HIPCHK(hipGetLastError());
+  return MLF_OK;
+}
+
+int rows_per_chunk(const mlf_handle* h, int fields) {
+  size_t row = (size_t)fields * h->p.n_layers * h->p.nx * sizeof(double);
+  return (int)std::max<size_t>(0, kStageBytes / row);
+}
+
+mlf_status check_guard(mlf_handle* h) {
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, flag_ptr(h), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (flag == 1)
+    return fail(h, MLF_ENONPOSITIVE,
+                "a layer height became <= 0 at or before step " + std::to_string(h->steps));
+  if (flag != 0)
+    return fail(h, MLF_ENONFINITE,
+                "a layer height or flux became non-finite at or before step " + std::to_string(h->steps));
+  return MLF_OK;
+}
+
+mlf_status check_stability(mlf_handle* h) {
+  const mlf_params& p = h->p;
+  if (p.allow_unstable) return MLF_OK;
+  // explicit friction: every eigenvalue of -K must stay below 2 with each
+  // layer at h* or at its reference thickness
+  double worst = 0.0;
+  for (int mask = 0; mask < (1 << p.n_layers); ++mask) {
+    double hh[kMaxLayers], K[kMaxLayers * kMaxLayers];
+    for (int i = 0; i < p.n_layers; ++i) hh[i] = (mask >> i & 1) ? p.hstar : h->hbar[i];
+    friction_matrix(p.n_layers, hh, p.mu, K);
+    worst = std::max(worst, max_rate(p.n_layers, K));
+  }
+  if (!(worst < 2.0)) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "explicit friction unstable: largest friction rate %.4g >= 2", worst);
+    return fail(h, MLF_EUNSTABLE, buf);
+  }
+  return MLF_OK;
+}
+
+// Both population buffers start zeroed so that the row padding (never
+// written by the kernels) is deterministic in checkpoints.
+mlf_status zero_buffers(mlf_handle* h) {
+  HIPCHK(hipMemsetAsync(h->pop[0], 0, h->pop_bytes, h->stream));
+  HIPCHK(hipMemsetAsync(h->pop[1], 0, h->pop_bytes, h->stream));
+  return MLF_OK;
+}
+
+mlf_status finish_init(mlf_handle* h) {
+  HIPCHK(hipMemsetAsync(flag_ptr(h), 0, sizeof(int), h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->steps = 0;
+  h->initialised = true;
+  return MLF_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ====
+extern "C" {
+
+const char* mlf_version(void) { return "mlfilm 0.1 gfx950"; }
+
+mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes) {
+  mlf_status st = validate(p, nullptr);
+  if (st != MLF_OK) return st;
+  if (pop_bytes) *pop_bytes = (size_t)pitch_of(p) * p->ny * kQ * p->n_layers * elem_size(p->precision);
+  if (scratch_bytes) *scratch_bytes = kScratchBytes;
+  return MLF_OK;
+}
+
+mlf_status mlf_query_pitch(const mlf_params* p, int32_t* pitch) {
+  mlf_status st = validate(p, nullptr);
+  if (st != MLF_OK) return st;
+  if (pitch) *pitch = pitch_of(p);
+  return MLF_OK;
+}
+
+mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scratch, void* stream,
+                      mlf_handle** out) {
+  if (!out) return MLF_EINVAL;
+  *out = nullptr;
+  std::string why;
+  mlf_status st = validate(p, &why);
+  if (st != MLF_OK) return st;
+  if (!pop_a || !pop_b || !scratch || pop_a == pop_b) return MLF_EINVAL;
+  auto aligned = [](void* v) { return (reinterpret_cast<uintptr_t>(v) & 255) == 0; };
+  if (!aligned(pop_a) || !aligned(pop_b) || !aligned(scratch)) return MLF_EINVAL;
+  mlf_handle* h = new (std::nothrow) mlf_handle();
+  if (!h) return MLF_EINVAL;
+  h->p = *p;
+  h->pop[0] = pop_a;
+  h->pop[1] = pop_b;
+  h->cur = 0;
+  h->scratch = static_cast<unsigned char*>(scratch);
+  h->stream = static_cast<hipStream_t>(stream);
+  h->pitch = pitch_of(p);
+  h->plane = (size_t)h->pitch * p->ny;
+  h->pop_bytes = h->plane * kQ * p->n_layers * elem_size(p->precision);
+  for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0;
+  h->steps = 0;
+  h->initialised = false;
+  default_launch(p, &h->block_w, &h->seg_h);
+  *out = h;
+  return MLF_OK;
+}
+
+mlf_status mlf_destroy(mlf_handle* h) {
+  delete h;
+  return MLF_OK;
+}
+
+int64_t mlf_steps_done(const mlf_handle* h) { return h ? h->steps : -1; }
+
+const char* mlf_last_error(const mlf_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h) {
+  if (!h) return MLF_EINVAL;
+  int bw, sh;
+  default_launch(&h->p, &bw, &sh);
+  if (block_w != 0) {
+    if (block_w != 64 && block_w != 128 && block_w != 256)
+      return fail(h, MLF_EINVAL, "block_w must be 64, 128 or 256");
+    bw = block_w;
+  }
+  if (seg_h != 0) {
+    if (seg_h < 1) return fail(h, MLF_EINVAL, "seg_h must be >= 1");
+    sh = std::min(seg_h, h->p.ny);
+  }
+  h->block_w = bw;
+  h->seg_h = sh;
+  return MLF_OK;
+}
+
+mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h) {
+  if (!h) return MLF_EINVAL;
+  if (block_w) *block_w = h->block_w;
+  if (seg_h) *seg_h = h->seg_h;
+  return MLF_OK;
+}
+
+mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const double* uy) {
+  if (!h || !hgt) return MLF_EINVAL;
+  const mlf_params& p = h->p;
+  const long long nn = (long long)p.nx * p.ny;
+  h->initialised = false;
+  for (int i = 0; i < p.n_layers; ++i) {
+    double s = 0.0;
+    for (long long j = 0; j < nn; ++j) {
+      const double v = hgt[i * nn + j];
+      if (!std::isfinite(v) || (ux && !std::isfinite(ux[i * nn + j])) || (uy && !std::isfinite(uy[i * nn + j])))
+        return fail(h, MLF_ENONFINITE, "initial field is not finite");
+      if (!(v > 0.0)) return fail(h, MLF_ENONPOSITIVE, "initial height <= 0");
+      s += v;
+    }
+    h->hbar[i] = s / (double)nn;
+  }
+  mlf_status chk = check_stability(h);
+  if (chk != MLF_OK) return chk;
+  const int rows = rows_per_chunk(h, 3);
+  if (rows < 1) return fail(h, MLF_EUNSUPPORTED, "grid rows too wide for the staging area");
+  chk = zero_buffers(h);
+  if (chk != MLF_OK) return chk;
+  double* st = reinterpret_cast<double*>(stage_ptr(h));
+  for (int ya = 0; ya < p.ny; ya += rows) {
+    const int yb = std::min(p.ny, ya + rows);
+    const long long cnt = (long long)(yb - ya) * p.nx, lstride = cnt;
+    double* sh = st;
+    double* sx = ux ? st + cnt * p.n_layers : nullptr;
+    double* sy = uy ? st + 2 * cnt * p.n_layers : nullptr;
+    for (int i = 0; i < p.n_layers; ++i) {
+      HIPCHK(hipMemcpyAsync(sh + i * cnt, hgt + i * nn + (long long)ya * p.nx, cnt * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+      if (sx)
+        HIPCHK(hipMemcpyAsync(sx + i * cnt, ux + i * nn + (long long)ya * p.nx, cnt * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+      if (sy)
+        HIPCHK(hipMemcpyAsync(sy + i * cnt, uy + i * nn + (long long)ya * p.nx, cnt * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+    }
+    mlf_status s = launch_init(h, sh, sx, sy, lstride, ya, ya, yb);
+    if (s != MLF_OK) return s;
+    HIPCHK(hipStreamSynchronize(h->stream));  // staging is reused
+  }
+  return finish_init(h);
+}
+
+mlf_status mlf_init_device(mlf_handle* h, const double* hgt, const double* ux, const double* uy) {
+  if (!h || !hgt) return MLF_EINVAL;
+  const mlf_params& p = h->p;
+  const long long nn = (long long)p.nx * p.ny;
+  h->initialised = false;
+  hipLaunchKernelGGL(field_partials, dim3(kRedBlocks), dim3(256), 0, h->stream, hgt, part_ptr(h), nn, p.n_layers);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
+                     p.n_layers);
+  HIPCHK(hipGetLastError());
+  double sums[kMaxLayers];
+  HIPCHK(hipMemcpyAsync(sums, redout_ptr(h), p.n_layers * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < p.n_layers; ++i) {
+    h->hbar[i] = sums[i] / (double)nn;
+    if (!std::isfinite(h->hbar[i])) return fail(h, MLF_ENONFINITE, "initial field is not finite");
+    if (!(h->hbar[i] > 0.0)) return fail(h, MLF_ENONPOSITIVE, "initial height <= 0");
+  }
+  mlf_status s = check_stability(h);
+  if (s != MLF_OK) return s;
+  s = zero_buffers(h);
+  if (s != MLF_OK) return s;
+  s = launch_init(h, hgt, ux, uy, nn, 0, 0, p.ny);
+  if (s != MLF_OK) return s;
+  s = finish_init(h);
+  if (s != MLF_OK) return s;
+  // per-node validity of device inputs is checked by the first step's guard
+  return MLF_OK;
+}
+
+mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
+  if (!h || nsteps < 0) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_step before mlf_init");
+  const int every = h->p.check_every;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    HIPCHK(launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]));
+    h->cur ^= 1;
+    h->steps += 1;
+    if (every > 0 && (t + 1) % every == 0 && t + 1 < nsteps) {
+      mlf_status s = check_guard(h);
+      if (s != MLF_OK) return s;
+    }
+  }
+  if (every >= 0) return check_guard(h);
+  return MLF_OK;
+}
+
+mlf_status mlf_read_device(mlf_handle* h, double* hgt, double* ux, double* uy) {
+  if (!h) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "read before init");
+  if (!hgt && !ux && !uy) return MLF_OK;
+  const long long nn = (long long)h->p.nx * h->p.ny;
+  return launch_read(h, hgt, ux, uy, nn, 0, 0, h->p.ny);
+}
+
+mlf_status mlf_read(mlf_handle* h, double* hgt, double* ux, double* uy) {
+  if (!h) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "read before init");
+  const mlf_params& p = h->p;
+  const long long nn = (long long)p.nx * p.ny;
+  const int rows = rows_per_chunk(h, 3);
+  if (rows < 1) return fail(h, MLF_EUNSUPPORTED, "grid rows too wide for the staging area");
+  double* st = reinterpret_cast<double*>(stage_ptr(h));
+  for (int ya = 0; ya < p.ny; ya += rows) {
+    const int yb = std::min(p.ny, ya + rows);
+    const long long cnt = (long long)(yb - ya) * p.nx;
+    double* sh = hgt ? st : nullptr;
+    double* sx = ux ? st + cnt * p.n_layers : nullptr;
+    double* sy = uy ? st + 2 * cnt * p.n_layers : nullptr;
+    mlf_status s = launch_read(h, sh, sx, sy, cnt, ya, ya, yb);
+    if (s != MLF_OK) return s;
+    for (int i = 0; i < p.n_layers; ++i) {
+      if (hgt)
+        HIPCHK(hipMemcpyAsync(hgt + i * nn + (long long)ya * p.nx, sh + i * cnt, cnt * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+      if (ux)
+        HIPCHK(hipMemcpyAsync(ux + i * nn + (long long)ya * p.nx, sx + i * cnt, cnt * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+      if (uy)
+        HIPCHK(hipMemcpyAsync(uy + i * nn + (long long)ya * p.nx, sy + i * cnt, cnt * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return MLF_OK;
+}
+
+mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
+  if (!h || !mass) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "mass before init");
+  const mlf_params& p = h->p;
+  if (p.precision == MLF_F64)
+    hipLaunchKernelGGL(mass_partials<double>, dim3(kRedBlocks), dim3(256), 0, h->stream,
+                       static_cast<const double*>(h->pop[h->cur]), part_ptr(h), p.nx, p.ny, h->pitch,
+                       (long long)h->plane, p.n_layers);
+  else
+    hipLaunchKernelGGL(mass_partials<float>, dim3(kRedBlocks), dim3(256), 0, h->stream,
+                       static_cast<const float*>(h->pop[h->cur]), part_ptr(h), p.nx, p.ny, h->pitch,
+                       (long long)h->plane, p.n_layers);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
+                     p.n_layers);
+  HIPCHK(hipGetLastError());
+  double dev[kMaxLayers];
+  HIPCHK(hipMemcpyAsync(dev, redout_ptr(h), p.n_layers * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double nn = (double)p.nx * (double)p.ny;
+  for (int i = 0; i < p.n_layers; ++i) mass[i] = nn * h->hbar[i] + dev[i];
+  return MLF_OK;
+}
+
+mlf_status mlf_read_populations(mlf_handle* h, double* f) {
+  if (!h || !f) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "read before init");
+  const mlf_params& p = h->p;
+  std::vector<unsigned char> raw(h->pop_bytes);
+  HIPCHK(hipMemcpyAsync(raw.data(), h->pop[h->cur], h->pop_bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < p.n_layers; ++i)
+    for (int k = 0; k < kQ; ++k)
+      for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+          const size_t si = ((size_t)(i * kQ + k)) * h->plane + (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          double v = p.precision == MLF_F64 ? reinterpret_cast<const double*>(raw.data())[si]
+                                            : (double)reinterpret_cast<const float*>(raw.data())[si];
+          if (k == 0) v += h->hbar[i];
+          f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x] = v;
+        }
+  return MLF_OK;
+}
+
+mlf_status mlf_write_populations(mlf_handle* h, const double* f) {
+  if (!h || !f) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "write before init");
+  const mlf_params& p = h->p;
+  std::vector<unsigned char> raw(h->pop_bytes, 0);
+  for (int i = 0; i < p.n_layers; ++i)
+    for (int k = 0; k < kQ; ++k)
+      for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+          const size_t si = ((size_t)(i * kQ + k)) * h->plane + (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          double v = f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x];
+          if (k == 0) v -= h->hbar[i];
+          if (p.precision == MLF_F64)
+            reinterpret_cast<double*>(raw.data())[si] = v;
+          else
+            reinterpret_cast<float*>(raw.data())[si] = (float)v;
+        }
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], raw.data(), h->pop_bytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return MLF_OK;
+}
+
+mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes) {
+  if (!h || !bytes) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "save before init");
+  const size_t need = sizeof(BlobHeader) + h->pop_bytes;
+  if (!blob) {
+    *bytes = need;
+    return MLF_OK;
+  }
+  if (*bytes < need) return fail(h, MLF_EINVAL, "checkpoint buffer too small");
+  BlobHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, "MLFILM01", 8);
+  hd.version = 1;
+  hd.precision = h->p.precision;
+  hd.n_layers = h->p.n_layers;
+  hd.nx = h->p.nx;
+  hd.ny = h->p.ny;
+  hd.pitch = h->pitch;
+  hd.steps = h->steps;
+  for (int i = 0; i < kMaxLayers; ++i) hd.hbar[i] = h->hbar[i];
+  hd.digest = params_digest(&h->p);
+  hd.payload = h->pop_bytes;
+  std::memcpy(blob, &hd, sizeof hd);
+  HIPCHK(hipMemcpyAsync(static_cast<unsigned char*>(blob) + sizeof hd, h->pop[h->cur], h->pop_bytes,
+                        hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *bytes = need;
+  return MLF_OK;
+}
+
+mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes) {
+  if (!h || !blob) return MLF_EINVAL;
+  if (bytes < sizeof(BlobHeader)) return fail(h, MLF_EINVAL, "checkpoint too small");
+  BlobHeader hd;
+  std::memcpy(&hd, blob, sizeof hd);
+  if (std::memcmp(hd.magic, "MLFILM01", 8) != 0 || hd.version != 1) return fail(h, MLF_EINVAL, "not a checkpoint");
+  if (hd.digest != params_digest(&h->p) || hd.pitch != h->pitch || hd.payload != h->pop_bytes ||
+      bytes < sizeof hd + hd.payload)
+    return fail(h, MLF_EINVAL, "checkpoint does not match these parameters");
+  for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = hd.hbar[i];
+  mlf_status z = zero_buffers(h);
+  if (z != MLF_OK) return z;
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], static_cast<const unsigned char*>(blob) + sizeof hd, h->pop_bytes,
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemsetAsync(flag_ptr(h), 0, sizeof(int), h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->steps = hd.steps;
+  h->initialised = true;
+  return MLF_OK;
+}
+
+mlf_status mlf_spreading_from_tensions(int32_t n, const double* g, double* spread) {
+  if (n < 1 || n > MLF_MAX_LAYERS || !g || !spread) return MLF_EINVAL;
+  const int m = n + 2;
+  auto G = [&](int a, int b) { return g[a * m + b]; };
+  for (int j = 0; j < MLF_MAX_PAIRS; ++j) spread[j] = 0.0;
+  for (int l = 0; l < n; ++l)
+    for (int k = 1; k <= n - l; ++k) {
+      double s = (k == 1) ? G(l, l + 2) - G(l, l + 1) - G(l + 1, l + 2)
+                          : G(l, l + k + 1) + G(l + 1, l + k) - G(l, l + k) - G(l + 1, l + k + 1);
+      spread[pair_index(n, l, k)] = s;
+    }
+  return MLF_OK;
+}
+
+mlf_status mlf_friction_matrix(int32_t n, const double* hh, const double* mu, double* K, double* rate) {
+  if (n < 1 || n > MLF_MAX_LAYERS || !hh || !mu) return MLF_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(hh[i] > 0.0) || !(mu[i] > 0.0)) return MLF_EINVAL;
+  double k[kMaxLayers * kMaxLayers];
+  friction_matrix(n, hh, mu, k);
+  if (K) std::memcpy(K, k, sizeof(double) * n * n);
+  if (rate) *rate = max_rate(n, k);
+  return MLF_OK;
+}
+
+}  // extern "C"

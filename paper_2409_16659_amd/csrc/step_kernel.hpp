@@ -1,0 +1,497 @@
+// step_kernel.hpp -- fused N-layer thin-film lattice Boltzmann step for
+// gfx950 (one launch per time step).
+//
+// What one step computes (Sec. III with the pressure and friction of Sec. II
+// of Richter, Malgaretti & Harting, arXiv 2409.16659), per node and layer:
+//   moments   h_i = sum_k f_ki, q_i = sum_k c_k f_ki
+//   z_i = z_{i-1} + h_i; grad z_i, lap z_i (isotropic 9-point stencils)
+//   phi_lk = S_lk phi_k(z_{l+k} - z_l), phi'_lk  (Eq. wetting_potential)
+//   Delta_i = -(gamma_i + sum_k phi_ik) lap z_i
+//             - sum_k phi'_ik (1 + |grad z_i|^2/2)
+//             + sum_{l<i} phi'_{l,i-l} (1 + |grad z_l|^2/2)
+//             (Eqs. Laplace_pressure, disjoining_pressure)
+//   p_i = sum_{j>=i} Delta_j; F_i = -h_i grad p_i + friction_i (Eq. force)
+//   f*_ki = f_ki - (f_ki - f^eq_ki)/tau + 3 w_k c_k.F_i   (Eq. BGK)
+//   f_ki(x + c_k, t+1) = f*_ki(x), periodic
+//
+// Layout and schedule (gfx950, wave64):
+//  * Populations are structure-of-arrays, plane (i, k) = ny rows of `pitch`
+//    elements, x fastest.
+//  * Streaming is split by axis: the y-shift is applied when a population is
+//    written (push) and the x-shift when it is read (pull).  Plane k stores
+//    at column x the population that belongs to node x + c_kx:
+//      f_k(x, y) = S_k(x - c_kx, y),   S_k(x, y + c_ky) <- f*_k(x, y).
+//    Every store of a wavefront is thus a column-aligned run (no partial
+//    cache lines written twice); only loads carry the +-1 column offsets,
+//    which the caches absorb.
+//  * The rest population is stored as its deviation from the per-layer
+//    reference height hbar_i (moving populations as they are), so that FP32
+//    (and 16-bit) storage keeps the small height perturbations exact to
+//    storage precision; heights are hbar_i + dh_i and interface heights are
+//    handled as deviations dz_i from the reference stack.
+//  * A workgroup owns a strip of columns and marches along a segment of rows
+//    (a sliding window).  Its lanes cover the strip plus two halo columns on
+//    each side (overlapped tiling): every lane loads and reduces one column,
+//    the inner lanes form pressures and the innermost ones collide and
+//    stream.  Segments alternate their marching direction, so the two
+//    workgroups that share halo rows read them at about the same time, and
+//    tiles are numbered so that neighbours run on the same XCD (shared L2).
+//  * LDS holds a ring of 5 rows of dz (two stencil levels behind a written
+//    row) and a ring of 3 rows of p.  The moments of the last three rows
+//    stay in registers, and the next row's populations are prefetched into
+//    registers while the current row is processed.
+//  * Friction: the Poiseuille profiles of Sec. II.A.2 are fixed by the
+//    interface velocities v_i (v_0 = 0).  Flux, bottom/top velocities and
+//    stress continuity give a symmetric diagonally dominant tridiagonal
+//    system in v, solved by Thomas elimination without pivoting:
+//      g_i v_{i-1} + 2 (g_i + g_{i+1}) v_i + g_{i+1} v_{i+1}
+//          = 3 (g_i U_i + g_{i+1} U_{i+1}),   g_i = mu_i / h_i, g_{N+1} = 0,
+//    and friction_i = 2 mu_i h_i a_i = 6 g_i (v_{i-1} + v_i - 2 U_i).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlf {
+
+constexpr int kMaxLayers = 4;
+constexpr int kQ = 9;
+constexpr int kXcds = 8;  // MI355X: workgroup b runs on XCD b % 8
+
+// D2Q9 ordering: rest, then counter-clockwise from east.
+//   k:  0  1  2  3  4  5  6  7  8
+//  cx:  0  1  1  0 -1 -1 -1  0  1
+//  cy:  0  0  1  1  1  0 -1 -1 -1
+
+template <typename C>
+struct StepConsts {
+  int nx, ny, pitch;
+  int nstrip, wout, seg_h, nseg;
+  long long plane;                 // elements per (layer, direction) plane
+  C hbar[kMaxLayers];              // reference heights
+  C dbar[kMaxLayers][kMaxLayers];  // reference gaps z_{l+k} - z_l, [l][k-1]
+  C gamma[kMaxLayers];             // gamma_{i,i+1}
+  C mu[kMaxLayers];
+  C spread[kMaxLayers][kMaxLayers];  // S_lk, [l][k-1]
+  C khs[kMaxLayers];                 // k h*, [k-1]
+  C ca, cb;                          // a/(a-b), b/(a-b)
+  C cab;                             // a b/(a-b)
+  C omega;                           // 1/tau
+  int ea, eb;                        // runtime exponents (generic path)
+  int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
+};
+
+// Storage access through raw buffer descriptors: one descriptor per layer
+// (base address and byte size in scalar registers), the (layer, direction)
+// plane offset as the scalar offset, and per-lane 32-bit byte offsets shared
+// by all planes.  Accesses beyond the descriptor's size read zero and drop
+// the write instead of faulting.
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit format
+// Per-lane offset of a masked access: at least the descriptor size (one layer
+// is limited to 2 GiB) and, with any plane offset added, still below 2^32, so
+// the access is out of range whether or not the range check includes the
+// scalar offset.
+constexpr uint32_t kMasked = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <typename S>
+__device__ inline S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <>
+__device__ inline double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
+// Reciprocal: the hardware approximation (1 ulp) in FP32, a correctly
+// rounded division in FP64.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
+
+template <int E, typename C>
+__device__ inline C ipow_c(C r) {
+  if constexpr (E == 1) {
+    return r;
+  } else if constexpr (E % 2 == 0) {
+    C h = ipow_c<E / 2>(r);
+    return h * h;
+  } else {
+    return r * ipow_c<E - 1>(r);
+  }
+}
+
+template <typename C>
+__device__ inline C ipow_rt(C r, int e) {
+  C v = C(1), b = r;
+  while (e > 0) {
+    if (e & 1) v *= b;
+    b *= b;
+    e >>= 1;
+  }
+  return v;
+}
+
+// r^a and r^b; EA == 0 selects the runtime exponents.
+template <int EA, int EB, typename C>
+__device__ inline void pow_ab(C r, const StepConsts<C>& k, C& ra, C& rb) {
+  if constexpr (EA == 9 && EB == 3) {
+    C r3 = r * r * r;
+    rb = r3;
+    ra = r3 * r3 * r3;
+  } else if constexpr (EA > 0) {
+    ra = ipow_c<EA>(r);
+    rb = ipow_c<EB>(r);
+  } else {
+    ra = ipow_rt(r, k.ea);
+    rb = ipow_rt(r, k.eb);
+  }
+}
+
+__host__ __device__ inline int wrap(int v, int n) {
+  v = v < 0 ? v + n : v;
+  v = v >= n ? v - n : v;
+  if (v < 0 || v >= n) v = ((v % n) + n) % n;  // only for n < 3
+  return v;
+}
+
+// Tile of workgroup b in a grid of gridDim.x (a multiple of kXcds)
+// workgroups: consecutive tiles go to the same XCD.
+__device__ inline int tile_of_block(int b, int nblocks) {
+  const int per = nblocks / kXcds;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+template <typename S, typename C, int NL, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(256)
+step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> kc) {
+  const int W = blockDim.x;
+  const int tid = threadIdx.x;
+  const int tile = tile_of_block(blockIdx.x, gridDim.x);
+  if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)
+  const int strip = tile % kc.nstrip;
+  const int seg = tile / kc.nstrip;
+  const int x0 = strip * kc.wout;
+  const int w = min(kc.wout, kc.nx - x0);
+  const int y0 = seg * kc.seg_h;
+  const int y1 = min(y0 + kc.seg_h, kc.ny);
+  const int dir = (seg & 1) ? -1 : 1;  // marching direction in y
+  const uint32_t rowb = (uint32_t)kc.pitch * (uint32_t)sizeof(S);  // bytes per row
+  const uint32_t planeb = (uint32_t)(kc.plane * (long long)sizeof(S));  // bytes per plane
+  const uint32_t layerb = planeb * (uint32_t)kQ;                          // bytes per layer
+  if (w <= 0 || y1 <= y0) return;  // uniform per workgroup; never taken with host geometry
+  __amdgpu_buffer_rsrc_t rs[NL], rd[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    rs[i] = make_rsrc(src + (long long)i * kQ * kc.plane, layerb);
+    rd[i] = make_rsrc(dst + (long long)i * kQ * kc.plane, layerb);
+  }
+
+  extern __shared__ unsigned char smem_raw[];
+  C* zr = reinterpret_cast<C*>(smem_raw);  // [5][NL][W]
+  C* pr = zr + 5 * NL * W;                 // [3][NL][W]
+
+  const int lc = tid - 2;                      // local column of this lane
+  const bool act1 = tid < w + 4;               // loads / dz
+  const bool act2 = tid >= 1 && tid <= w + 2;  // pressure
+  const bool act3 = tid >= 2 && tid < w + 2;   // collide + stream
+  const int x = wrap(x0 + lc, kc.nx);
+  const uint32_t bx = (uint32_t)x * sizeof(S);
+  const uint32_t bxm = (uint32_t)wrap(x - 1, kc.nx) * sizeof(S);
+  const uint32_t bxp = (uint32_t)wrap(x + 1, kc.nx) * sizeof(S);
+
+  // register pipeline of moments: row of iteration it (0), it-1 (1), it-2 (2)
+  C dh0[NL], qx0[NL], qy0[NL];
+  C dh1[NL], qx1[NL], qy1[NL];
+  C dh2[NL], qx2[NL], qy2[NL];
+  // populations of the current row and the prefetched next row (ping-pong)
+  C fa[NL][kQ], fb[NL][kQ];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) fa[i][k] = fb[i][k] = C(0);
+    dh0[i] = dh1[i] = dh2[i] = C(0);
+    qx0[i] = qx1[i] = qx2[i] = C(0);
+    qy0[i] = qy1[i] = qy2[i] = C(0);
+  }
+
+  // Every path through the row loop issues the same vector-memory sequence
+  // (9N loads, then 9N stores), inactive lanes using masked offsets: the
+  // compiler's wait for a row's loads then never covers the stores issued
+  // after them, and the prefetched row stays in flight across P2 and P3.
+  // Pre-collision f_k(x, y) = S_k(x - c_kx, y): directions 1, 2, 8 read
+  // column x - 1, directions 4, 5, 6 column x + 1.
+  auto load_row = [&](int r, bool valid, C (&fn)[NL][kQ]) {
+    const bool ok = act1 && valid;
+    const uint32_t row = (uint32_t)wrap(r, kc.ny) * rowb;
+    const uint32_t om = ok ? row + bxm : kMasked, o0 = ok ? row + bx : kMasked,
+                   op = ok ? row + bxp : kMasked;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      fn[i][0] = C(bload<S>(rs[i], o0, 0u * planeb));
+      fn[i][1] = C(bload<S>(rs[i], om, 1u * planeb));
+      fn[i][2] = C(bload<S>(rs[i], om, 2u * planeb));
+      fn[i][3] = C(bload<S>(rs[i], o0, 3u * planeb));
+      fn[i][4] = C(bload<S>(rs[i], op, 4u * planeb));
+      fn[i][5] = C(bload<S>(rs[i], op, 5u * planeb));
+      fn[i][6] = C(bload<S>(rs[i], op, 6u * planeb));
+      fn[i][7] = C(bload<S>(rs[i], o0, 7u * planeb));
+      fn[i][8] = C(bload<S>(rs[i], om, 8u * planeb));
+    }
+  };
+  // Post-collision f*_k(x, y) goes to S_k(x, y + c_ky): row offsets oS, oC, oN
+  // are for rows y - 1, y, y + 1 at this lane's column.
+  auto store_row = [&](bool ok, uint32_t oS, uint32_t oC, uint32_t oN, const C (&fo)[NL][kQ]) {
+    const uint32_t mS = ok ? oS : kMasked, mC = ok ? oC : kMasked, mN = ok ? oN : kMasked;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      bstore(rd[i], mC, 0u * planeb, S(fo[i][0]));
+      bstore(rd[i], mC, 1u * planeb, S(fo[i][1]));
+      bstore(rd[i], mN, 2u * planeb, S(fo[i][2]));
+      bstore(rd[i], mN, 3u * planeb, S(fo[i][3]));
+      bstore(rd[i], mN, 4u * planeb, S(fo[i][4]));
+      bstore(rd[i], mC, 5u * planeb, S(fo[i][5]));
+      bstore(rd[i], mS, 6u * planeb, S(fo[i][6]));
+      bstore(rd[i], mS, 7u * planeb, S(fo[i][7]));
+      bstore(rd[i], mS, 8u * planeb, S(fo[i][8]));
+    }
+  };
+
+  const int niter = (y1 - y0) + 4;
+  const int rstart = dir > 0 ? y0 - 2 : y1 + 1;  // row of iteration 0
+
+  auto body = [&](int it, C (&fc)[NL][kQ], C (&fn)[NL][kQ]) {
+    const int r = rstart + dir * it;
+    // ---- P1: moments and interface deviations of row r ------------------
+    {
+      const int zs = it % 5;
+      C dz = C(0);
+      int bad = 0;
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const C* f = fc[i];
+        C dh = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        C qx = (f[1] + f[2] + f[8]) - (f[4] + f[5] + f[6]);
+        C qy = (f[2] + f[3] + f[4]) - (f[6] + f[7] + f[8]);
+        dh0[i] = dh;
+        qx0[i] = qx;
+        qy0[i] = qy;
+        dz += dh;
+        zr[(zs * NL + i) * W + tid] = dz;
+        C h = kc.hbar[i] + dh;
+        if (!(h > C(0))) bad = 1;
+        if (!(h - h == C(0)) || !(qx - qx == C(0)) || !(qy - qy == C(0))) bad = 2;
+      }
+      if (act1 && bad) kc.flag[0] = bad;
+    }
+    // Prefetch the next row only after this row's registers are consumed: the
+    // loads then stay in flight across both barriers and the stores of P3,
+    // and the wait at the next P1 covers these loads but not those stores.
+    load_row(r + dir, it + 1 < niter, fn);
+    __syncthreads();
+    // ---- P2: pressures of row r - dir ---------------------------------------
+    if (it >= 2 && act2) {
+      const int sA = (it - 2) % 5, sC = (it - 1) % 5, sB = it % 5;
+      const int sS = dir > 0 ? sA : sB, sN = dir > 0 ? sB : sA;  // rows y-1, y+1
+      C dzv[NL + 1], lap[NL + 1], qq[NL + 1];
+      dzv[0] = C(0);
+      qq[0] = C(0);
+      lap[0] = C(0);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const C* a = zr + (sS * NL + i) * W + tid;
+        const C* c = zr + (sC * NL + i) * W + tid;
+        const C* n = zr + (sN * NL + i) * W + tid;
+        const C sw = a[-1], s = a[0], se = a[1];
+        const C wv = c[-1], cc = c[0], e = c[1];
+        const C nw = n[-1], nn = n[0], ne = n[1];
+        const C gx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
+        const C gy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
+        lap[i + 1] = (C(4) * ((e + wv) + (nn + s)) + ((ne + nw) + (se + sw)) - C(20) * cc) *
+                     C(1.0 / 6.0);
+        qq[i + 1] = gx * gx + gy * gy;
+        dzv[i + 1] = cc;
+      }
+      C sphi[NL + 1], dup[NL + 1], ddn[NL + 1];
+#pragma unroll
+      for (int i = 0; i <= NL; ++i) sphi[i] = dup[i] = ddn[i] = C(0);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+#pragma unroll
+        for (int kk = 1; kk <= NL - l; ++kk) {
+          const C d = kc.dbar[l][kk - 1] + (dzv[l + kk] - dzv[l]);
+          const C rd = rcp(d);
+          const C rr = kc.khs[kk - 1] * rd;
+          C ra, rb;
+          pow_ab<EA, EB>(rr, kc, ra, rb);
+          const C s = kc.spread[l][kk - 1];
+          const C phi = s * (kc.ca * rb - kc.cb * ra);
+          const C dphi = s * kc.cab * (ra - rb) * rd;
+          sphi[l] += phi;
+          dup[l] += dphi;
+          ddn[l + kk] += dphi * (C(1) + C(0.5) * qq[l]);
+        }
+      }
+      const int ps = (it - 2) % 3;
+      C acc = C(0);
+#pragma unroll
+      for (int i = NL; i >= 1; --i) {
+        const C delta = -(kc.gamma[i - 1] + sphi[i]) * lap[i] - dup[i] * (C(1) + C(0.5) * qq[i]) + ddn[i];
+        acc += delta;
+        pr[(ps * NL + (i - 1)) * W + tid] = acc;
+      }
+    }
+    __syncthreads();
+    // ---- P3: force, collision and streaming of row y = r - 2 dir ------------
+    const bool st_ok = it >= 4 && act3;
+    const int y = wrap(r - 2 * dir, kc.ny);
+    const uint32_t oC = (uint32_t)y * rowb + bx;
+    const uint32_t oS = (uint32_t)wrap(y - 1, kc.ny) * rowb + bx;
+    const uint32_t oN = (uint32_t)wrap(y + 1, kc.ny) * rowb + bx;
+    C fo[NL][kQ];
+    if (st_ok) {
+      const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
+      const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
+      C h[NL], ux[NL], uy[NL], g[NL + 1];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        h[i] = kc.hbar[i] + dh2[i];
+        const C rh = rcp(h[i]);
+        ux[i] = qx2[i] * rh;
+        uy[i] = qy2[i] * rh;
+        g[i] = kc.mu[i] * rh;
+      }
+      g[NL] = C(0);
+      // Thomas elimination for the interface velocities (x and y share pivots)
+      C cpr[NL], vx[NL], vy[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const C diag = C(2) * (g[i] + g[i + 1]);
+        const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
+        const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
+        if (i == 0) {
+          const C im = rcp(diag);
+          cpr[i] = g[i + 1] * im;
+          vx[i] = rx * im;
+          vy[i] = ry * im;
+        } else {
+          const C im = rcp(diag - g[i] * cpr[i - 1]);
+          cpr[i] = g[i + 1] * im;
+          vx[i] = (rx - g[i] * vx[i - 1]) * im;
+          vy[i] = (ry - g[i] * vy[i - 1]) * im;
+        }
+      }
+#pragma unroll
+      for (int i = NL - 2; i >= 0; --i) {
+        vx[i] -= cpr[i] * vx[i + 1];
+        vy[i] -= cpr[i] * vy[i + 1];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const C* a = pr + (pS * NL + i) * W + tid;
+        const C* c = pr + (pC * NL + i) * W + tid;
+        const C* n = pr + (pN * NL + i) * W + tid;
+        const C sw = a[-1], s = a[0], se = a[1];
+        const C wv = c[-1], e = c[1];
+        const C nw = n[-1], nn = n[0], ne = n[1];
+        const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
+        const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
+        const C vlo_x = i > 0 ? vx[i - 1] : C(0), vlo_y = i > 0 ? vy[i - 1] : C(0);
+        const C frx = C(6) * g[i] * ((vlo_x + vx[i]) - C(2) * ux[i]);
+        const C fry = C(6) * g[i] * ((vlo_y + vy[i]) - C(2) * uy[i]);
+        const C Fx = -h[i] * gpx + frx;
+        const C Fy = -h[i] * gpy + fry;
+        const C qx = qx2[i], qy = qy2[i];
+        const C qu = qx * ux[i] + qy * uy[i];
+        const C t15 = C(1.5) * qu;
+        // equilibrium (rest population as deviation from hbar) and forcing
+        C feq[kQ], frc[kQ];
+        feq[0] = dh2[i] - C(2.0 / 3.0) * qu;
+        frc[0] = C(0);
+        const C ax = C(4.5) * qx * ux[i], ay = C(4.5) * qy * uy[i];
+        feq[1] = C(1.0 / 9.0) * (C(3) * qx + ax - t15);
+        feq[5] = C(1.0 / 9.0) * (-C(3) * qx + ax - t15);
+        feq[3] = C(1.0 / 9.0) * (C(3) * qy + ay - t15);
+        feq[7] = C(1.0 / 9.0) * (-C(3) * qy + ay - t15);
+        const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
+        const C dpp = C(4.5) * spq * spu, dmm = C(4.5) * smq * smu;
+        feq[2] = C(1.0 / 36.0) * (C(3) * spq + dpp - t15);
+        feq[6] = C(1.0 / 36.0) * (-C(3) * spq + dpp - t15);
+        feq[4] = C(1.0 / 36.0) * (C(3) * smq + dmm - t15);
+        feq[8] = C(1.0 / 36.0) * (-C(3) * smq + dmm - t15);
+        frc[1] = C(1.0 / 3.0) * Fx;
+        frc[5] = -frc[1];
+        frc[3] = C(1.0 / 3.0) * Fy;
+        frc[7] = -frc[3];
+        frc[2] = C(1.0 / 12.0) * (Fx + Fy);
+        frc[6] = -frc[2];
+        frc[4] = C(1.0 / 12.0) * (Fy - Fx);
+        frc[8] = -frc[4];
+        if constexpr (TAU1) {
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) fo[i][k] = feq[k] + frc[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) fo[i][k] = kc.omega * feq[k] + frc[k];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) fo[i][k] = C(0);
+    }
+    if constexpr (!TAU1) {
+      // f* = (1 - omega) f + [omega f^eq + forcing]; the pre-collision
+      // populations of row y are re-read (cache hits: loaded two rows ago)
+      C fy[NL][kQ];
+      load_row(y, st_ok, fy);
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
+    }
+    store_row(st_ok, oS, oC, oN, fo);
+    // rotate the moment pipeline
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      dh2[i] = dh1[i];
+      qx2[i] = qx1[i];
+      qy2[i] = qy1[i];
+      dh1[i] = dh0[i];
+      qx1[i] = qx0[i];
+      qy1[i] = qy0[i];
+    }
+  };
+
+  load_row(rstart, true, fa);
+  {
+    // dropped stores: the loop is entered with the same pending sequence
+    // (loads, then stores) as every later iteration
+    C zero[NL][kQ];
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) zero[i][k] = C(0);
+    store_row(false, 0, 0, 0, zero);
+  }
+  int it = 0;
+  for (; it + 1 < niter; it += 2) {
+    body(it, fa, fb);
+    body(it + 1, fb, fa);
+  }
+  if (it < niter) body(it, fa, fb);
+}
+
+}  // namespace mlf

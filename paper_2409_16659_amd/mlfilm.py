@@ -1,0 +1,282 @@
+"""ctypes binding of ``libmlfilm.so`` (C ABI in ``include/mlfilm.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies the device buffers (caller-owned, as the ABI requires) and
+the stream.  If the library has not been built this module raises; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+MAX_LAYERS = 4
+MAX_PAIRS = MAX_LAYERS * (MAX_LAYERS + 1) // 2
+F64, F32, F16, BF16 = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16dev": F16, "bf16dev": BF16}
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFINITE",
+          -5: "ENONPOSITIVE", -6: "EUNSTABLE"}
+
+
+class MlfError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        super().__init__(f"{what} failed: {STATUS.get(code, code)}" + (f" ({detail})" if detail else ""))
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_layers", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
+        ("tau", C.c_double), ("hstar", C.c_double), ("exp_a", C.c_int32), ("exp_b", C.c_int32),
+        ("gamma", C.c_double * MAX_LAYERS), ("mu", C.c_double * MAX_LAYERS),
+        ("slip", C.c_double * MAX_LAYERS), ("spread", C.c_double * MAX_PAIRS),
+        ("check_every", C.c_int32), ("allow_unstable", C.c_int32),
+    ]
+
+
+_D = C.POINTER(C.c_double)
+_lib = None
+
+
+def load_library():
+    """Load the built library; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run python -m paper_2409_16659_amd.build")
+    lib = C.CDLL(path)
+    P = C.POINTER(Params)
+    H = C.c_void_p
+    st = C.c_int
+    sig = {
+        "mlf_query_sizes": (st, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "mlf_query_pitch": (st, [P, C.POINTER(C.c_int32)]),
+        "mlf_create": (st, [P, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(H)]),
+        "mlf_init": (st, [H, _D, _D, _D]),
+        "mlf_init_device": (st, [H, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "mlf_step": (st, [H, C.c_int64]),
+        "mlf_read": (st, [H, _D, _D, _D]),
+        "mlf_read_device": (st, [H, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "mlf_layer_mass": (st, [H, _D]),
+        "mlf_read_populations": (st, [H, _D]),
+        "mlf_write_populations": (st, [H, _D]),
+        "mlf_save": (st, [H, C.c_void_p, C.POINTER(C.c_size_t)]),
+        "mlf_load": (st, [H, C.c_void_p, C.c_size_t]),
+        "mlf_set_launch": (st, [H, C.c_int32, C.c_int32]),
+        "mlf_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mlf_steps_done": (C.c_int64, [H]),
+        "mlf_last_error": (C.c_char_p, [H]),
+        "mlf_destroy": (st, [H]),
+        "mlf_spreading_from_tensions": (st, [C.c_int32, _D, _D]),
+        "mlf_friction_matrix": (st, [C.c_int32, _D, _D, _D, _D]),
+        "mlf_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def make_params(film, precision="f64", check_every=0, allow_unstable=False) -> Params:
+    """Copy a film parameter mapping (see ``inputs``) into the ABI struct."""
+    p = Params()
+    n = int(film["n_layers"])
+    p.n_layers, p.nx, p.ny = n, int(film["nx"]), int(film["ny"])
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.tau = float(film.get("tau", 1.0))
+    p.hstar = float(film["hstar"])
+    p.exp_a, p.exp_b = int(film.get("exp_a", 9)), int(film.get("exp_b", 3))
+    for i in range(n):
+        p.gamma[i] = float(film["gamma"][i])
+        p.mu[i] = float(film["mu"][i])
+        p.slip[i] = float(film.get("slip", [0.0] * n)[i])
+    idx = 0
+    spread = dict(film.get("spread", {}))
+    for l in range(n):
+        for k in range(1, n - l + 1):
+            p.spread[idx] = float(spread.get((l, k), 0.0))
+            idx += 1
+    for key in spread:
+        l, k = key
+        if not (0 <= l < n and 1 <= k <= n - l):
+            raise ValueError(f"spreading coefficient S_{l}{k} out of range for N={n}")
+    p.check_every = int(check_every)
+    p.allow_unstable = 1 if allow_unstable else 0
+    return p
+
+
+def query_sizes(params: Params):
+    lib = load_library()
+    a, b = C.c_size_t(), C.c_size_t()
+    rc = lib.mlf_query_sizes(C.byref(params), C.byref(a), C.byref(b))
+    if rc:
+        raise MlfError(rc, "mlf_query_sizes")
+    return a.value, b.value
+
+
+def query_pitch(params: Params) -> int:
+    lib = load_library()
+    v = C.c_int32()
+    rc = lib.mlf_query_pitch(C.byref(params), C.byref(v))
+    if rc:
+        raise MlfError(rc, "mlf_query_pitch")
+    return v.value
+
+
+def spreading_from_tensions(n: int, g) -> dict:
+    lib = load_library()
+    g = _f64(g)
+    out = np.zeros(MAX_PAIRS)
+    rc = lib.mlf_spreading_from_tensions(int(n), _dp(g), _dp(out))
+    if rc:
+        raise MlfError(rc, "mlf_spreading_from_tensions")
+    res, idx = {}, 0
+    for l in range(n):
+        for k in range(1, n - l + 1):
+            res[(l, k)] = out[idx]
+            idx += 1
+    return res
+
+
+def friction_matrix(h, mu):
+    lib = load_library()
+    h, mu = _f64(h), _f64(mu)
+    n = h.shape[0]
+    K = np.zeros((n, n))
+    rate = C.c_double()
+    rc = lib.mlf_friction_matrix(n, _dp(h), _dp(mu), _dp(K), C.byref(rate))
+    if rc:
+        raise MlfError(rc, "mlf_friction_matrix")
+    return K, rate.value
+
+
+class Film:
+    """One film on the current CUDA/HIP device.
+
+    Device buffers are torch uint8 tensors owned by this object; the stream is
+    torch's current stream at construction unless one is given.
+    """
+
+    def __init__(self, film, precision="f64", check_every=0, allow_unstable=False,
+                 stream=None, device=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.film = dict(film)
+        self.params = make_params(film, precision, check_every, allow_unstable)
+        self.n, self.nx, self.ny = self.params.n_layers, self.params.nx, self.params.ny
+        pop_bytes, scratch_bytes = query_sizes(self.params)
+        self.pop_bytes, self.scratch_bytes = pop_bytes, scratch_bytes
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = dev
+        self.pop_a = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.pop_b = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = C.c_void_p()
+        rc = self.lib.mlf_create(C.byref(self.params), C.c_void_p(self.pop_a.data_ptr()),
+                                 C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.scratch.data_ptr()),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise MlfError(rc, "mlf_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.mlf_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc, what):
+        if rc:
+            detail = self.lib.mlf_last_error(self.h)
+            raise MlfError(rc, what, detail.decode() if detail else "")
+
+    def init(self, h, ux=None, uy=None):
+        t = self.torch
+        if isinstance(h, t.Tensor):
+            args = [None if a is None else C.c_void_p(a.data_ptr()) for a in (h, ux, uy)]
+            for a in (h, ux, uy):
+                if a is not None:
+                    assert a.dtype == t.float64 and a.is_contiguous() and a.device.type == "cuda"
+                    assert tuple(a.shape) == (self.n, self.ny, self.nx)
+            self._check(self.lib.mlf_init_device(self.h, *args), "mlf_init_device")
+            return
+        h = _f64(h)
+        assert h.shape == (self.n, self.ny, self.nx)
+        ux = None if ux is None else _f64(ux)
+        uy = None if uy is None else _f64(uy)
+        self._check(self.lib.mlf_init(self.h, _dp(h), _dp(ux), _dp(uy)), "mlf_init")
+
+    def step(self, n=1):
+        self._check(self.lib.mlf_step(self.h, int(n)), "mlf_step")
+
+    @property
+    def steps_done(self) -> int:
+        return int(self.lib.mlf_steps_done(self.h))
+
+    def read(self):
+        shape = (self.n, self.ny, self.nx)
+        h, ux, uy = np.empty(shape), np.empty(shape), np.empty(shape)
+        self._check(self.lib.mlf_read(self.h, _dp(h), _dp(ux), _dp(uy)), "mlf_read")
+        return h, ux, uy
+
+    def read_device(self, out=None):
+        t = self.torch
+        shape = (self.n, self.ny, self.nx)
+        if out is None:
+            out = tuple(t.empty(shape, dtype=t.float64, device=self.device) for _ in range(3))
+        ptrs = [None if a is None else C.c_void_p(a.data_ptr()) for a in out]
+        self._check(self.lib.mlf_read_device(self.h, *ptrs), "mlf_read_device")
+        return out
+
+    def mass(self):
+        m = np.empty(self.n)
+        self._check(self.lib.mlf_layer_mass(self.h, _dp(m)), "mlf_layer_mass")
+        return m
+
+    def populations(self):
+        f = np.empty((self.n, 9, self.ny, self.nx))
+        self._check(self.lib.mlf_read_populations(self.h, _dp(f)), "mlf_read_populations")
+        return f
+
+    def set_populations(self, f):
+        f = _f64(f)
+        assert f.shape == (self.n, 9, self.ny, self.nx)
+        self._check(self.lib.mlf_write_populations(self.h, _dp(f)), "mlf_write_populations")
+
+    def save(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self.lib.mlf_save(self.h, None, C.byref(n)), "mlf_save")
+        buf = C.create_string_buffer(n.value)
+        self._check(self.lib.mlf_save(self.h, buf, C.byref(n)), "mlf_save")
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.lib.mlf_load(self.h, buf, len(blob)), "mlf_load")
+
+    def set_launch(self, block_w=0, seg_h=0):
+        self._check(self.lib.mlf_set_launch(self.h, int(block_w), int(seg_h)), "mlf_set_launch")
+
+    def get_launch(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.mlf_get_launch(self.h, C.byref(a), C.byref(b)), "mlf_get_launch")
+        return a.value, b.value

@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical seeded inputs, plus properties that hold at any size.
+
+Gates (relative to the reference's maximum):
+  FP64:  e_h = max|h - h_ref| / max|h_ref| <= 1e-12,
+         e_U = max over x, y components of |U - U_ref| / max |U_ref| <= 1e-10
+  FP32:  e_h <= 1e-5,  e_U <= 1e-4 (short horizons, linear regime)
+  mass:  per-layer relative drift <= 1e-12 (FP64 storage)
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2409_16659_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mlf(torch_cuda):
+    from paper_2409_16659_amd import mlfilm
+
+    mlfilm.load_library()
+    return mlfilm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run_pair(mlf, oracle_mod, film, h0, steps, precision="f64", launch=None, ux=None, uy=None):
+    say(f"case N={film['n_layers']} {film['nx']}x{film['ny']} {precision} steps={steps} launch={launch}")
+    g = mlf.Film(film, precision)
+    if launch:
+        g.set_launch(*launch)
+    g.init(h0, ux, uy)
+    o = oracle_mod.Oracle(film)
+    o.init(h0, ux, uy)
+    g.step(steps)
+    o.step(steps)
+    return g, o
+
+
+def check(g, o, tol_h, tol_u):
+    hg, uxg, uyg = g.read()
+    ho, uxo, uyo = o.read()
+    eh = err(hg, ho)
+    # velocity error against the velocity scale of both components (on a
+    # single-row film U_y is pure rounding noise)
+    uscale = max(np.abs(uxo).max(), np.abs(uyo).max(), 1e-300)
+    eu = float(max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / uscale)
+    say(f"   e_h={eh:.3e} e_U={eu:.3e}")
+    assert eh <= tol_h, eh
+    assert eu <= tol_u, eu
+    return eh, eu
+
+
+def small_film(n, nx, ny, seed=0, hstar=0.15, tau=1.0, exps=(9, 3)):
+    rng = np.random.default_rng(seed)
+    gam = list(rng.uniform(0.5e-2, 1.5e-2, size=n))
+    spread = {(l, 1): inputs.young_spreading(gam[l], 20.0) for l in range(n)}
+    for l in range(n):
+        for k in range(2, n - l + 1):
+            spread[(l, k)] = rng.uniform(-2e-3, 2e-3)
+    mu = list(rng.uniform(2e-3, 5e-3, size=n))
+    return inputs.film_params(n, nx, ny, gamma=gam, mu=mu, hstar=hstar, spread=spread, tau=tau,
+                              exp_a=exps[0], exp_b=exps[1])
+
+
+def noisy(n, nx, ny, seed, amp=1e-2):
+    rng = np.random.default_rng(seed)
+    return np.stack([(1.0 - 0.15 * i) + amp * rng.uniform(-1, 1, size=(ny, nx)) for i in range(n)])
+
+
+# ------------------------------------------------------------------ FP64 --
+def test_fp64_two_layer_workload(mlf, oracle_mod):
+    """The 2-layer pseudo-1D workload over its full 10^4 steps."""
+    film, h0, spec = inputs.workload("film2_pseudo1d_512")
+    g = mlf.Film(film, "f64")
+    g.init(h0)
+    o = oracle_mod.Oracle(film)
+    o.init(h0)
+    m0 = g.mass()
+    for t in (1000, 10_000):
+        g.step(t - g.steps_done)
+        o.step(t - o.steps_done)
+        check(g, o, 1e-12, 1e-10)
+    m1 = g.mass()
+    assert np.abs(m1 - m0).max() <= 1e-12 * m0.max()
+    assert np.abs(m1 - o.mass()).max() <= 1e-12 * m0.max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_fp64_ragged_2d(mlf, oracle_mod, n):
+    """2D films spanning several strips and segments with ragged tails."""
+    film = small_film(n, 150, 70, seed=n)
+    h0 = noisy(n, 150, 70, seed=100 + n)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 300, "f64", launch=(64, 16))
+    check(g, o, 1e-12, 1e-10)
+    fo = o.get_f()
+    fg = g.populations()
+    assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max()
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (3, 2), (5, 3), (7, 1), (1, 6), (64, 2), (61, 5), (65, 9)])
+def test_fp64_tiny_and_degenerate_grids(mlf, oracle_mod, nx, ny):
+    film = small_film(2, nx, ny, seed=7)
+    h0 = noisy(2, nx, ny, seed=8)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 50, "f64", launch=(64, 4))
+    check(g, o, 1e-12, 1e-10)
+
+
+def test_fp64_general_tau_and_exponents(mlf, oracle_mod):
+    film = small_film(3, 70, 33, seed=9, tau=0.8, exps=(4, 3))
+    h0 = noisy(3, 70, 33, seed=10)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 200, "f64", launch=(128, 8))
+    check(g, o, 1e-12, 1e-10)
+    film = small_film(2, 70, 33, seed=11, tau=1.3)
+    g, o = run_pair(mlf, oracle_mod, film, noisy(2, 70, 33, seed=12), 200, "f64")
+    check(g, o, 1e-12, 1e-10)
+
+
+def test_fp64_initial_velocity(mlf, oracle_mod):
+    film = small_film(2, 40, 30, seed=13)
+    rng = np.random.default_rng(14)
+    h0 = noisy(2, 40, 30, seed=15)
+    ux = 1e-3 * rng.uniform(-1, 1, size=h0.shape)
+    uy = 1e-3 * rng.uniform(-1, 1, size=h0.shape)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 100, "f64", ux=ux, uy=uy)
+    check(g, o, 1e-12, 1e-10)
+
+
+# ------------------------------------------------------------------ FP32 --
+def test_fp32_three_layer_crop(mlf, oracle_mod):
+    """The 3-layer workload's parameters on a 256x200 crop, 2000 steps."""
+    film, h0, _ = inputs.workload("film3_2d_1024")
+    film["nx"], film["ny"] = 256, 200
+    h0 = np.ascontiguousarray(h0[:, :200, :256])
+    g, o = run_pair(mlf, oracle_mod, film, h0, 2000, "f32")
+    check(g, o, 1e-5, 1e-4)
+    m_g, m_o = g.mass(), o.mass()
+    say("   mass rel diff", np.abs(m_g - m_o).max() / m_o.max())
+    assert np.abs(m_g - m_o).max() <= 1e-9 * m_o.max()
+
+
+def test_fp32_three_layer_full_size(mlf, oracle_mod):
+    """Full 1024x1024 3-layer workload in the benchmark's launch shape."""
+    film, h0, _ = inputs.workload("film3_2d_1024")
+    g, o = run_pair(mlf, oracle_mod, film, h0, 20, "f32")
+    check(g, o, 1e-5, 1e-4)
+
+
+# ------------------------------------------------------------ properties --
+def test_launch_shape_independence(mlf):
+    """Per-node arithmetic has a fixed order, so every launch shape gives
+    bit-identical results (a race or halo bug would break this)."""
+    for prec in ("f64", "f32"):
+        film = small_film(3, 300, 45, seed=16)
+        h0 = noisy(3, 300, 45, seed=17)
+        ref = None
+        for launch in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 45), (128, 3)]:
+            say(f"shape {prec} {launch}")
+            g = mlf.Film(film, prec)
+            g.set_launch(*launch)
+            g.init(h0)
+            g.step(40)
+            f = g.populations()
+            if ref is None:
+                ref = f
+            else:
+                assert np.array_equal(f, ref), launch
+
+
+def test_flat_film_fixed_point(mlf):
+    film = small_film(4, 67, 29, seed=18)
+    h0 = np.stack([np.full((29, 67), v) for v in (0.9, 0.6, 0.45, 0.3)])
+    for prec in ("f64", "f32"):
+        g = mlf.Film(film, prec)
+        g.init(h0)
+        f0 = g.populations()
+        g.step(500)
+        assert np.array_equal(g.populations(), f0)
+
+
+def _shift_blob(g, blob, dx, dy):
+    """Roll the raw population payload of a checkpoint by a lattice vector."""
+    pitch = mlf_pitch(g)
+    dt = np.float64 if g.params.precision == 0 else np.float32
+    head = len(blob) - g.pop_bytes
+    pay = np.frombuffer(blob[head:], dtype=dt).reshape(g.n, 9, g.ny, pitch).copy()
+    pay[..., : g.nx] = np.roll(np.roll(pay[..., : g.nx], dx, axis=3), dy, axis=2)
+    return blob[:head] + pay.tobytes()
+
+
+def mlf_pitch(g):
+    from paper_2409_16659_amd import mlfilm
+
+    return mlfilm.query_pitch(g.params)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_translation_equivariance(mlf, prec):
+    """Shifting the stored populations by a lattice vector shifts the result
+    of later steps by the same vector, bit for bit."""
+    film = small_film(2, 90, 40, seed=19)
+    h0 = noisy(2, 90, 40, seed=20)
+    g = mlf.Film(film, prec)
+    g.init(h0)
+    g.step(3)
+    blob = g.save()
+    g.step(7)
+    want = _shift_blob(g, g.save(), 5, -3)
+    g2 = mlf.Film(film, prec)
+    g2.load(_shift_blob(g2, blob, 5, -3))
+    g2.step(7)
+    got = g2.save()
+    assert got[len(got) - g2.pop_bytes:] == want[len(want) - g.pop_bytes:]
+    # zeroed padding: whole checkpoints of equal states are byte-identical
+    a = mlf.Film(film, prec)
+    a.init(h0)
+    a.step(10)
+    b = mlf.Film(film, prec)
+    b.init(h0)
+    b.step(10)
+    assert a.save() == b.save()
+
+
+def test_mass_conservation(mlf):
+    film, h0, _ = inputs.workload("film3_2d_1024")
+    film["nx"], film["ny"] = 512, 512
+    h0 = np.ascontiguousarray(h0[:, :512, :512])
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-9)):
+        g = mlf.Film(film, prec)
+        g.init(h0)
+        m0 = g.mass()
+        g.step(3000)
+        m1 = g.mass()
+        rel = np.abs(m1 - m0).max() / m0.max()
+        say(f"   {prec} mass drift {rel:.3e}")
+        assert rel <= tol
+
+
+def test_checkpoint_round_trip(mlf):
+    film = small_film(3, 80, 60, seed=21)
+    h0 = noisy(3, 80, 60, seed=22)
+    for prec in ("f64", "f32"):
+        a = mlf.Film(film, prec)
+        a.init(h0)
+        a.step(50)
+        blob = a.save()
+        a.step(50)
+        fa = a.populations()
+        b = mlf.Film(film, prec)
+        b.load(blob)
+        assert b.steps_done == 50
+        b.step(50)
+        assert np.array_equal(b.populations(), fa)
+        other = small_film(3, 80, 60, seed=23)
+        c = mlf.Film(other, prec)
+        with pytest.raises(mlf.MlfError):
+            c.load(blob)
+
+
+def test_read_paths_agree(mlf, torch_cuda):
+    film = small_film(2, 33, 17, seed=24)
+    g = mlf.Film(film, "f64")
+    g.init(noisy(2, 33, 17, seed=25))
+    g.step(20)
+    h, ux, uy = g.read()
+    hd, uxd, uyd = g.read_device()
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(hd.cpu().numpy(), h)
+    assert np.array_equal(uxd.cpu().numpy(), ux)
+    assert np.array_equal(uyd.cpu().numpy(), uy)
+    f = g.populations()
+    assert np.allclose(f.sum(axis=1), h, rtol=0, atol=1e-15)
+
+
+def test_device_init_matches_host_init(mlf, torch_cuda):
+    film = small_film(3, 45, 31, seed=26)
+    h0 = noisy(3, 45, 31, seed=27)
+    a = mlf.Film(film, "f64")
+    a.init(h0)
+    b = mlf.Film(film, "f64")
+    b.init(torch_cuda.from_numpy(h0).cuda())
+    assert np.allclose(a.populations(), b.populations(), rtol=0, atol=1e-15)
+
+
+def test_guard_trips_on_nonpositive_height(mlf):
+    film = small_film(2, 20, 10, seed=28)
+    g = mlf.Film(film, "f64", check_every=1)
+    g.init(noisy(2, 20, 10, seed=29))
+    f = g.populations()
+    f[1, 0, 4, 7] = -5.0  # forces h < 0 at one node
+    g.set_populations(f)
+    with pytest.raises(mlf.MlfError) as e:
+        g.step(3)
+    assert e.value.status == "ENONPOSITIVE"
