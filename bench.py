@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--seg-h", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget; 0 disables it")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device copy of one population buffer instead (copy ceiling; "
+                         "the reference kernel for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -99,6 +102,25 @@ def main():
     prec = args.precision or spec["precision"]
     n_lu = film["n_layers"] * film["nx"] * film["ny"]
     bytes_per_lu = 18 * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16dev": 2, "bf16dev": 2}[prec]
+
+    if args.copy_probe:
+        nbytes = n_lu * bytes_per_lu // 2
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / reps * 1e-3
+        print(json.dumps({"probe": "device_copy", "workload": args.workload, "bytes_read": nbytes,
+                          "bytes_written": nbytes, "us": sec * 1e6, "GBs": 2 * nbytes / sec / 1e9}), flush=True)
+        return
 
     g = mlfilm.Film(film, prec, check_every=-1)
     g.set_launch(args.block_w, args.seg_h)
