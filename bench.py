@@ -76,8 +76,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="film3_2d_1024")
     ap.add_argument("--precision", default=None, help="override the workload's storage precision")
-    ap.add_argument("--block-w", type=int, default=0)
-    ap.add_argument("--seg-h", type=int, default=0)
+    ap.add_argument("--block-w", type=int, default=0, help="launch shape; default: autotuned")
+    ap.add_argument("--seg-h", type=int, default=0, help="launch shape; default: autotuned")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget; 0 disables it")
     ap.add_argument("--copy-probe", action="store_true",
@@ -123,9 +123,12 @@ def main():
         return
 
     g = mlfilm.Film(film, prec, check_every=-1)
-    g.set_launch(args.block_w, args.seg_h)
-    launch = g.get_launch()
     g.init(h0)
+    if args.block_w or args.seg_h:
+        g.set_launch(args.block_w, args.seg_h)
+    else:
+        g.autotune(reps=3)  # library autotuner: times shapes, state unchanged
+    launch = g.get_launch()
     print(f"[bench] {args.workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
           f"launch={launch} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
     g.step(args.warmup)

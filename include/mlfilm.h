@@ -141,11 +141,21 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f);
 mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes);
 mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
 
-/* Launch shape of the step kernel: block_w threads (64, 128, 256 or 512)
- * each owning one column of a strip of block_w columns, and seg_h rows per
- * workgroup (>= 1).  Results do not depend on the shape.  0 = default. */
+/* Launch shape of the step kernel: block_w threads (64, 128, 192 or 256),
+ * one per column of a strip of block_w - 4 columns plus two halo columns on
+ * each side, and seg_h rows per workgroup (>= 1).  Results do not depend on
+ * the shape.  0 = default. */
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h);
 mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h);
+
+/* Autotuner: times candidate launch shapes on the current state and keeps
+ * the fastest (written to block_w / seg_h if not NULL).  Each candidate is
+ * launched `reps` times (>= 1) from the current population buffer into the
+ * other one without swapping, so the state and step counter are unchanged.
+ * Candidates: block_w in {64, 128, 192, 256} and segment heights from a
+ * fixed list plus those that fill whole dispatch rounds of the device.
+ * Synchronises. */
+mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h);
 
 int64_t mlf_steps_done(const mlf_handle* h);
 const char* mlf_last_error(const mlf_handle* h);

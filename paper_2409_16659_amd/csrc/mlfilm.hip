@@ -318,7 +318,7 @@ unsigned char* stage_ptr(mlf_handle* h) { return h->scratch + kStageOff; }
 
 void default_launch(const mlf_params* p, int* bw, int* sh) {
   int w = p->nx + 4;
-  *bw = w <= 64 ? 64 : (w <= 128 ? 128 : 256);
+  *bw = w <= 64 ? 64 : (w <= 128 ? 128 : (w <= 192 ? 192 : 256));
   *sh = std::max(1, std::min(p->ny, 12));
 }
 
@@ -332,11 +332,8 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
   k.pitch = h->pitch;
   k.plane = (long long)h->plane;
   const int W = h->block_w;
-  // strips of equal width wout <= W - 4 (lanes cover two halo columns on each
-  // side); recomputing nstrip from wout guarantees no empty strip
-  k.nstrip = (p.nx + (W - 4) - 1) / (W - 4);
-  k.wout = (p.nx + k.nstrip - 1) / k.nstrip;
-  k.nstrip = (p.nx + k.wout - 1) / k.wout;
+  k.wout = mlf::strip_width(p.nx, W);
+  k.nstrip = mlf::strip_count(p.nx, W);
   k.seg_h = h->seg_h;
   k.nseg = (p.ny + k.seg_h - 1) / k.seg_h;
   const int n = p.n_layers;
@@ -351,18 +348,30 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
   for (int l = 0; l < n; ++l)
     for (int kk = 1; kk <= n - l; ++kk) {
       k.dbar[l][kk - 1] = C(z[l + kk] - z[l]);
-      k.spread[l][kk - 1] = C(p.spread[pair_index(n, l, kk)]);
+      const double S = p.spread[pair_index(n, l, kk)];
+      const double a = p.exp_a, b = p.exp_b;
+      k.sa[l][kk - 1] = C(S * a / (a - b));
+      k.sb[l][kk - 1] = C(S * b / (a - b));
+      k.sab[l][kk - 1] = C(S * a * b / (a - b));
     }
   for (int kk = 1; kk <= kMaxLayers; ++kk) k.khs[kk - 1] = C(kk * p.hstar);
-  const double a = p.exp_a, b = p.exp_b;
-  k.ca = C(a / (a - b));
-  k.cb = C(b / (a - b));
-  k.cab = C(a * b / (a - b));
   k.omega = C(1.0 / p.tau);
   k.ea = p.exp_a;
   k.eb = p.exp_b;
   k.flag = flag_ptr(const_cast<mlf_handle*>(h));
   return k;
+}
+
+// Workgroups of the step kernel that fit on one CU at the handle's block
+// width (0 if unknown).
+template <typename S, typename C, int NL, bool T1, int EA, int EB>
+int occupancy_nl(const mlf_handle* h) {
+  int nb = 0;
+  size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mlf::step_kernel<S, C, NL, T1, EA, EB>, h->block_w, lds) !=
+      hipSuccess)
+    return 0;
+  return nb;
 }
 
 template <typename S, typename C, int NL, bool T1, int EA, int EB>
@@ -378,29 +387,48 @@ hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
   return hipGetLastError();
 }
 
+// Dispatch on (layers, tau == 1, exponents == (9, 3)); OCC selects the
+// occupancy query instead of a launch.
 template <typename S, typename C, bool T1, int EA, int EB>
-hipError_t launch_t(const mlf_handle* h, const void* src, void* dst) {
+hipError_t launch_t(const mlf_handle* h, const void* src, void* dst, int* occ) {
   switch (h->p.n_layers) {
-    case 1: return launch_nl<S, C, 1, T1, EA, EB>(h, src, dst);
-    case 2: return launch_nl<S, C, 2, T1, EA, EB>(h, src, dst);
-    case 3: return launch_nl<S, C, 3, T1, EA, EB>(h, src, dst);
-    default: return launch_nl<S, C, 4, T1, EA, EB>(h, src, dst);
+    case 1:
+      if (occ) return *occ = occupancy_nl<S, C, 1, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<S, C, 1, T1, EA, EB>(h, src, dst);
+    case 2:
+      if (occ) return *occ = occupancy_nl<S, C, 2, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<S, C, 2, T1, EA, EB>(h, src, dst);
+    case 3:
+      if (occ) return *occ = occupancy_nl<S, C, 3, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<S, C, 3, T1, EA, EB>(h, src, dst);
+    default:
+      if (occ) return *occ = occupancy_nl<S, C, 4, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<S, C, 4, T1, EA, EB>(h, src, dst);
   }
 }
 
 template <typename S, typename C>
-hipError_t launch_sc(const mlf_handle* h, const void* src, void* dst) {
+hipError_t launch_sc(const mlf_handle* h, const void* src, void* dst, int* occ) {
   const bool t1 = h->p.tau == 1.0;
   const bool e93 = h->p.exp_a == 9 && h->p.exp_b == 3;
-  if (t1 && e93) return launch_t<S, C, true, 9, 3>(h, src, dst);
-  if (t1) return launch_t<S, C, true, 0, 0>(h, src, dst);
-  if (e93) return launch_t<S, C, false, 9, 3>(h, src, dst);
-  return launch_t<S, C, false, 0, 0>(h, src, dst);
+  if (t1 && e93) return launch_t<S, C, true, 9, 3>(h, src, dst, occ);
+  if (t1) return launch_t<S, C, true, 0, 0>(h, src, dst, occ);
+  if (e93) return launch_t<S, C, false, 9, 3>(h, src, dst, occ);
+  return launch_t<S, C, false, 0, 0>(h, src, dst, occ);
 }
 
 hipError_t launch_step(const mlf_handle* h, const void* src, void* dst) {
-  if (h->p.precision == MLF_F64) return launch_sc<double, double>(h, src, dst);
-  return launch_sc<float, float>(h, src, dst);
+  if (h->p.precision == MLF_F64) return launch_sc<double, double>(h, src, dst, nullptr);
+  return launch_sc<float, float>(h, src, dst, nullptr);
+}
+
+int step_occupancy(const mlf_handle* h) {
+  int occ = 0;
+  if (h->p.precision == MLF_F64)
+    launch_sc<double, double>(h, nullptr, nullptr, &occ);
+  else
+    launch_sc<float, float>(h, nullptr, nullptr, &occ);
+  return occ;
 }
 
 unsigned grid_for(long long n) {
@@ -559,8 +587,8 @@ mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h) {
   int bw, sh;
   default_launch(&h->p, &bw, &sh);
   if (block_w != 0) {
-    if (block_w != 64 && block_w != 128 && block_w != 256)
-      return fail(h, MLF_EINVAL, "block_w must be 64, 128 or 256");
+    if (block_w != 64 && block_w != 128 && block_w != 192 && block_w != 256)
+      return fail(h, MLF_EINVAL, "block_w must be 64, 128, 192 or 256");
     bw = block_w;
   }
   if (seg_h != 0) {
@@ -576,6 +604,66 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
   if (!h) return MLF_EINVAL;
   if (block_w) *block_w = h->block_w;
   if (seg_h) *seg_h = h->seg_h;
+  return MLF_OK;
+}
+
+mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h) {
+  if (!h || reps < 1) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "autotune before init");
+  const mlf_params& p = h->p;
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int keep_w = h->block_w, keep_h = h->seg_h;
+  std::vector<std::pair<int, int>> cand;
+  const int fixed[] = {2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64, 96, 128};
+  for (int w : {64, 128, 192, 256}) {
+    h->block_w = w;
+    const int nstrip = mlf::strip_count(p.nx, w);
+    for (int sh : fixed)
+      if (sh <= p.ny) cand.emplace_back(w, sh);
+    // heights that fill 1..4 whole dispatch rounds
+    const int slots = std::max(1, step_occupancy(h)) * std::max(1, ncu);
+    for (int rounds = 1; rounds <= 4; ++rounds) {
+      const int segs = std::max(1, rounds * slots / nstrip);
+      const int sh = std::max(1, (p.ny + segs - 1) / segs);
+      cand.emplace_back(w, std::min(sh, p.ny));
+    }
+  }
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bw = keep_w, bh = keep_h;
+  mlf_status st = MLF_OK;
+  for (const auto& c : cand) {
+    h->block_w = c.first;
+    h->seg_h = c.second;
+    // current -> other buffer, never swapped: the state is left unchanged
+    if ((st = hip_check(h, launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]), "autotune launch")) != MLF_OK) break;
+    if ((st = hip_check(h, hipEventRecord(e0, h->stream), "hipEventRecord")) != MLF_OK) break;
+    for (int r = 0; r < reps && st == MLF_OK; ++r)
+      st = hip_check(h, launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]), "autotune launch");
+    if (st != MLF_OK) break;
+    if ((st = hip_check(h, hipEventRecord(e1, h->stream), "hipEventRecord")) != MLF_OK) break;
+    if ((st = hip_check(h, hipEventSynchronize(e1), "hipEventSynchronize")) != MLF_OK) break;
+    float ms = 0.f;
+    if ((st = hip_check(h, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != MLF_OK) break;
+    if (ms < best) {
+      best = ms;
+      bw = c.first;
+      bh = c.second;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  h->block_w = (st == MLF_OK) ? bw : keep_w;
+  h->seg_h = (st == MLF_OK) ? bh : keep_h;
+  if (st != MLF_OK) return st;
+  if (block_w) *block_w = bw;
+  if (seg_h) *seg_h = bh;
   return MLF_OK;
 }
 

@@ -72,10 +72,10 @@ struct StepConsts {
   C dbar[kMaxLayers][kMaxLayers];  // reference gaps z_{l+k} - z_l, [l][k-1]
   C gamma[kMaxLayers];             // gamma_{i,i+1}
   C mu[kMaxLayers];
-  C spread[kMaxLayers][kMaxLayers];  // S_lk, [l][k-1]
-  C khs[kMaxLayers];                 // k h*, [k-1]
-  C ca, cb;                          // a/(a-b), b/(a-b)
-  C cab;                             // a b/(a-b)
+  C sa[kMaxLayers][kMaxLayers];   // S_lk a/(a-b), [l][k-1]
+  C sb[kMaxLayers][kMaxLayers];   // S_lk b/(a-b)
+  C sab[kMaxLayers][kMaxLayers];  // S_lk a b/(a-b)
+  C khs[kMaxLayers];              // k h*, [k-1]
   C omega;                           // 1/tau
   int ea, eb;                        // runtime exponents (generic path)
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
@@ -164,6 +164,17 @@ __host__ __device__ inline int wrap(int v, int n) {
   v = v >= n ? v - n : v;
   if (v < 0 || v >= n) v = ((v % n) + n) % n;  // only for n < 3
   return v;
+}
+
+// Strips of equal width wout <= W - 4 (the lanes cover two halo columns on
+// each side); recomputing the count from wout guarantees no empty strip.
+__host__ __device__ inline int strip_width(int nx, int W) {
+  const int n = (nx + (W - 4) - 1) / (W - 4);
+  return (nx + n - 1) / n;
+}
+__host__ __device__ inline int strip_count(int nx, int W) {
+  const int wo = strip_width(nx, W);
+  return (nx + wo - 1) / wo;
 }
 
 // Tile of workgroup b in a grid of gridDim.x (a multiple of kXcds)
@@ -289,9 +300,10 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
         qy0[i] = qy;
         dz += dh;
         zr[(zs * NL + i) * W + tid] = dz;
-        C h = kc.hbar[i] + dh;
+        const C h = kc.hbar[i] + dh;
+        const C chk = h + qx + qy;  // NaN if any of them is NaN or infinite
         if (!(h > C(0))) bad = 1;
-        if (!(h - h == C(0)) || !(qx - qx == C(0)) || !(qy - qy == C(0))) bad = 2;
+        if (!(chk - chk == C(0))) bad = 2;
       }
       if (act1 && bad) kc.flag[0] = bad;
     }
@@ -335,9 +347,9 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
           const C rr = kc.khs[kk - 1] * rd;
           C ra, rb;
           pow_ab<EA, EB>(rr, kc, ra, rb);
-          const C s = kc.spread[l][kk - 1];
-          const C phi = s * (kc.ca * rb - kc.cb * ra);
-          const C dphi = s * kc.cab * (ra - rb) * rd;
+          // phi = S (a r^b - b r^a)/(a-b), phi' = S a b (r^a - r^b)/((a-b) d)
+          const C phi = kc.sa[l][kk - 1] * rb - kc.sb[l][kk - 1] * ra;
+          const C dphi = kc.sab[l][kk - 1] * (ra - rb) * rd;
           sphi[l] += phi;
           dup[l] += dphi;
           ddn[l + kk] += dphi * (C(1) + C(0.5) * qq[l]);
@@ -415,36 +427,43 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
         const C qx = qx2[i], qy = qy2[i];
         const C qu = qx * ux[i] + qy * uy[i];
         const C t15 = C(1.5) * qu;
-        // equilibrium (rest population as deviation from hbar) and forcing
-        C feq[kQ], frc[kQ];
-        feq[0] = dh2[i] - C(2.0 / 3.0) * qu;
-        frc[0] = C(0);
-        const C ax = C(4.5) * qx * ux[i], ay = C(4.5) * qy * uy[i];
-        feq[1] = C(1.0 / 9.0) * (C(3) * qx + ax - t15);
-        feq[5] = C(1.0 / 9.0) * (-C(3) * qx + ax - t15);
-        feq[3] = C(1.0 / 9.0) * (C(3) * qy + ay - t15);
-        feq[7] = C(1.0 / 9.0) * (-C(3) * qy + ay - t15);
+        // Shallow-water equilibrium with the rest population as deviation
+        // from hbar, split into its even part (quadratic in U, shared by
+        // opposite directions) and odd part c.q/c_s^2 w_k; the forcing
+        // 3 w_k c_k.F is odd too.  With q_k = c_k.q and u_k = c_k.U:
+        //   f^eq_k = w_k (3 q_k + 4.5 q_k u_k - 1.5 q.U),  k >= 1.
+        const C ex = C(1.0 / 9.0) * (C(4.5) * qx * ux[i] - t15);  // axial x, even
+        const C ey = C(1.0 / 9.0) * (C(4.5) * qy * uy[i] - t15);  // axial y, even
         const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
-        const C dpp = C(4.5) * spq * spu, dmm = C(4.5) * smq * smu;
-        feq[2] = C(1.0 / 36.0) * (C(3) * spq + dpp - t15);
-        feq[6] = C(1.0 / 36.0) * (-C(3) * spq + dpp - t15);
-        feq[4] = C(1.0 / 36.0) * (C(3) * smq + dmm - t15);
-        feq[8] = C(1.0 / 36.0) * (-C(3) * smq + dmm - t15);
-        frc[1] = C(1.0 / 3.0) * Fx;
-        frc[5] = -frc[1];
-        frc[3] = C(1.0 / 3.0) * Fy;
-        frc[7] = -frc[3];
-        frc[2] = C(1.0 / 12.0) * (Fx + Fy);
-        frc[6] = -frc[2];
-        frc[4] = C(1.0 / 12.0) * (Fy - Fx);
-        frc[8] = -frc[4];
+        const C ep = C(1.0 / 36.0) * (C(4.5) * spq * spu - t15);  // diagonal (1,1), even
+        const C em = C(1.0 / 36.0) * (C(4.5) * smq * smu - t15);  // diagonal (-1,1), even
+        C ox, oy;                                                  // axial odd parts
         if constexpr (TAU1) {
-#pragma unroll
-          for (int k = 0; k < kQ; ++k) fo[i][k] = feq[k] + frc[k];
+          ox = C(1.0 / 3.0) * (qx + Fx);
+          oy = C(1.0 / 3.0) * (qy + Fy);
+          fo[i][0] = dh2[i] - C(2.0 / 3.0) * qu;
         } else {
-#pragma unroll
-          for (int k = 0; k < kQ; ++k) fo[i][k] = kc.omega * feq[k] + frc[k];
+          const C w = kc.omega;
+          ox = C(1.0 / 3.0) * (w * qx + Fx);
+          oy = C(1.0 / 3.0) * (w * qy + Fy);
+          fo[i][0] = w * (dh2[i] - C(2.0 / 3.0) * qu);
         }
+        const C op = C(0.25) * (ox + oy), om = C(0.25) * (oy - ox);  // diagonal odd parts
+        C gx = ex, gy = ey, gp = ep, gm = em;
+        if constexpr (!TAU1) {
+          gx = kc.omega * ex;
+          gy = kc.omega * ey;
+          gp = kc.omega * ep;
+          gm = kc.omega * em;
+        }
+        fo[i][1] = gx + ox;
+        fo[i][5] = gx - ox;
+        fo[i][3] = gy + oy;
+        fo[i][7] = gy - oy;
+        fo[i][2] = gp + op;
+        fo[i][6] = gp - op;
+        fo[i][4] = gm + om;
+        fo[i][8] = gm - om;
       }
     } else {
 #pragma unroll

@@ -71,6 +71,7 @@ def load_library():
         "mlf_load": (st, [H, C.c_void_p, C.c_size_t]),
         "mlf_set_launch": (st, [H, C.c_int32, C.c_int32]),
         "mlf_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mlf_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_steps_done": (C.c_int64, [H]),
         "mlf_last_error": (C.c_char_p, [H]),
         "mlf_destroy": (st, [H]),
@@ -275,6 +276,12 @@ class Film:
 
     def set_launch(self, block_w=0, seg_h=0):
         self._check(self.lib.mlf_set_launch(self.h, int(block_w), int(seg_h)), "mlf_set_launch")
+
+    def autotune(self, reps=5):
+        """Pick the fastest launch shape on the current state (unchanged)."""
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.mlf_autotune(self.h, int(reps), C.byref(a), C.byref(b)), "mlf_autotune")
+        return a.value, b.value
 
     def get_launch(self):
         a, b = C.c_int32(), C.c_int32()

@@ -312,3 +312,26 @@ def test_guard_trips_on_nonpositive_height(mlf):
     with pytest.raises(mlf.MlfError) as e:
         g.step(3)
     assert e.value.status == "ENONPOSITIVE"
+
+
+def test_autotune_keeps_state(mlf):
+    """The autotuner launches current -> other buffer without swapping: the
+    state, step counter and later results are unchanged."""
+    film = small_film(3, 200, 90, seed=30)
+    h0 = noisy(3, 200, 90, seed=31)
+    for prec in ("f64", "f32"):
+        a = mlf.Film(film, prec)
+        a.init(h0)
+        a.step(5)
+        f0 = a.populations()
+        bw, sh = a.autotune(reps=2)
+        say(f"   autotune {prec}: {bw}x{sh}")
+        assert bw in (64, 128, 192, 256) and 1 <= sh <= 90
+        assert a.get_launch() == (bw, sh)
+        assert a.steps_done == 5
+        assert np.array_equal(a.populations(), f0)
+        a.step(10)
+        b = mlf.Film(film, prec)
+        b.init(h0)
+        b.step(15)
+        assert np.array_equal(a.populations(), b.populations())
