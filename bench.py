@@ -101,7 +101,7 @@ def main():
     film, h0, spec = inputs.workload(args.workload)
     prec = args.precision or spec["precision"]
     n_lu = film["n_layers"] * film["nx"] * film["ny"]
-    bytes_per_lu = 18 * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16dev": 2, "bf16dev": 2}[prec]
+    bytes_per_lu = mlfilm.bytes_per_update(prec)
 
     if args.copy_probe:
         nbytes = n_lu * bytes_per_lu // 2

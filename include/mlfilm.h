@@ -30,7 +30,8 @@
  *    is the default stream).  mlf_step is asynchronous except for the guard
  *    polls; every call that returns host data synchronises the stream.
  *  - Fields are [N][ny][nx] row-major (x fastest).  Populations are stored
- *    structure-of-arrays, plane (i, k) of ny rows of `pitch` elements.
+ *    structure-of-arrays: per layer the rest plane, then the eight moving
+ *    planes, each of ny rows of `pitch` elements of that plane's type.
  *  - A handle is not thread-safe.
  */
 #ifndef MLFILM_H
@@ -59,12 +60,19 @@ typedef enum {
 /* Storage of the populations.  Arithmetic is FP64 for MLF_F64 and FP32
  * otherwise.  All formats store the rest population as a deviation from the
  * rest-state equilibrium h_ref_i (f_0 - h_ref_i), the moving ones as they
- * are; h_ref_i is the per-layer mean of the initial heights. */
+ * are; h_ref_i is the per-layer mean of the initial heights.  IEEE half
+ * values are scaled by a per-layer power of two near 2^12 / h_ref_i.
+ * In the all-16-bit formats a height change per step below half an ulp of
+ * the stored deviation is lost (slow dynamics stall); the MIX formats keep
+ * the rest population, which carries the height, in FP32 (40 instead of 36
+ * bytes per layer-node update). */
 typedef enum {
   MLF_F64 = 0,
   MLF_F32 = 1,
-  MLF_F16 = 2,  /* IEEE half storage of deviations, FP32 arithmetic */
-  MLF_BF16 = 3  /* bfloat16 storage of deviations, FP32 arithmetic  */
+  MLF_F16 = 2,      /* IEEE half storage of deviations, FP32 arithmetic          */
+  MLF_BF16 = 3,     /* bfloat16 storage of deviations, FP32 arithmetic           */
+  MLF_F16_MIX = 4,  /* FP32 rest population, IEEE half moving ones, FP32 arith.  */
+  MLF_BF16_MIX = 5  /* FP32 rest population, bfloat16 moving ones, FP32 arith.   */
 } mlf_precision;
 
 typedef struct mlf_params {

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "step_kernel.hpp"
@@ -31,12 +32,37 @@ constexpr int kPitchAlign = 64;  // elements
 // node x at column x - kCx[k] (see step_kernel.hpp)
 constexpr int kCx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
 
-size_t elem_size(int precision) {
+// Element format of a population plane.
+enum Fmt { kFmtF64, kFmtF32, kFmtF16, kFmtBF16 };
+
+// Format of the rest plane and of the eight moving planes.
+Fmt rest_fmt(int precision) {
   switch (precision) {
-    case MLF_F64: return 8;
-    case MLF_F32: return 4;
-    default: return 2;
+    case MLF_F64: return kFmtF64;
+    case MLF_F16: return kFmtF16;
+    case MLF_BF16: return kFmtBF16;
+    default: return kFmtF32;  // F32 and both MIX formats
   }
+}
+Fmt move_fmt(int precision) {
+  switch (precision) {
+    case MLF_F64: return kFmtF64;
+    case MLF_F32: return kFmtF32;
+    case MLF_F16:
+    case MLF_F16_MIX: return kFmtF16;
+    default: return kFmtBF16;
+  }
+}
+size_t fmt_size(Fmt f) { return f == kFmtF64 ? 8 : (f == kFmtF32 ? 4 : 2); }
+bool fmt_scaled(Fmt f) { return f == kFmtF16 || f == kFmtBF16; }
+
+// Bytes of one layer (rest plane, then eight moving planes) and the byte
+// offset of plane k inside it; `plane` is in elements.
+size_t layer_bytes(int precision, size_t plane) {
+  return plane * (fmt_size(rest_fmt(precision)) + (kQ - 1) * fmt_size(move_fmt(precision)));
+}
+size_t plane_offset(int precision, size_t plane, int k) {
+  return k == 0 ? 0 : plane * (fmt_size(rest_fmt(precision)) + (size_t)(k - 1) * fmt_size(move_fmt(precision)));
 }
 
 int pitch_of(const mlf_params* p) { return (p->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
@@ -55,7 +81,7 @@ mlf_status validate(const mlf_params* p, std::string* why) {
   if (!p) return bad("null parameters");
   if (p->n_layers < 1 || p->n_layers > MLF_MAX_LAYERS) return bad("n_layers must be 1..4");
   if (p->nx < 1 || p->ny < 1) return bad("nx, ny must be >= 1");
-  if (p->precision < MLF_F64 || p->precision > MLF_BF16) return bad("unknown precision");
+  if (p->precision < MLF_F64 || p->precision > MLF_BF16_MIX) return bad("unknown precision");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return bad("tau must be > 0.5");
   if (!(p->hstar > 0.0) || !std::isfinite(p->hstar)) return bad("hstar must be > 0");
   if (!(p->exp_a > p->exp_b && p->exp_b >= 1) || p->exp_a > 64) return bad("need 64 >= exp_a > exp_b >= 1");
@@ -70,7 +96,7 @@ mlf_status validate(const mlf_params* p, std::string* why) {
   if (plane * kQ * (size_t)p->n_layers > (size_t)1 << 40) return bad("grid too large");
   // the step kernel addresses one layer (nine planes) through a buffer
   // descriptor with 32-bit offsets and masks lanes with offset 2^31
-  if (plane * kQ * elem_size(p->precision) > (size_t)0x80000000u) {
+  if (layer_bytes(p->precision, plane) > (size_t)0x80000000u) {
     if (why) *why = "one layer of populations exceeds 2 GiB";
     return MLF_EUNSUPPORTED;
   }
@@ -79,10 +105,6 @@ mlf_status validate(const mlf_params* p, std::string* why) {
       if (why) *why = "slip lengths other than 0 are not supported";
       return MLF_EUNSUPPORTED;
     }
-  if (p->precision == MLF_F16 || p->precision == MLF_BF16) {
-    if (why) *why = "16-bit storage is not available in this build";
-    return MLF_EUNSUPPORTED;
-  }
   return MLF_OK;
 }
 
@@ -157,13 +179,56 @@ struct BlobHeader {
 };
 
 // ---------------------------------------------------------------- kernels --
+// Per-layer constants of the auxiliary kernels: reference heights and the
+// storage scale of the 16-bit planes (they store scaled deviations).
+struct Layers {
+  double hb[kMaxLayers];
+  double sc[kMaxLayers];
+};
+
+template <typename T>
+constexpr bool kIs16 = sizeof(T) == 2;
+
+template <typename S>
+__device__ inline S to_store(double v) {
+  return S((float)v);
+}
+template <>
+__device__ inline double to_store<double>(double v) {
+  return v;
+}
+
+// Populations of all layers: per layer the rest plane (type R), then the
+// eight moving planes (type S), each of `plane` elements.
+template <typename R, typename S>
+struct PopView {
+  unsigned char* base;
+  long long plane;
+  __device__ long long layer_bytes() const { return plane * (long long)(sizeof(R) + (kQ - 1) * sizeof(S)); }
+  // unscaled value of element e of plane (i, k)
+  __device__ double ld(int i, int k, long long e, const Layers& L) const {
+    const unsigned char* l = base + i * layer_bytes();
+    if (k == 0) return double(reinterpret_cast<const R*>(l)[e]) / (kIs16<R> ? L.sc[i] : 1.0);
+    const S* m = reinterpret_cast<const S*>(l + plane * (long long)sizeof(R));
+    return double(m[(long long)(k - 1) * plane + e]) / (kIs16<S> ? L.sc[i] : 1.0);
+  }
+  __device__ void st(int i, int k, long long e, double v, const Layers& L) const {
+    unsigned char* l = base + i * layer_bytes();
+    if (k == 0) {
+      reinterpret_cast<R*>(l)[e] = to_store<R>(v * (kIs16<R> ? L.sc[i] : 1.0));
+      return;
+    }
+    S* m = reinterpret_cast<S*>(l + plane * (long long)sizeof(R));
+    m[(long long)(k - 1) * plane + e] = to_store<S>(v * (kIs16<S> ? L.sc[i] : 1.0));
+  }
+};
+
 // Populations at equilibrium f^eq(h, U) (Eq. equilibrium_distribution), rest
 // population stored as deviation from hbar, for rows [ya, yb).
-template <typename S>
-__global__ void init_kernel(S* __restrict__ f, const double* __restrict__ hs, const double* __restrict__ uxs,
+template <typename R, typename S>
+__global__ void init_kernel(PopView<R, S> f, const double* __restrict__ hs, const double* __restrict__ uxs,
                             const double* __restrict__ uys, long long lstride, int yoff, int ya, int yb, int nx,
-                            int pitch, long long plane, int nl, double h0, double h1, double h2, double h3) {
-  const double hb[4] = {h0, h1, h2, h3};
+                            int pitch, int nl, Layers L) {
   long long n = (long long)(yb - ya) * nx;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n * nl;
        t += (long long)gridDim.x * blockDim.x) {
@@ -177,35 +242,34 @@ __global__ void init_kernel(S* __restrict__ f, const double* __restrict__ hs, co
     const int cy[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
     // plane k keeps at column x - c_kx the population of node x
-    S* o = f + (long long)(i * 9) * plane + (long long)y * pitch;
-    o[x] = S((h - hb[i]) - h * (2.0 / 3.0) * uu);
+    const long long row = (long long)y * pitch;
+    f.st(i, 0, row + x, (h - L.hb[i]) - h * (2.0 / 3.0) * uu, L);
     for (int k = 1; k < 9; ++k) {
       const double cu = cx[k] * ux + cy[k] * uy;
-      o[(long long)k * plane + mlf::wrap(x - cx[k], nx)] = S(w[k] * h * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+      f.st(i, k, row + mlf::wrap(x - cx[k], nx), w[k] * h * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu), L);
     }
   }
 }
 
 // h = hbar + sum_k f_k, U = q / h in FP64 for rows [ya, yb).
-template <typename S>
-__global__ void read_kernel(const S* __restrict__ f, double* __restrict__ ho, double* __restrict__ uxo,
+template <typename R, typename S>
+__global__ void read_kernel(PopView<R, S> f, double* __restrict__ ho, double* __restrict__ uxo,
                             double* __restrict__ uyo, long long lstride, int yoff, int ya, int yb, int nx,
-                            int pitch, long long plane, int nl, double h0, double h1, double h2, double h3) {
-  const double hb[4] = {h0, h1, h2, h3};
+                            int pitch, int nl, Layers L) {
   long long n = (long long)(yb - ya) * nx;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n * nl;
        t += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(t / n);
     const long long rem = t % n;
     const int y = ya + (int)(rem / nx), x = (int)(rem % nx);
-    const S* b = f + (long long)(i * 9) * plane + (long long)y * pitch;
+    const long long row = (long long)y * pitch;
     const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
     double v[9];
-    for (int k = 0; k < 9; ++k) v[k] = double(b[(long long)k * plane + mlf::wrap(x - cx[k], nx)]);
+    for (int k = 0; k < 9; ++k) v[k] = f.ld(i, k, row + mlf::wrap(x - cx[k], nx), L);
     const double dh = v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7] + v[8];
     const double qx = (v[1] + v[2] + v[8]) - (v[4] + v[5] + v[6]);
     const double qy = (v[2] + v[3] + v[4]) - (v[6] + v[7] + v[8]);
-    const double h = hb[i] + dh;
+    const double h = L.hb[i] + dh;
     const long long di = i * lstride + (long long)(y - yoff) * nx + x;
     if (ho) ho[di] = h;
     if (uxo) uxo[di] = qx / h;
@@ -213,19 +277,19 @@ __global__ void read_kernel(const S* __restrict__ f, double* __restrict__ ho, do
   }
 }
 
-// Block sums of sum_k f_ki (FP64) per layer: partials[blockIdx.x][i].
-template <typename S>
-__global__ void __launch_bounds__(256) mass_partials(const S* __restrict__ f, double* __restrict__ part, int nx,
-                                                     int ny, int pitch, long long plane, int nl) {
+// Block sums of sum_k f_ki (FP64, unscaled) per layer: partials[blockIdx.x][i].
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) mass_partials(PopView<R, S> f, double* __restrict__ part, int nx,
+                                                     int ny, int pitch, int nl, Layers L) {
   __shared__ double red[256 / 64][kMaxLayers];
   double acc[kMaxLayers] = {0, 0, 0, 0};
   const long long n = (long long)nx * ny;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
     const int y = (int)(t / nx), x = (int)(t % nx);
     for (int i = 0; i < nl; ++i) {
-      const S* b = f + (long long)(i * 9) * plane + (long long)y * pitch + x;
+      const long long e = (long long)y * pitch + x;
       double s = 0.0;
-      for (int k = 0; k < 9; ++k) s += double(b[(long long)k * plane]);
+      for (int k = 0; k < 9; ++k) s += f.ld(i, k, e, L);  // power-of-two scales: exact
       acc[i] += s;
     }
   }
@@ -287,6 +351,7 @@ struct mlf_handle {
   size_t plane;
   size_t pop_bytes;
   double hbar[kMaxLayers];
+  double scale[kMaxLayers];  // storage scale per layer (1 except IEEE half)
   int64_t steps;
   int block_w, seg_h;
   bool initialised;
@@ -294,6 +359,87 @@ struct mlf_handle {
 };
 
 namespace {
+
+// IEEE-half storage keeps the population deviations scaled by a power of two
+// near 2^12 / hbar: values of order 1e-8 .. 1e-3 then stay in the normal
+// range and deviations up to 16 hbar remain finite.  Other formats: 1.
+double storage_scale(int precision, double hbar) {
+  if (move_fmt(precision) != kFmtF16) return 1.0;
+  int e = (int)std::floor(std::log2(4096.0 / std::max(hbar, 1e-30)));
+  e = std::max(-30, std::min(30, e));
+  return std::ldexp(1.0, e);
+}
+
+void set_scales(mlf_handle* h) {
+  for (int i = 0; i < kMaxLayers; ++i)
+    h->scale[i] = i < h->p.n_layers ? storage_scale(h->p.precision, h->hbar[i]) : 1.0;
+}
+
+// Host-side conversion of one stored element (population read/write);
+// `raw` points at the element.
+double host_load(Fmt fmt, const unsigned char* raw) {
+  switch (fmt) {
+    case kFmtF64: {
+      double d;
+      std::memcpy(&d, raw, 8);
+      return d;
+    }
+    case kFmtF32: {
+      float f;
+      std::memcpy(&f, raw, 4);
+      return f;
+    }
+    case kFmtF16: {
+      _Float16 f;
+      std::memcpy(&f, raw, 2);
+      return (double)f;
+    }
+    default: {
+      uint16_t u;
+      std::memcpy(&u, raw, 2);
+      uint32_t b = (uint32_t)u << 16;
+      float f;
+      std::memcpy(&f, &b, 4);
+      return f;
+    }
+  }
+}
+
+void host_store(Fmt fmt, unsigned char* raw, double v) {
+  switch (fmt) {
+    case kFmtF64: std::memcpy(raw, &v, 8); break;
+    case kFmtF32: {
+      float f = (float)v;
+      std::memcpy(raw, &f, 4);
+      break;
+    }
+    case kFmtF16: {
+      _Float16 f = (_Float16)v;
+      std::memcpy(raw, &f, 2);
+      break;
+    }
+    default: {
+      float f = (float)v;
+      uint32_t b;
+      std::memcpy(&b, &f, 4);
+      if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x7fffffu))
+        b = 0x7fc00000u;  // NaN stays NaN
+      else
+        b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest even
+      const uint16_t u = (uint16_t)(b >> 16);
+      std::memcpy(raw, &u, 2);
+    }
+  }
+}
+
+Layers layers_of(const mlf_handle* h) {
+  Layers L;
+  for (int i = 0; i < kMaxLayers; ++i) {
+    L.hb[i] = h->hbar[i];
+    L.sc[i] = h->scale[i];
+  }
+  return L;
+}
 
 mlf_status fail(mlf_handle* h, mlf_status st, const std::string& m) {
   if (h) h->err = m;
@@ -356,6 +502,10 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
     }
   for (int kk = 1; kk <= kMaxLayers; ++kk) k.khs[kk - 1] = C(kk * p.hstar);
   k.omega = C(1.0 / p.tau);
+  for (int i = 0; i < kMaxLayers; ++i) {
+    k.scale[i] = C(h->scale[i]);
+    k.iscale[i] = C(1.0 / h->scale[i]);
+  }
   k.ea = p.exp_a;
   k.eb = p.exp_b;
   k.flag = flag_ptr(const_cast<mlf_handle*>(h));
@@ -364,17 +514,17 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
 
 // Workgroups of the step kernel that fit on one CU at the handle's block
 // width (0 if unknown).
-template <typename S, typename C, int NL, bool T1, int EA, int EB>
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
 int occupancy_nl(const mlf_handle* h) {
   int nb = 0;
   size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mlf::step_kernel<S, C, NL, T1, EA, EB>, h->block_w, lds) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mlf::step_kernel<R, S, C, NL, T1, EA, EB>, h->block_w,
+                                                   lds) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename S, typename C, int NL, bool T1, int EA, int EB>
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
 hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
   mlf::StepConsts<C> kc = make_consts<C>(h);
   // grid padded to a multiple of the XCD count (tile_of_block)
@@ -382,52 +532,74 @@ hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
   const int nblocks = (ntiles + mlf::kXcds - 1) / mlf::kXcds * mlf::kXcds;
   dim3 grid((unsigned)nblocks), block((unsigned)h->block_w);
   size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
-  hipLaunchKernelGGL((mlf::step_kernel<S, C, NL, T1, EA, EB>), grid, block, lds, h->stream,
-                     static_cast<const S*>(src), static_cast<S*>(dst), kc);
+  hipLaunchKernelGGL((mlf::step_kernel<R, S, C, NL, T1, EA, EB>), grid, block, lds, h->stream,
+                     static_cast<const unsigned char*>(src), static_cast<unsigned char*>(dst), kc);
   return hipGetLastError();
 }
 
 // Dispatch on (layers, tau == 1, exponents == (9, 3)); OCC selects the
 // occupancy query instead of a launch.
-template <typename S, typename C, bool T1, int EA, int EB>
+template <typename R, typename S, typename C, bool T1, int EA, int EB>
 hipError_t launch_t(const mlf_handle* h, const void* src, void* dst, int* occ) {
   switch (h->p.n_layers) {
     case 1:
-      if (occ) return *occ = occupancy_nl<S, C, 1, T1, EA, EB>(h), hipSuccess;
-      return launch_nl<S, C, 1, T1, EA, EB>(h, src, dst);
+      if (occ) return *occ = occupancy_nl<R, S, C, 1, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<R, S, C, 1, T1, EA, EB>(h, src, dst);
     case 2:
-      if (occ) return *occ = occupancy_nl<S, C, 2, T1, EA, EB>(h), hipSuccess;
-      return launch_nl<S, C, 2, T1, EA, EB>(h, src, dst);
+      if (occ) return *occ = occupancy_nl<R, S, C, 2, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<R, S, C, 2, T1, EA, EB>(h, src, dst);
     case 3:
-      if (occ) return *occ = occupancy_nl<S, C, 3, T1, EA, EB>(h), hipSuccess;
-      return launch_nl<S, C, 3, T1, EA, EB>(h, src, dst);
+      if (occ) return *occ = occupancy_nl<R, S, C, 3, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<R, S, C, 3, T1, EA, EB>(h, src, dst);
     default:
-      if (occ) return *occ = occupancy_nl<S, C, 4, T1, EA, EB>(h), hipSuccess;
-      return launch_nl<S, C, 4, T1, EA, EB>(h, src, dst);
+      if (occ) return *occ = occupancy_nl<R, S, C, 4, T1, EA, EB>(h), hipSuccess;
+      return launch_nl<R, S, C, 4, T1, EA, EB>(h, src, dst);
   }
 }
 
-template <typename S, typename C>
+template <typename R, typename S, typename C>
 hipError_t launch_sc(const mlf_handle* h, const void* src, void* dst, int* occ) {
   const bool t1 = h->p.tau == 1.0;
   const bool e93 = h->p.exp_a == 9 && h->p.exp_b == 3;
-  if (t1 && e93) return launch_t<S, C, true, 9, 3>(h, src, dst, occ);
-  if (t1) return launch_t<S, C, true, 0, 0>(h, src, dst, occ);
-  if (e93) return launch_t<S, C, false, 9, 3>(h, src, dst, occ);
-  return launch_t<S, C, false, 0, 0>(h, src, dst, occ);
+  if (t1 && e93) return launch_t<R, S, C, true, 9, 3>(h, src, dst, occ);
+  if (t1) return launch_t<R, S, C, true, 0, 0>(h, src, dst, occ);
+  if (e93) return launch_t<R, S, C, false, 9, 3>(h, src, dst, occ);
+  return launch_t<R, S, C, false, 0, 0>(h, src, dst, occ);
+}
+
+// Calls f with typed null pointers of the handle's rest-plane and
+// moving-plane storage types.
+template <typename F>
+void by_storage(const mlf_handle* h, F&& f) {
+  switch (h->p.precision) {
+    case MLF_F64: f((double*)nullptr, (double*)nullptr); break;
+    case MLF_F32: f((float*)nullptr, (float*)nullptr); break;
+    case MLF_F16: f((_Float16*)nullptr, (_Float16*)nullptr); break;
+    case MLF_BF16: f((__bf16*)nullptr, (__bf16*)nullptr); break;
+    case MLF_F16_MIX: f((float*)nullptr, (_Float16*)nullptr); break;
+    default: f((float*)nullptr, (__bf16*)nullptr); break;
+  }
 }
 
 hipError_t launch_step(const mlf_handle* h, const void* src, void* dst) {
-  if (h->p.precision == MLF_F64) return launch_sc<double, double>(h, src, dst, nullptr);
-  return launch_sc<float, float>(h, src, dst, nullptr);
+  hipError_t e = hipSuccess;
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    using C = std::conditional_t<std::is_same_v<S, double>, double, float>;
+    e = launch_sc<R, S, C>(h, src, dst, nullptr);
+  });
+  return e;
 }
 
 int step_occupancy(const mlf_handle* h) {
   int occ = 0;
-  if (h->p.precision == MLF_F64)
-    launch_sc<double, double>(h, nullptr, nullptr, &occ);
-  else
-    launch_sc<float, float>(h, nullptr, nullptr, &occ);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    using C = std::conditional_t<std::is_same_v<S, double>, double, float>;
+    launch_sc<R, S, C>(h, nullptr, nullptr, &occ);
+  });
   return occ;
 }
 
@@ -440,14 +612,14 @@ mlf_status launch_init(mlf_handle* h, const double* hs, const double* uxs, const
                        int yoff, int ya, int yb) {
   const mlf_params& p = h->p;
   const long long n = (long long)(yb - ya) * p.nx * p.n_layers;
-  if (p.precision == MLF_F64)
-    hipLaunchKernelGGL(init_kernel<double>, dim3(grid_for(n)), dim3(256), 0, h->stream,
-                       static_cast<double*>(h->pop[h->cur]), hs, uxs, uys, lstride, yoff, ya, yb, p.nx, h->pitch,
-                       (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
-  else
-    hipLaunchKernelGGL(init_kernel<float>, dim3(grid_for(n)), dim3(256), 0, h->stream,
-                       static_cast<float*>(h->pop[h->cur]), hs, uxs, uys, lstride, yoff, ya, yb, p.nx, h->pitch,
-                       (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  const Layers L = layers_of(h);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    hipLaunchKernelGGL((init_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, hs, uxs, uys, lstride,
+                       yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
+  });
   HIPCHK(hipGetLastError());
   return MLF_OK;
 }
@@ -456,14 +628,14 @@ mlf_status launch_read(mlf_handle* h, double* ho, double* uxo, double* uyo, long
                        int yb) {
   const mlf_params& p = h->p;
   const long long n = (long long)(yb - ya) * p.nx * p.n_layers;
-  if (p.precision == MLF_F64)
-    hipLaunchKernelGGL(read_kernel<double>, dim3(grid_for(n)), dim3(256), 0, h->stream,
-                       static_cast<const double*>(h->pop[h->cur]), ho, uxo, uyo, lstride, yoff, ya, yb, p.nx,
-                       h->pitch, (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
-  else
-    hipLaunchKernelGGL(read_kernel<float>, dim3(grid_for(n)), dim3(256), 0, h->stream,
-                       static_cast<const float*>(h->pop[h->cur]), ho, uxo, uyo, lstride, yoff, ya, yb, p.nx,
-                       h->pitch, (long long)h->plane, p.n_layers, h->hbar[0], h->hbar[1], h->hbar[2], h->hbar[3]);
+  const Layers L = layers_of(h);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    hipLaunchKernelGGL((read_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, ho, uxo, uyo, lstride,
+                       yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
+  });
   HIPCHK(hipGetLastError());
   return MLF_OK;
 }
@@ -532,7 +704,7 @@ const char* mlf_version(void) { return "mlfilm 0.1 gfx950"; }
 mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes) {
   mlf_status st = validate(p, nullptr);
   if (st != MLF_OK) return st;
-  if (pop_bytes) *pop_bytes = (size_t)pitch_of(p) * p->ny * kQ * p->n_layers * elem_size(p->precision);
+  if (pop_bytes) *pop_bytes = layer_bytes(p->precision, (size_t)pitch_of(p) * p->ny) * p->n_layers;
   if (scratch_bytes) *scratch_bytes = kScratchBytes;
   return MLF_OK;
 }
@@ -564,8 +736,8 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   h->stream = static_cast<hipStream_t>(stream);
   h->pitch = pitch_of(p);
   h->plane = (size_t)h->pitch * p->ny;
-  h->pop_bytes = h->plane * kQ * p->n_layers * elem_size(p->precision);
-  for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0;
+  h->pop_bytes = layer_bytes(p->precision, h->plane) * p->n_layers;
+  for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0, h->scale[i] = 1.0;
   h->steps = 0;
   h->initialised = false;
   default_launch(p, &h->block_w, &h->seg_h);
@@ -683,6 +855,7 @@ mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const do
     }
     h->hbar[i] = s / (double)nn;
   }
+  set_scales(h);
   mlf_status chk = check_stability(h);
   if (chk != MLF_OK) return chk;
   const int rows = rows_per_chunk(h, 3);
@@ -731,6 +904,7 @@ mlf_status mlf_init_device(mlf_handle* h, const double* hgt, const double* ux, c
     if (!std::isfinite(h->hbar[i])) return fail(h, MLF_ENONFINITE, "initial field is not finite");
     if (!(h->hbar[i] > 0.0)) return fail(h, MLF_ENONPOSITIVE, "initial height <= 0");
   }
+  set_scales(h);
   mlf_status s = check_stability(h);
   if (s != MLF_OK) return s;
   s = zero_buffers(h);
@@ -804,14 +978,14 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
   if (!h || !mass) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "mass before init");
   const mlf_params& p = h->p;
-  if (p.precision == MLF_F64)
-    hipLaunchKernelGGL(mass_partials<double>, dim3(kRedBlocks), dim3(256), 0, h->stream,
-                       static_cast<const double*>(h->pop[h->cur]), part_ptr(h), p.nx, p.ny, h->pitch,
-                       (long long)h->plane, p.n_layers);
-  else
-    hipLaunchKernelGGL(mass_partials<float>, dim3(kRedBlocks), dim3(256), 0, h->stream,
-                       static_cast<const float*>(h->pop[h->cur]), part_ptr(h), p.nx, p.ny, h->pitch,
-                       (long long)h->plane, p.n_layers);
+  const Layers L = layers_of(h);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    hipLaunchKernelGGL((mass_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part_ptr(h), p.nx, p.ny,
+                       h->pitch, p.n_layers, L);
+  });
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
                      p.n_layers);
@@ -835,9 +1009,11 @@ mlf_status mlf_read_populations(mlf_handle* h, double* f) {
     for (int k = 0; k < kQ; ++k)
       for (int y = 0; y < p.ny; ++y)
         for (int x = 0; x < p.nx; ++x) {
-          const size_t si = ((size_t)(i * kQ + k)) * h->plane + (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
-          double v = p.precision == MLF_F64 ? reinterpret_cast<const double*>(raw.data())[si]
-                                            : (double)reinterpret_cast<const float*>(raw.data())[si];
+          const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
+          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          const size_t b = i * layer_bytes(p.precision, h->plane) + plane_offset(p.precision, h->plane, k) +
+                           e * fmt_size(fm);
+          double v = host_load(fm, raw.data() + b) / (fmt_scaled(fm) ? h->scale[i] : 1.0);
           if (k == 0) v += h->hbar[i];
           f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x] = v;
         }
@@ -853,13 +1029,13 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f) {
     for (int k = 0; k < kQ; ++k)
       for (int y = 0; y < p.ny; ++y)
         for (int x = 0; x < p.nx; ++x) {
-          const size_t si = ((size_t)(i * kQ + k)) * h->plane + (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
+          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          const size_t b = i * layer_bytes(p.precision, h->plane) + plane_offset(p.precision, h->plane, k) +
+                           e * fmt_size(fm);
           double v = f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x];
           if (k == 0) v -= h->hbar[i];
-          if (p.precision == MLF_F64)
-            reinterpret_cast<double*>(raw.data())[si] = v;
-          else
-            reinterpret_cast<float*>(raw.data())[si] = (float)v;
+          host_store(fm, raw.data() + b, v * (fmt_scaled(fm) ? h->scale[i] : 1.0));
         }
   HIPCHK(hipMemcpyAsync(h->pop[h->cur], raw.data(), h->pop_bytes, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -906,6 +1082,7 @@ mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes) {
       bytes < sizeof hd + hd.payload)
     return fail(h, MLF_EINVAL, "checkpoint does not match these parameters");
   for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = hd.hbar[i];
+  set_scales(h);
   mlf_status z = zero_buffers(h);
   if (z != MLF_OK) return z;
   HIPCHK(hipMemcpyAsync(h->pop[h->cur], static_cast<const unsigned char*>(blob) + sizeof hd, h->pop_bytes,

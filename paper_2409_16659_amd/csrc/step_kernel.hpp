@@ -29,6 +29,11 @@
 //    (and 16-bit) storage keeps the small height perturbations exact to
 //    storage precision; heights are hbar_i + dh_i and interface heights are
 //    handled as deviations dz_i from the reference stack.
+//  * The rest plane may have its own storage type R (FP32 rest with 16-bit
+//    moving populations): the rest population carries the height, whose
+//    per-step change is far below a 16-bit ulp of its deviation, while the
+//    moving ones are rebuilt from the moments every step.  A layer is the
+//    rest plane followed by the eight moving planes, addressed in bytes.
 //  * A workgroup owns a strip of columns and marches along a segment of rows
 //    (a sliding window).  Its lanes cover the strip plus two halo columns on
 //    each side (overlapped tiling): every lane loads and reduces one column,
@@ -77,6 +82,7 @@ struct StepConsts {
   C sab[kMaxLayers][kMaxLayers];  // S_lk a b/(a-b)
   C khs[kMaxLayers];              // k h*, [k-1]
   C omega;                           // 1/tau
+  C scale[kMaxLayers], iscale[kMaxLayers];  // storage scale per layer (16-bit formats)
   int ea, eb;                        // runtime exponents (generic path)
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
 };
@@ -97,23 +103,53 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <typename S>
-__device__ inline S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ inline float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
+// Element access by storage type.  16-bit formats hold the deviations of
+// the populations scaled by a per-layer power of two (IEEE half: keeps the
+// small populations out of the subnormal range; bfloat16: scale 1) and are
+// converted to/from FP32 with round-to-nearest-even.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename S>
+struct Elem;
 template <>
-__device__ inline double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
-}
-__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
-}
+struct Elem<double> {
+  static constexpr bool kScaled = false;
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  }
+};
+template <>
+struct Elem<float> {
+  static constexpr bool kScaled = false;
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+  }
+};
+template <>
+struct Elem<_Float16> {
+  static constexpr bool kScaled = true;
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)voff, (int)soff, 0);
+  }
+};
+template <>
+struct Elem<__bf16> {
+  static constexpr bool kScaled = true;
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, (int)voff, (int)soff, 0);
+  }
+};
 
 // Reciprocal: the hardware approximation (1 ulp) in FP32, a correctly
 // rounded division in FP64.
@@ -184,9 +220,9 @@ __device__ inline int tile_of_block(int b, int nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
-template <typename S, typename C, int NL, bool TAU1, int EA, int EB>
+template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
 __global__ void __launch_bounds__(256)
-step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> kc) {
+step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
   const int W = blockDim.x;
   const int tid = threadIdx.x;
   const int tile = tile_of_block(blockIdx.x, gridDim.x);
@@ -198,15 +234,19 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
   const int y0 = seg * kc.seg_h;
   const int y1 = min(y0 + kc.seg_h, kc.ny);
   const int dir = (seg & 1) ? -1 : 1;  // marching direction in y
-  const uint32_t rowb = (uint32_t)kc.pitch * (uint32_t)sizeof(S);  // bytes per row
-  const uint32_t planeb = (uint32_t)(kc.plane * (long long)sizeof(S));  // bytes per plane
-  const uint32_t layerb = planeb * (uint32_t)kQ;                          // bytes per layer
+  const uint32_t rowb = (uint32_t)kc.pitch * (uint32_t)sizeof(S);   // bytes per row, moving planes
+  const uint32_t rowbr = (uint32_t)kc.pitch * (uint32_t)sizeof(R);  // bytes per row, rest plane
+  const uint32_t planeb = (uint32_t)(kc.plane * (long long)sizeof(S));
+  const uint32_t planebr = (uint32_t)(kc.plane * (long long)sizeof(R));
+  const uint32_t layerb = planebr + planeb * (uint32_t)(kQ - 1);  // bytes per layer
+  // byte offset of plane k >= 1 in a layer
+  auto poff = [&](uint32_t k) { return planebr + (k - 1u) * planeb; };
   if (w <= 0 || y1 <= y0) return;  // uniform per workgroup; never taken with host geometry
   __amdgpu_buffer_rsrc_t rs[NL], rd[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    rs[i] = make_rsrc(src + (long long)i * kQ * kc.plane, layerb);
-    rd[i] = make_rsrc(dst + (long long)i * kQ * kc.plane, layerb);
+    rs[i] = make_rsrc(src + (long long)i * layerb, layerb);
+    rd[i] = make_rsrc(dst + (long long)i * layerb, layerb);
   }
 
   extern __shared__ unsigned char smem_raw[];
@@ -221,6 +261,7 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
   const uint32_t bx = (uint32_t)x * sizeof(S);
   const uint32_t bxm = (uint32_t)wrap(x - 1, kc.nx) * sizeof(S);
   const uint32_t bxp = (uint32_t)wrap(x + 1, kc.nx) * sizeof(S);
+  const uint32_t bxr = (uint32_t)x * sizeof(R);
 
   // register pipeline of moments: row of iteration it (0), it-1 (1), it-2 (2)
   C dh0[NL], qx0[NL], qy0[NL];
@@ -245,37 +286,49 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
   // column x - 1, directions 4, 5, 6 column x + 1.
   auto load_row = [&](int r, bool valid, C (&fn)[NL][kQ]) {
     const bool ok = act1 && valid;
-    const uint32_t row = (uint32_t)wrap(r, kc.ny) * rowb;
+    const uint32_t yr = (uint32_t)wrap(r, kc.ny);
+    const uint32_t row = yr * rowb;
     const uint32_t om = ok ? row + bxm : kMasked, o0 = ok ? row + bx : kMasked,
-                   op = ok ? row + bxp : kMasked;
+                   op = ok ? row + bxp : kMasked, orr = ok ? yr * rowbr + bxr : kMasked;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      fn[i][0] = C(bload<S>(rs[i], o0, 0u * planeb));
-      fn[i][1] = C(bload<S>(rs[i], om, 1u * planeb));
-      fn[i][2] = C(bload<S>(rs[i], om, 2u * planeb));
-      fn[i][3] = C(bload<S>(rs[i], o0, 3u * planeb));
-      fn[i][4] = C(bload<S>(rs[i], op, 4u * planeb));
-      fn[i][5] = C(bload<S>(rs[i], op, 5u * planeb));
-      fn[i][6] = C(bload<S>(rs[i], op, 6u * planeb));
-      fn[i][7] = C(bload<S>(rs[i], o0, 7u * planeb));
-      fn[i][8] = C(bload<S>(rs[i], om, 8u * planeb));
+      fn[i][0] = C(Elem<R>::ld(rs[i], orr, 0u));
+      fn[i][1] = C(Elem<S>::ld(rs[i], om, poff(1)));
+      fn[i][2] = C(Elem<S>::ld(rs[i], om, poff(2)));
+      fn[i][3] = C(Elem<S>::ld(rs[i], o0, poff(3)));
+      fn[i][4] = C(Elem<S>::ld(rs[i], op, poff(4)));
+      fn[i][5] = C(Elem<S>::ld(rs[i], op, poff(5)));
+      fn[i][6] = C(Elem<S>::ld(rs[i], op, poff(6)));
+      fn[i][7] = C(Elem<S>::ld(rs[i], o0, poff(7)));
+      fn[i][8] = C(Elem<S>::ld(rs[i], om, poff(8)));
+      if constexpr (Elem<R>::kScaled) fn[i][0] *= kc.iscale[i];
+      if constexpr (Elem<S>::kScaled) {
+#pragma unroll
+        for (int k = 1; k < kQ; ++k) fn[i][k] *= kc.iscale[i];
+      }
     }
   };
   // Post-collision f*_k(x, y) goes to S_k(x, y + c_ky): row offsets oS, oC, oN
-  // are for rows y - 1, y, y + 1 at this lane's column.
-  auto store_row = [&](bool ok, uint32_t oS, uint32_t oC, uint32_t oN, const C (&fo)[NL][kQ]) {
-    const uint32_t mS = ok ? oS : kMasked, mC = ok ? oC : kMasked, mN = ok ? oN : kMasked;
+  // are for rows y - 1, y, y + 1 at this lane's column (moving planes), oR
+  // for row y of the rest plane.
+  auto store_row = [&](bool ok, uint32_t oS, uint32_t oC, uint32_t oN, uint32_t oR, const C (&fo)[NL][kQ]) {
+    const uint32_t mS = ok ? oS : kMasked, mC = ok ? oC : kMasked, mN = ok ? oN : kMasked,
+                   mR = ok ? oR : kMasked;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      bstore(rd[i], mC, 0u * planeb, S(fo[i][0]));
-      bstore(rd[i], mC, 1u * planeb, S(fo[i][1]));
-      bstore(rd[i], mN, 2u * planeb, S(fo[i][2]));
-      bstore(rd[i], mN, 3u * planeb, S(fo[i][3]));
-      bstore(rd[i], mN, 4u * planeb, S(fo[i][4]));
-      bstore(rd[i], mC, 5u * planeb, S(fo[i][5]));
-      bstore(rd[i], mS, 6u * planeb, S(fo[i][6]));
-      bstore(rd[i], mS, 7u * planeb, S(fo[i][7]));
-      bstore(rd[i], mS, 8u * planeb, S(fo[i][8]));
+      C v[kQ];
+      v[0] = Elem<R>::kScaled ? fo[i][0] * kc.scale[i] : fo[i][0];
+#pragma unroll
+      for (int k = 1; k < kQ; ++k) v[k] = Elem<S>::kScaled ? fo[i][k] * kc.scale[i] : fo[i][k];
+      Elem<R>::st(rd[i], mR, 0u, v[0]);
+      Elem<S>::st(rd[i], mC, poff(1), v[1]);
+      Elem<S>::st(rd[i], mN, poff(2), v[2]);
+      Elem<S>::st(rd[i], mN, poff(3), v[3]);
+      Elem<S>::st(rd[i], mN, poff(4), v[4]);
+      Elem<S>::st(rd[i], mC, poff(5), v[5]);
+      Elem<S>::st(rd[i], mS, poff(6), v[6]);
+      Elem<S>::st(rd[i], mS, poff(7), v[7]);
+      Elem<S>::st(rd[i], mS, poff(8), v[8]);
     }
   };
 
@@ -371,6 +424,7 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
     const uint32_t oC = (uint32_t)y * rowb + bx;
     const uint32_t oS = (uint32_t)wrap(y - 1, kc.ny) * rowb + bx;
     const uint32_t oN = (uint32_t)wrap(y + 1, kc.ny) * rowb + bx;
+    const uint32_t oR = (uint32_t)y * rowbr + bxr;
     C fo[NL][kQ];
     if (st_ok) {
       const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
@@ -481,7 +535,7 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
 #pragma unroll
         for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
     }
-    store_row(st_ok, oS, oC, oN, fo);
+    store_row(st_ok, oS, oC, oN, oR, fo);
     // rotate the moment pipeline
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
@@ -503,7 +557,7 @@ step_kernel(const S* __restrict__ src, S* __restrict__ dst, const StepConsts<C> 
     for (int i = 0; i < NL; ++i)
 #pragma unroll
       for (int k = 0; k < kQ; ++k) zero[i][k] = C(0);
-    store_row(false, 0, 0, 0, zero);
+    store_row(false, 0, 0, 0, 0, zero);
   }
   int it = 0;
   for (; it + 1 < niter; it += 2) {

@@ -16,8 +16,19 @@ from . import build as _build
 
 MAX_LAYERS = 4
 MAX_PAIRS = MAX_LAYERS * (MAX_LAYERS + 1) // 2
-F64, F32, F16, BF16 = 0, 1, 2, 3
-PRECISIONS = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16dev": F16, "bf16dev": BF16}
+F64, F32, F16, BF16, F16_MIX, BF16_MIX = 0, 1, 2, 3, 4, 5
+PRECISIONS = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16dev": F16, "bf16dev": BF16,
+              "f16mix": F16_MIX, "bf16mix": BF16_MIX}
+# bytes of (rest plane, one moving plane) per node
+PLANE_BYTES = {F64: (8, 8), F32: (4, 4), F16: (2, 2), BF16: (2, 2), F16_MIX: (4, 2), BF16_MIX: (4, 2)}
+
+
+def bytes_per_update(precision) -> int:
+    """Algorithmic bytes per layer-node update: every population read once
+    and written once."""
+    code = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    r, m = PLANE_BYTES[code]
+    return 2 * (r + 8 * m)
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFINITE",
           -5: "ENONPOSITIVE", -6: "EUNSTABLE"}
 
@@ -51,6 +62,11 @@ def load_library():
     path = _build.lib_path()
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run python -m paper_2409_16659_amd.build")
+    # torch ships its own HIP runtime under the soname the library links
+    # against; loading torch first makes the library bind to that copy, so
+    # that one runtime owns the device memory torch allocates for us.
+    import torch  # noqa: F401
+
     lib = C.CDLL(path)
     P = C.POINTER(Params)
     H = C.c_void_p

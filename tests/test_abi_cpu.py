@@ -81,6 +81,22 @@ def test_query_sizes_and_validation():
     p64 = mlfilm.make_params(inputs.film_params(2, 100, 3, gamma=[1, 1], mu=[1, 1], hstar=0.1), "f64")
     assert mlfilm.query_pitch(p64) == 128
     assert mlfilm.query_sizes(p64)[0] == 128 * 3 * 9 * 2 * 8
+    # per layer: the rest plane, then eight moving planes of that plane type
+    for prec, (rb, mb) in [("f16", (2, 2)), ("bf16", (2, 2)), ("f16mix", (4, 2)), ("bf16mix", (4, 2))]:
+        q = mlfilm.make_params(film, prec)
+        assert mlfilm.query_sizes(q)[0] == 1024 * 1024 * 3 * (rb + 8 * mb)
+        assert mlfilm.bytes_per_update(prec) == 2 * (rb + 8 * mb)
+    q = mlfilm.make_params(film, "f32")
+    q.precision = 6
+    with pytest.raises(mlfilm.MlfError):
+        mlfilm.query_sizes(q)
+    # one layer must fit a 2 GiB buffer descriptor
+    big = inputs.film_params(1, 8192, 7281, gamma=[1], mu=[1], hstar=0.1)
+    assert mlfilm.query_sizes(mlfilm.make_params(big, "f32"))[0] == 8192 * 7281 * 9 * 4 <= 2 ** 31
+    big["ny"] = 7282
+    with pytest.raises(mlfilm.MlfError) as e:
+        mlfilm.query_sizes(mlfilm.make_params(big, "f32"))
+    assert e.value.status == "EUNSUPPORTED"
     for field, val in [("n_layers", 0), ("n_layers", 5), ("nx", 0), ("tau", 0.5), ("hstar", 0.0),
                        ("exp_b", 9)]:
         q = mlfilm.make_params(film, "f32")

@@ -199,13 +199,26 @@ def test_flat_film_fixed_point(mlf):
 
 
 def _shift_blob(g, blob, dx, dy):
-    """Roll the raw population payload of a checkpoint by a lattice vector."""
+    """Roll the raw population payload of a checkpoint by a lattice vector
+    (per layer: the rest plane, then eight moving planes)."""
+    from paper_2409_16659_amd import mlfilm
+
     pitch = mlf_pitch(g)
-    dt = np.float64 if g.params.precision == 0 else np.float32
+    rb, mb = mlfilm.PLANE_BYTES[g.params.precision]
+    raw = {8: np.uint64, 4: np.uint32, 2: np.uint16}
     head = len(blob) - g.pop_bytes
-    pay = np.frombuffer(blob[head:], dtype=dt).reshape(g.n, 9, g.ny, pitch).copy()
-    pay[..., : g.nx] = np.roll(np.roll(pay[..., : g.nx], dx, axis=3), dy, axis=2)
-    return blob[:head] + pay.tobytes()
+    plane = g.ny * pitch
+    layer = plane * (rb + 8 * mb)
+    out = bytearray(blob[:head])
+    for i in range(g.n):
+        base = head + i * layer
+        for k in range(9):
+            off = base + (0 if k == 0 else plane * (rb + (k - 1) * mb))
+            sz = rb if k == 0 else mb
+            a = np.frombuffer(blob[off:off + plane * sz], dtype=raw[sz]).reshape(g.ny, pitch).copy()
+            a[:, : g.nx] = np.roll(np.roll(a[:, : g.nx], dx, axis=1), dy, axis=0)
+            out += a.tobytes()
+    return bytes(out)
 
 
 def mlf_pitch(g):
@@ -214,7 +227,7 @@ def mlf_pitch(g):
     return mlfilm.query_pitch(g.params)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16", "f16mix", "bf16mix"])
 def test_translation_equivariance(mlf, prec):
     """Shifting the stored populations by a lattice vector shifts the result
     of later steps by the same vector, bit for bit."""

@@ -1,0 +1,208 @@
+"""16-bit population storage (IEEE half or bfloat16 deviations from the
+rest state, FP32 arithmetic; either all nine planes 16-bit or the rest
+plane FP32 and the eight moving planes 16-bit) against the FP64 oracle.
+
+One step.  Started from the same populations (the GPU state decoded
+exactly into FP64 and handed to the oracle), the GPU result differs from
+the oracle's step only by FP32 arithmetic and one rounding of each stored
+value s = f - f_rest (f_rest = h_ref for the rest population, 0 for the
+moving ones).  Per population
+    |f_gpu - f_ref| <= ulp(s_ref) + 1e-5 max_plane |s_ref|,
+where ulp is the spacing of the plane's format at |s_ref| (2^(e-10) for
+half, 2^(e-7) for bfloat16, 2^(e-23) for FP32, e = floor(log2 |s_ref|)):
+half an ulp for the rounding, the rest for an FP32 result that lands across
+a rounding boundary, plus the FP32 parity tolerance.
+
+Many steps.  Each step rounds every stored value once more.  The roundings
+are independent, so after T steps the height error is a random walk of
+about sqrt(T) (u0 rms(s_0) + u rms_m) per node, u0 and u the unit
+roundoffs of the rest and moving planes (2^-11 half, 2^-8 bfloat16,
+2^-24 FP32) and rms_m the root of the summed mean squares of the eight
+moving populations; the dynamics damp it (diffusive modes) or amplify it
+(unstable modes, by at most exp(eta_max T)).  The tests allow 8 times that
+estimate, measured against the height perturbation h - mean(h).  Each step
+adds n roundings to a layer's mass; were they independent the relative
+drift would be about sqrt(T n) (u0 rms(s_0) + u rms_m) / (n h_ref), but
+successive roundings of a slowly varying value are correlated, which
+raises it several times.  The test allows 64 times the independent
+estimate, plus 1e-8 for the FP32 collision itself (FP32 storage drifts by
+about 1e-9 over this horizon): still far below the drift
+T u0 mean|s_0| / h_ref of a biased store (truncation instead of
+round-to-nearest) of the all-16-bit formats, which the test checks it can
+tell apart.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2409_16659_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# stored mantissa bits of the (rest, moving) planes
+MANT = {"f16": (10, 10), "bf16": (7, 7), "f16mix": (23, 10), "bf16mix": (23, 7)}
+PRECS = list(MANT)
+
+
+def unit(prec):
+    """Unit roundoffs of the (rest, moving) planes."""
+    return tuple(2.0 ** -(m + 1) for m in MANT[prec])
+
+ETA_MAX = 5.2e-4                  # fastest growth rate of the 4-layer film per step (LSA)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mlf(torch_cuda):
+    from paper_2409_16659_amd import mlfilm
+
+    mlfilm.load_library()
+    return mlfilm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ulp(s, mant):
+    """Spacing of a binary format with `mant` stored mantissa bits at |s|
+    (normal range; 0 where s == 0, which the absolute slack covers)."""
+    a = np.abs(s)
+    _, e = np.frexp(a)          # a = m 2^e, m in [0.5, 1)
+    return np.where(a > 0, np.ldexp(1.0, e - 1 - mant), 0.0)
+
+
+def stored(f, href):
+    """Stored value of absolute populations f[N][9][ny][nx]."""
+    s = f.copy()
+    s[:, 0] -= np.asarray(href)[:, None, None]
+    return s
+
+
+def one_step_check(mlf, oracle_mod, film, h0, prec, launch=None, autotune=False):
+    say(f"one step {prec} N={film['n_layers']} {film['nx']}x{film['ny']} launch={launch} tune={autotune}")
+    g = mlf.Film(film, prec)
+    g.init(h0)
+    if launch:
+        g.set_launch(*launch)
+    if autotune:
+        g.autotune(2)
+    href = h0.mean(axis=(1, 2))
+    g.step(3)                      # a state whose moving populations are not at equilibrium
+    f0 = g.populations()
+    o = oracle_mod.Oracle(film)
+    o.set_f(f0)
+    del f0
+    g.step(1)
+    o.step(1)
+    sg, so = stored(g.populations(), href), stored(o.get_f(), href)
+    del o
+    worst = 0.0
+    for i in range(film["n_layers"]):
+        for k in range(9):
+            d = np.abs(sg[i, k] - so[i, k])
+            tol = ulp(so[i, k], MANT[prec][0 if k == 0 else 1]) + 1e-5 * np.abs(so[i, k]).max()
+            r = float((d / np.maximum(tol, 1e-300)).max())
+            worst = max(worst, r)
+            assert np.all(d <= tol), (i, k, float(d.max()), r)
+    say(f"   worst error / tolerance = {worst:.3f}")
+    return worst
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_one_step_is_one_rounding_of_the_oracle(mlf, oracle_mod, prec):
+    """Ragged 2D grid, 4 layers, several tiles and a ragged tail."""
+    film, h0, _ = inputs.workload("film4_2d_512", 203, 77)
+    h0 = h0 + 0.02 * np.sin(2 * math.pi * np.arange(203) / 203)[None, None, :]
+    one_step_check(mlf, oracle_mod, film, h0, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_one_step_fewer_layers(mlf, oracle_mod, prec, n):
+    film, h0, _ = inputs.workload("film4_2d_512", 130, 33)
+    keep = [k for k in film["spread"] if k[0] + k[1] <= n]
+    film = inputs.film_params(n, 130, 33, gamma=film["gamma"][:n], mu=film["mu"][:n],
+                              hstar=film["hstar"], spread={k: film["spread"][k] for k in keep})
+    rng = np.random.default_rng(11 + n)
+    h0 = h0[:n] + 0.01 * rng.standard_normal(h0[:n].shape)
+    one_step_check(mlf, oracle_mod, film, h0, prec, launch=(64, 5))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["f16", "f16mix"])
+def test_one_step_full_size(mlf, oracle_mod, prec):
+    """4 layers at 4096 x 4096 with the autotuned launch shape."""
+    film, h0, _ = inputs.workload("film4_2d_4096")
+    one_step_check(mlf, oracle_mod, film, h0, prec, autotune=True)
+
+
+@pytest.fixture(scope="module")
+def crop_run(oracle_mod):
+    """FP64 oracle on the 512^2 crop of the 4-layer workload, T steps."""
+    film, h0, _ = inputs.workload("film4_2d_512")
+    T = 1000
+    say(f"oracle 512x512 N=4, {T} steps")
+    o = oracle_mod.Oracle(film)
+    o.init(h0)
+    o.step(T)
+    h, _, _ = o.read()
+    f = o.get_f()
+    rms_m = np.sqrt((f[:, 1:] ** 2).mean(axis=(2, 3)).sum(axis=1))
+    return film, h0, T, h, o.mass(), rms_m
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_crop_accuracy_and_mass(mlf, crop_run, prec):
+    film, h0, T, ho, mo, rms_m = crop_run
+    g = mlf.Film(film, prec)
+    g.init(h0)
+    m0 = g.mass()
+    g.step(T)
+    hg, _, _ = g.read()
+    mg = g.mass()
+    n = film["nx"] * film["ny"]
+    u0, u = unit(prec)
+    href = h0.mean(axis=(1, 2))
+    for i in range(film["n_layers"]):
+        pert = ho[i] - ho[i].mean()
+        rms_s = float(np.sqrt((pert ** 2).mean()))
+        per_node = u0 * rms_s + u * float(rms_m[i])
+        e_pert = float(np.linalg.norm(hg[i] - ho[i]) / np.linalg.norm(pert))
+        e_l2 = float(np.linalg.norm(hg[i] - ho[i]) / np.linalg.norm(ho[i]))
+        bound = 8 * math.sqrt(T) * math.exp(ETA_MAX * T) * per_node / rms_s
+        drift = abs(mg[i] - m0[i]) / m0[i]
+        dref = abs(mg[i] - mo[i]) / mo[i]
+        mbound = 64 * math.sqrt(T * n) * per_node / (n * href[i]) + 1e-8
+        if u0 == u:
+            biased = T * u * float(np.abs(pert).mean()) / href[i]
+            assert mbound < 1e-2 * biased
+        say(f"   {prec} layer {i}: L2 {e_l2:.3e}  vs perturbation {e_pert:.3e} (bound {bound:.2e})"
+            f"  mass drift {drift:.2e} vs oracle {dref:.2e} (bound {mbound:.2e})")
+        assert e_pert <= bound, (i, e_pert, bound)
+        assert drift <= mbound, (i, drift, mbound)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_flat_film_stays_flat(mlf, prec):
+    """A flat film is a fixed point: every stored deviation stays exactly 0
+    (dyadic heights, so that their means are exact)."""
+    film, _, _ = inputs.workload("film4_2d_512", 67, 19)
+    h0 = np.stack([np.full((19, 67), v) for v in (1.0, 0.75, 0.5, 0.25)])
+    g = mlf.Film(film, prec)
+    g.init(h0)
+    g.step(50)
+    h, ux, uy = g.read()
+    assert np.array_equal(h, h0)
+    assert not ux.any() and not uy.any()
