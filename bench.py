@@ -28,23 +28,38 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_digest() -> str:
+    """Digest of the step kernel's source (kernel body and tile geometry)."""
     h = hashlib.sha256()
-    for rel in ("paper_2409_16659_amd/csrc/step_kernel.hpp", "paper_2409_16659_amd/csrc/mlfilm.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2409_16659_amd/csrc/step_kernel.hpp"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, launch):
-    """HBM bytes per launch from rocprofv3 counters, if they were taken on
-    the current kernel source in this launch shape; else None."""
+def _profile_entry(workload: str, prec: str):
+    """The rocprofv3 record of this workload and storage format, if it was
+    taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = data.get(workload)
-    if not ent or ent.get("kernel_digest") != kernel_digest() or list(ent.get("launch", [])) != list(launch):
+    ent = data.get(f"{workload}:{prec}")
+    if not ent or ent.get("kernel_digest") != kernel_digest():
+        return None
+    return ent
+
+
+def profiled_launch(workload: str, prec: str):
+    """Launch shape the autotuner chose for the profiled run, if current."""
+    ent = _profile_entry(workload, prec)
+    return tuple(ent["launch"]) if ent else None
+
+
+def measured_traffic(workload: str, prec: str, launch):
+    """HBM bytes per launch from rocprofv3 counters, if they were taken on
+    the current kernel source in this launch shape; else None."""
+    ent = _profile_entry(workload, prec)
+    if not ent or list(ent.get("launch", [])) != list(launch):
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -76,8 +91,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="film3_2d_1024")
     ap.add_argument("--precision", default=None, help="override the workload's storage precision")
-    ap.add_argument("--block-w", type=int, default=0, help="launch shape; default: autotuned")
-    ap.add_argument("--seg-h", type=int, default=0, help="launch shape; default: autotuned")
+    ap.add_argument("--block-w", type=int, default=0,
+                    help="launch shape; default: the shape the autotuner chose for the profiled run of this "
+                         "kernel source, else the autotuner now")
+    ap.add_argument("--seg-h", type=int, default=0, help="launch shape (see --block-w)")
+    ap.add_argument("--autotune", action="store_true", help="always run the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget; 0 disables it")
     ap.add_argument("--copy-probe", action="store_true",
@@ -124,10 +142,16 @@ def main():
 
     g = mlfilm.Film(film, prec, check_every=-1)
     g.init(h0)
+    pl = None if args.autotune else profiled_launch(args.workload, prec)
     if args.block_w or args.seg_h:
         g.set_launch(args.block_w, args.seg_h)
+        source = "given"
+    elif pl:
+        g.set_launch(*pl)
+        source = "autotuned (profiled run)"
     else:
         g.autotune(reps=3)  # library autotuner: times shapes, state unchanged
+        source = "autotuned"
     launch = g.get_launch()
     print(f"[bench] {args.workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
           f"launch={launch} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
@@ -149,7 +173,7 @@ def main():
 
     value = n_lu * args.steps / wall
     achieved = bytes_per_lu * n_lu / (kern_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, launch)
+    traffic = measured_traffic(args.workload, prec, launch)
     out = {
         "metric": "layer-lattice updates/s & % HBM roofline; surrogate/batched speedup @1e-3 L2",
         "value": value,
@@ -164,7 +188,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32"}.get(prec, "f32"),
         "data": "synthetic",
         "config": {"workload": args.workload, "layers": film["n_layers"], "nx": film["nx"], "ny": film["ny"],
-                   "storage": prec, "lattice": "D2Q9", "tau": film["tau"], "launch": list(launch)},
+                   "storage": prec, "lattice": "D2Q9", "tau": film["tau"], "launch": list(launch),
+                   "launch_source": source},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_lu": bytes_per_lu, "kernel_ms": kern_ms},

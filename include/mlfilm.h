@@ -30,8 +30,9 @@
  *    is the default stream).  mlf_step is asynchronous except for the guard
  *    polls; every call that returns host data synchronises the stream.
  *  - Fields are [N][ny][nx] row-major (x fastest).  Populations are stored
- *    structure-of-arrays: per layer the rest plane, then the eight moving
- *    planes, each of ny rows of `pitch` elements of that plane's type.
+ *    per direction: the rest plane, then the eight moving planes, each of
+ *    ny rows of `pitch` nodes, x fastest; a node holds the N layers'
+ *    values of that plane's type next to each other.
  *  - A handle is not thread-safe.
  */
 #ifndef MLFILM_H

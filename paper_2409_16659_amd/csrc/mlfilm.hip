@@ -56,14 +56,17 @@ Fmt move_fmt(int precision) {
 size_t fmt_size(Fmt f) { return f == kFmtF64 ? 8 : (f == kFmtF32 ? 4 : 2); }
 bool fmt_scaled(Fmt f) { return f == kFmtF16 || f == kFmtBF16; }
 
-// Bytes of one layer (rest plane, then eight moving planes) and the byte
-// offset of plane k inside it; `plane` is in elements.
-size_t layer_bytes(int precision, size_t plane) {
-  return plane * (fmt_size(rest_fmt(precision)) + (kQ - 1) * fmt_size(move_fmt(precision)));
+// Population buffer layout: plane k (rest plane, then eight moving planes)
+// of `plane` nodes (ny rows of `pitch`), each node holding the n layers'
+// values next to each other.  Bytes per node of plane k, byte offset of
+// plane k, and bytes of the whole buffer.
+size_t node_bytes(int precision, int n, int k) {
+  return (size_t)n * fmt_size(k == 0 ? rest_fmt(precision) : move_fmt(precision));
 }
-size_t plane_offset(int precision, size_t plane, int k) {
-  return k == 0 ? 0 : plane * (fmt_size(rest_fmt(precision)) + (size_t)(k - 1) * fmt_size(move_fmt(precision)));
+size_t plane_offset(int precision, int n, size_t plane, int k) {
+  return k == 0 ? 0 : plane * (node_bytes(precision, n, 0) + (size_t)(k - 1) * node_bytes(precision, n, 1));
 }
+size_t buffer_bytes(int precision, int n, size_t plane) { return plane_offset(precision, n, plane, kQ); }
 
 int pitch_of(const mlf_params* p) { return (p->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
 
@@ -94,10 +97,12 @@ mlf_status validate(const mlf_params* p, std::string* why) {
     if (!std::isfinite(p->spread[j])) return bad("spread must be finite");
   size_t plane = (size_t)pitch_of(p) * (size_t)p->ny;
   if (plane * kQ * (size_t)p->n_layers > (size_t)1 << 40) return bad("grid too large");
-  // the step kernel addresses one layer (nine planes) through a buffer
+  // the step kernel addresses each group of three planes through a buffer
   // descriptor with 32-bit offsets and masks lanes with offset 2^31
-  if (layer_bytes(p->precision, plane) > (size_t)0x80000000u) {
-    if (why) *why = "one layer of populations exceeds 2 GiB";
+  const size_t g0 = plane_offset(p->precision, p->n_layers, plane, 3);
+  const size_t g1 = plane_offset(p->precision, p->n_layers, plane, 6) - g0;
+  if (std::max(g0, g1) > (size_t)0x80000000u) {
+    if (why) *why = "three population planes exceed 2 GiB";
     return MLF_EUNSUPPORTED;
   }
   for (int i = 0; i < p->n_layers; ++i)
@@ -198,28 +203,26 @@ __device__ inline double to_store<double>(double v) {
   return v;
 }
 
-// Populations of all layers: per layer the rest plane (type R), then the
-// eight moving planes (type S), each of `plane` elements.
+// Populations: the rest plane (type R), then the eight moving planes (type
+// S), each of `plane` nodes; a node holds the nl layers' values in a row.
 template <typename R, typename S>
 struct PopView {
   unsigned char* base;
   long long plane;
-  __device__ long long layer_bytes() const { return plane * (long long)(sizeof(R) + (kQ - 1) * sizeof(S)); }
-  // unscaled value of element e of plane (i, k)
+  int nl;
+  // unscaled value of layer i, direction k at node e
   __device__ double ld(int i, int k, long long e, const Layers& L) const {
-    const unsigned char* l = base + i * layer_bytes();
-    if (k == 0) return double(reinterpret_cast<const R*>(l)[e]) / (kIs16<R> ? L.sc[i] : 1.0);
-    const S* m = reinterpret_cast<const S*>(l + plane * (long long)sizeof(R));
-    return double(m[(long long)(k - 1) * plane + e]) / (kIs16<S> ? L.sc[i] : 1.0);
+    if (k == 0) return double(reinterpret_cast<const R*>(base)[e * nl + i]) / (kIs16<R> ? L.sc[i] : 1.0);
+    const S* m = reinterpret_cast<const S*>(base + plane * nl * (long long)sizeof(R));
+    return double(m[((long long)(k - 1) * plane + e) * nl + i]) / (kIs16<S> ? L.sc[i] : 1.0);
   }
   __device__ void st(int i, int k, long long e, double v, const Layers& L) const {
-    unsigned char* l = base + i * layer_bytes();
     if (k == 0) {
-      reinterpret_cast<R*>(l)[e] = to_store<R>(v * (kIs16<R> ? L.sc[i] : 1.0));
+      reinterpret_cast<R*>(base)[e * nl + i] = to_store<R>(v * (kIs16<R> ? L.sc[i] : 1.0));
       return;
     }
-    S* m = reinterpret_cast<S*>(l + plane * (long long)sizeof(R));
-    m[(long long)(k - 1) * plane + e] = to_store<S>(v * (kIs16<S> ? L.sc[i] : 1.0));
+    S* m = reinterpret_cast<S*>(base + plane * nl * (long long)sizeof(R));
+    m[((long long)(k - 1) * plane + e) * nl + i] = to_store<S>(v * (kIs16<S> ? L.sc[i] : 1.0));
   }
 };
 
@@ -616,7 +619,7 @@ mlf_status launch_init(mlf_handle* h, const double* hs, const double* uxs, const
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
     hipLaunchKernelGGL((init_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, hs, uxs, uys, lstride,
                        yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
   });
@@ -632,7 +635,7 @@ mlf_status launch_read(mlf_handle* h, double* ho, double* uxo, double* uyo, long
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
     hipLaunchKernelGGL((read_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, ho, uxo, uyo, lstride,
                        yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
   });
@@ -704,7 +707,7 @@ const char* mlf_version(void) { return "mlfilm 0.1 gfx950"; }
 mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes) {
   mlf_status st = validate(p, nullptr);
   if (st != MLF_OK) return st;
-  if (pop_bytes) *pop_bytes = layer_bytes(p->precision, (size_t)pitch_of(p) * p->ny) * p->n_layers;
+  if (pop_bytes) *pop_bytes = buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny);
   if (scratch_bytes) *scratch_bytes = kScratchBytes;
   return MLF_OK;
 }
@@ -736,7 +739,7 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   h->stream = static_cast<hipStream_t>(stream);
   h->pitch = pitch_of(p);
   h->plane = (size_t)h->pitch * p->ny;
-  h->pop_bytes = layer_bytes(p->precision, h->plane) * p->n_layers;
+  h->pop_bytes = buffer_bytes(p->precision, p->n_layers, h->plane);
   for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0, h->scale[i] = 1.0;
   h->steps = 0;
   h->initialised = false;
@@ -982,7 +985,7 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
     hipLaunchKernelGGL((mass_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part_ptr(h), p.nx, p.ny,
                        h->pitch, p.n_layers, L);
   });
@@ -1011,8 +1014,8 @@ mlf_status mlf_read_populations(mlf_handle* h, double* f) {
         for (int x = 0; x < p.nx; ++x) {
           const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
           const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
-          const size_t b = i * layer_bytes(p.precision, h->plane) + plane_offset(p.precision, h->plane, k) +
-                           e * fmt_size(fm);
+          const size_t b = plane_offset(p.precision, p.n_layers, h->plane, k) +
+                           (e * p.n_layers + i) * fmt_size(fm);
           double v = host_load(fm, raw.data() + b) / (fmt_scaled(fm) ? h->scale[i] : 1.0);
           if (k == 0) v += h->hbar[i];
           f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x] = v;
@@ -1031,8 +1034,8 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f) {
         for (int x = 0; x < p.nx; ++x) {
           const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
           const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
-          const size_t b = i * layer_bytes(p.precision, h->plane) + plane_offset(p.precision, h->plane, k) +
-                           e * fmt_size(fm);
+          const size_t b = plane_offset(p.precision, p.n_layers, h->plane, k) +
+                           (e * p.n_layers + i) * fmt_size(fm);
           double v = f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x];
           if (k == 0) v -= h->hbar[i];
           host_store(fm, raw.data() + b, v * (fmt_scaled(fm) ? h->scale[i] : 1.0));

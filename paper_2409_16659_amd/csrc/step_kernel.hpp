@@ -15,8 +15,12 @@
 //   f_ki(x + c_k, t+1) = f*_ki(x), periodic
 //
 // Layout and schedule (gfx950, wave64):
-//  * Populations are structure-of-arrays, plane (i, k) = ny rows of `pitch`
-//    elements, x fastest.
+//  * Populations are stored per direction k: plane k = ny rows of `pitch`
+//    nodes, x fastest, and each node holds the populations of all N layers
+//    next to each other.  One 4N- (FP32), 8N- (FP64) or 2N-byte (16-bit)
+//    vector access then moves a direction's populations of every layer,
+//    N times fewer memory instructions than one access per layer; the step
+//    is otherwise bound by the rate of vector-memory instructions.
 //  * Streaming is split by axis: the y-shift is applied when a population is
 //    written (push) and the x-shift when it is read (pull).  Plane k stores
 //    at column x the population that belongs to node x + c_kx:
@@ -32,7 +36,7 @@
 //  * The rest plane may have its own storage type R (FP32 rest with 16-bit
 //    moving populations): the rest population carries the height, whose
 //    per-step change is far below a 16-bit ulp of its deviation, while the
-//    moving ones are rebuilt from the moments every step.  A layer is the
+//    moving ones are rebuilt from the moments every step.  The buffer is the
 //    rest plane followed by the eight moving planes, addressed in bytes.
 //  * A workgroup owns a strip of columns and marches along a segment of rows
 //    (a sliding window).  Its lanes cover the strip plus two halo columns on
@@ -56,6 +60,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace mlf {
 
@@ -87,69 +93,146 @@ struct StepConsts {
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
 };
 
-// Storage access through raw buffer descriptors: one descriptor per layer
-// (base address and byte size in scalar registers), the (layer, direction)
-// plane offset as the scalar offset, and per-lane 32-bit byte offsets shared
-// by all planes.  Accesses beyond the descriptor's size read zero and drop
-// the write instead of faulting.
+// Storage access through raw buffer descriptors: one descriptor per group of
+// three direction planes (base address and byte size in scalar registers),
+// the plane's offset inside its group as the scalar offset, and per-lane
+// 32-bit byte offsets shared by the planes of one type.  Accesses beyond the
+// descriptor's size read zero and drop the write instead of faulting.
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit format
-// Per-lane offset of a masked access: at least the descriptor size (one layer
-// is limited to 2 GiB) and, with any plane offset added, still below 2^32, so
-// the access is out of range whether or not the range check includes the
-// scalar offset.
+// Per-lane offset of a masked access: at least the descriptor size (a group
+// of three planes is limited to 2 GiB) and, with any plane offset added,
+// still below 2^32, so the access is out of range whether or not the range
+// check includes the scalar offset.
 constexpr uint32_t kMasked = 0x80000000u;
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-// Element access by storage type.  16-bit formats hold the deviations of
-// the populations scaled by a per-layer power of two (IEEE half: keeps the
-// small populations out of the subnormal range; bfloat16: scale 1) and are
-// converted to/from FP32 with round-to-nearest-even.
+// Element formats.  16-bit formats hold the deviations of the populations
+// scaled by a per-layer power of two (IEEE half: keeps the small populations
+// out of the subnormal range; bfloat16: scale 1) and are converted to and
+// from FP32 with round-to-nearest-even.
+template <typename T>
+struct Elem {
+  static constexpr bool kScaled = sizeof(T) == 2;
+};
+
+template <int NW>
+struct Words {
+  uint32_t w[NW];
+};
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-template <typename S>
-struct Elem;
-template <>
-struct Elem<double> {
-  static constexpr bool kScaled = false;
-  __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// NW consecutive 32-bit words at byte offset voff + soff (+ j) through the
+// widest raw buffer accesses (16, 12, 8, 4 bytes).
+template <int NW>
+__device__ inline void load_words(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t (&w)[NW]) {
+  int j = 0;
+#pragma unroll
+  for (; j + 4 <= NW; j += 4) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(voff + 4 * j), (int)soff, 0);
+    w[j] = v.x, w[j + 1] = v.y, w[j + 2] = v.z, w[j + 3] = v.w;
   }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  if constexpr (NW % 4 == 3) {
+    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)(voff + 4 * (NW - 3)), (int)soff, 0);
+    w[NW - 3] = v.x, w[NW - 2] = v.y, w[NW - 1] = v.z;
+  } else if constexpr (NW % 4 == 2) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(voff + 4 * (NW - 2)), (int)soff, 0);
+    w[NW - 2] = v.x, w[NW - 1] = v.y;
+  } else if constexpr (NW % 4 == 1) {
+    w[NW - 1] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(voff + 4 * (NW - 1)), (int)soff, 0);
   }
-};
-template <>
-struct Elem<float> {
-  static constexpr bool kScaled = false;
-  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <int NW>
+__device__ inline void store_words(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, const uint32_t (&w)[NW]) {
+  int j = 0;
+#pragma unroll
+  for (; j + 4 <= NW; j += 4)
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[j], w[j + 1], w[j + 2], w[j + 3]}, r, (int)(voff + 4 * j),
+                                           (int)soff, 0);
+  if constexpr (NW % 4 == 3)
+    __builtin_amdgcn_raw_buffer_store_b96(u32x3{w[NW - 3], w[NW - 2], w[NW - 1]}, r,
+                                          (int)(voff + 4 * (NW - 3)), (int)soff, 0);
+  else if constexpr (NW % 4 == 2)
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{w[NW - 2], w[NW - 1]}, r, (int)(voff + 4 * (NW - 2)), (int)soff, 0);
+  else if constexpr (NW % 4 == 1)
+    __builtin_amdgcn_raw_buffer_store_b32(w[NW - 1], r, (int)(voff + 4 * (NW - 1)), (int)soff, 0);
+}
+
+__device__ inline float half_bits_to_f32(uint32_t b) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+}
+__device__ inline uint32_t f32_to_half_bits(float v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
+__device__ inline float bf16_bits_to_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
+__device__ inline uint32_t f32_to_bf16_bits(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+
+// The NL populations of one direction at one node (layers next to each
+// other), converted to the arithmetic type C.
+template <typename T, int NL, typename C>
+__device__ inline void load_node(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, C (&v)[NL]) {
+  if constexpr (sizeof(T) == 4) {
+    uint32_t w[NL];
+    load_words<NL>(r, voff, soff, w);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) v[i] = C(__builtin_bit_cast(float, w[i]));
+  } else if constexpr (sizeof(T) == 8) {
+    uint32_t w[2 * NL];
+    load_words<2 * NL>(r, voff, soff, w);
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      v[i] = C(__builtin_bit_cast(double, (unsigned long long)w[2 * i] | ((unsigned long long)w[2 * i + 1] << 32)));
+  } else if constexpr (NL % 2 == 0) {  // 16-bit, whole words
+    uint32_t w[NL / 2];
+    load_words<NL / 2>(r, voff, soff, w);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const uint32_t b = (i & 1) ? (w[i / 2] >> 16) : (w[i / 2] & 0xffffu);
+      v[i] = C(std::is_same_v<T, _Float16> ? half_bits_to_f32(b) : bf16_bits_to_f32(b));
+    }
+  } else {  // 16-bit, odd layer count: one 2-byte access per layer
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(voff + 2 * i), (int)soff, 0);
+      v[i] = C(std::is_same_v<T, _Float16> ? half_bits_to_f32(b) : bf16_bits_to_f32(b));
+    }
   }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+template <typename T, int NL, typename C>
+__device__ inline void store_node(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, const C (&v)[NL]) {
+  if constexpr (sizeof(T) == 4) {
+    uint32_t w[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) w[i] = __builtin_bit_cast(uint32_t, (float)v[i]);
+    store_words<NL>(r, voff, soff, w);
+  } else if constexpr (sizeof(T) == 8) {
+    uint32_t w[2 * NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, (double)v[i]);
+      w[2 * i] = (uint32_t)b;
+      w[2 * i + 1] = (uint32_t)(b >> 32);
+    }
+    store_words<2 * NL>(r, voff, soff, w);
+  } else {
+    uint32_t b[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      b[i] = std::is_same_v<T, _Float16> ? f32_to_half_bits((float)v[i]) : f32_to_bf16_bits((float)v[i]);
+    if constexpr (NL % 2 == 0) {
+      uint32_t w[NL / 2];
+#pragma unroll
+      for (int j = 0; j < NL / 2; ++j) w[j] = b[2 * j] | (b[2 * j + 1] << 16);
+      store_words<NL / 2>(r, voff, soff, w);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b[i], r, (int)(voff + 2 * i), (int)soff, 0);
+    }
   }
-};
-template <>
-struct Elem<_Float16> {
-  static constexpr bool kScaled = true;
-  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
-  }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)voff, (int)soff, 0);
-  }
-};
-template <>
-struct Elem<__bf16> {
-  static constexpr bool kScaled = true;
-  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
-  }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, (int)voff, (int)soff, 0);
-  }
-};
+}
 
 // Reciprocal: the hardware approximation (1 ulp) in FP32, a correctly
 // rounded division in FP64.
@@ -234,20 +317,21 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   const int y0 = seg * kc.seg_h;
   const int y1 = min(y0 + kc.seg_h, kc.ny);
   const int dir = (seg & 1) ? -1 : 1;  // marching direction in y
-  const uint32_t rowb = (uint32_t)kc.pitch * (uint32_t)sizeof(S);   // bytes per row, moving planes
-  const uint32_t rowbr = (uint32_t)kc.pitch * (uint32_t)sizeof(R);  // bytes per row, rest plane
-  const uint32_t planeb = (uint32_t)(kc.plane * (long long)sizeof(S));
-  const uint32_t planebr = (uint32_t)(kc.plane * (long long)sizeof(R));
-  const uint32_t layerb = planebr + planeb * (uint32_t)(kQ - 1);  // bytes per layer
-  // byte offset of plane k >= 1 in a layer
-  auto poff = [&](uint32_t k) { return planebr + (k - 1u) * planeb; };
+  constexpr uint32_t nodeb = NL * sizeof(S), nodebr = NL * sizeof(R);  // bytes per node
+  const uint32_t rowb = (uint32_t)kc.pitch * nodeb;    // bytes per row, moving planes
+  const uint32_t rowbr = (uint32_t)kc.pitch * nodebr;  // bytes per row, rest plane
+  const uint32_t planeb = (uint32_t)(kc.plane * (long long)nodeb);
+  const uint32_t planebr = (uint32_t)(kc.plane * (long long)nodebr);
   if (w <= 0 || y1 <= y0) return;  // uniform per workgroup; never taken with host geometry
-  __amdgpu_buffer_rsrc_t rs[NL], rd[NL];
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    rs[i] = make_rsrc(src + (long long)i * layerb, layerb);
-    rd[i] = make_rsrc(dst + (long long)i * layerb, layerb);
-  }
+  // descriptors of the plane groups {0, 1, 2}, {3, 4, 5}, {6, 7, 8}
+  const uint32_t g0b = planebr + 2u * planeb, g1b = 3u * planeb;
+  __amdgpu_buffer_rsrc_t rs[3], rd[3];
+  rs[0] = make_rsrc(src, g0b);
+  rs[1] = make_rsrc(src + g0b, g1b);
+  rs[2] = make_rsrc(src + (long long)g0b + g1b, g1b);
+  rd[0] = make_rsrc(dst, g0b);
+  rd[1] = make_rsrc(dst + g0b, g1b);
+  rd[2] = make_rsrc(dst + (long long)g0b + g1b, g1b);
 
   extern __shared__ unsigned char smem_raw[];
   C* zr = reinterpret_cast<C*>(smem_raw);  // [5][NL][W]
@@ -258,10 +342,10 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   const bool act2 = tid >= 1 && tid <= w + 2;  // pressure
   const bool act3 = tid >= 2 && tid < w + 2;   // collide + stream
   const int x = wrap(x0 + lc, kc.nx);
-  const uint32_t bx = (uint32_t)x * sizeof(S);
-  const uint32_t bxm = (uint32_t)wrap(x - 1, kc.nx) * sizeof(S);
-  const uint32_t bxp = (uint32_t)wrap(x + 1, kc.nx) * sizeof(S);
-  const uint32_t bxr = (uint32_t)x * sizeof(R);
+  const uint32_t bx = (uint32_t)x * nodeb;
+  const uint32_t bxm = (uint32_t)wrap(x - 1, kc.nx) * nodeb;
+  const uint32_t bxp = (uint32_t)wrap(x + 1, kc.nx) * nodeb;
+  const uint32_t bxr = (uint32_t)x * nodebr;
 
   // register pipeline of moments: row of iteration it (0), it-1 (1), it-2 (2)
   C dh0[NL], qx0[NL], qy0[NL];
@@ -279,10 +363,10 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   }
 
   // Every path through the row loop issues the same vector-memory sequence
-  // (9N loads, then 9N stores), inactive lanes using masked offsets: the
-  // compiler's wait for a row's loads then never covers the stores issued
-  // after them, and the prefetched row stays in flight across P2 and P3.
-  // Pre-collision f_k(x, y) = S_k(x - c_kx, y): directions 1, 2, 8 read
+  // (9 node loads, then 9 node stores), inactive lanes using masked offsets:
+  // the compiler's wait for a row's loads then never covers the stores
+  // issued after them, and the prefetched row stays in flight across P2 and
+  // P3.  Pre-collision f_k(x, y) = S_k(x - c_kx, y): directions 1, 2, 8 read
   // column x - 1, directions 4, 5, 6 column x + 1.
   auto load_row = [&](int r, bool valid, C (&fn)[NL][kQ]) {
     const bool ok = act1 && valid;
@@ -290,17 +374,20 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     const uint32_t row = yr * rowb;
     const uint32_t om = ok ? row + bxm : kMasked, o0 = ok ? row + bx : kMasked,
                    op = ok ? row + bxp : kMasked, orr = ok ? yr * rowbr + bxr : kMasked;
+    C v[kQ][NL];
+    load_node<R, NL>(rs[0], orr, 0u, v[0]);
+    load_node<S, NL>(rs[0], om, planebr, v[1]);
+    load_node<S, NL>(rs[0], om, planebr + planeb, v[2]);
+    load_node<S, NL>(rs[1], o0, 0u, v[3]);
+    load_node<S, NL>(rs[1], op, planeb, v[4]);
+    load_node<S, NL>(rs[1], op, 2u * planeb, v[5]);
+    load_node<S, NL>(rs[2], op, 0u, v[6]);
+    load_node<S, NL>(rs[2], o0, planeb, v[7]);
+    load_node<S, NL>(rs[2], om, 2u * planeb, v[8]);
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      fn[i][0] = C(Elem<R>::ld(rs[i], orr, 0u));
-      fn[i][1] = C(Elem<S>::ld(rs[i], om, poff(1)));
-      fn[i][2] = C(Elem<S>::ld(rs[i], om, poff(2)));
-      fn[i][3] = C(Elem<S>::ld(rs[i], o0, poff(3)));
-      fn[i][4] = C(Elem<S>::ld(rs[i], op, poff(4)));
-      fn[i][5] = C(Elem<S>::ld(rs[i], op, poff(5)));
-      fn[i][6] = C(Elem<S>::ld(rs[i], op, poff(6)));
-      fn[i][7] = C(Elem<S>::ld(rs[i], o0, poff(7)));
-      fn[i][8] = C(Elem<S>::ld(rs[i], om, poff(8)));
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) fn[i][k] = v[k][i];
       if constexpr (Elem<R>::kScaled) fn[i][0] *= kc.iscale[i];
       if constexpr (Elem<S>::kScaled) {
 #pragma unroll
@@ -314,22 +401,22 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   auto store_row = [&](bool ok, uint32_t oS, uint32_t oC, uint32_t oN, uint32_t oR, const C (&fo)[NL][kQ]) {
     const uint32_t mS = ok ? oS : kMasked, mC = ok ? oC : kMasked, mN = ok ? oN : kMasked,
                    mR = ok ? oR : kMasked;
+    C v[kQ][NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      C v[kQ];
-      v[0] = Elem<R>::kScaled ? fo[i][0] * kc.scale[i] : fo[i][0];
+      v[0][i] = Elem<R>::kScaled ? fo[i][0] * kc.scale[i] : fo[i][0];
 #pragma unroll
-      for (int k = 1; k < kQ; ++k) v[k] = Elem<S>::kScaled ? fo[i][k] * kc.scale[i] : fo[i][k];
-      Elem<R>::st(rd[i], mR, 0u, v[0]);
-      Elem<S>::st(rd[i], mC, poff(1), v[1]);
-      Elem<S>::st(rd[i], mN, poff(2), v[2]);
-      Elem<S>::st(rd[i], mN, poff(3), v[3]);
-      Elem<S>::st(rd[i], mN, poff(4), v[4]);
-      Elem<S>::st(rd[i], mC, poff(5), v[5]);
-      Elem<S>::st(rd[i], mS, poff(6), v[6]);
-      Elem<S>::st(rd[i], mS, poff(7), v[7]);
-      Elem<S>::st(rd[i], mS, poff(8), v[8]);
+      for (int k = 1; k < kQ; ++k) v[k][i] = Elem<S>::kScaled ? fo[i][k] * kc.scale[i] : fo[i][k];
     }
+    store_node<R, NL>(rd[0], mR, 0u, v[0]);
+    store_node<S, NL>(rd[0], mC, planebr, v[1]);
+    store_node<S, NL>(rd[0], mN, planebr + planeb, v[2]);
+    store_node<S, NL>(rd[1], mN, 0u, v[3]);
+    store_node<S, NL>(rd[1], mN, planeb, v[4]);
+    store_node<S, NL>(rd[1], mC, 2u * planeb, v[5]);
+    store_node<S, NL>(rd[2], mS, 0u, v[6]);
+    store_node<S, NL>(rd[2], mS, planeb, v[7]);
+    store_node<S, NL>(rd[2], mS, 2u * planeb, v[8]);
   };
 
   const int niter = (y1 - y0) + 4;

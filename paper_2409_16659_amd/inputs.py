@@ -136,15 +136,16 @@ WORKLOADS = {
     "film3_2d_4096": dict(make=lambda: _film3(4096, 4096), hbar=(1.0, 0.8, 0.6),
                           noise="uniform", amp=1e-3, seed=2, steps=1_000,
                           precision="f32"),
-    # 4 layers, 4096^2, 16-bit population storage
+    # 4 layers, 4096^2, 16-bit population storage (IEEE-half moving
+    # populations; the rest population, which carries the height, in FP32)
     "film4_2d_4096": dict(make=lambda: _film4(4096, 4096), hbar=(1.0, 0.8, 0.6, 0.4),
                           noise="lognormal", amp=1e-3, seed=4, steps=50_000,
-                          precision="f16dev"),
+                          precision="f16mix"),
     # the [0:512, 0:512] window of the 4096^2 fields above, run as its own
     # periodic domain (accuracy of the 16-bit storage against FP64)
     "film4_2d_512": dict(make=lambda: _film4(512, 512), crop_of="film4_2d_4096",
                          hbar=(1.0, 0.8, 0.6, 0.4), noise="lognormal", amp=1e-3,
-                         seed=4, steps=50_000, precision="f16dev"),
+                         seed=4, steps=50_000, precision="f16mix"),
 }
 
 

@@ -90,10 +90,11 @@ def test_query_sizes_and_validation():
     q.precision = 6
     with pytest.raises(mlfilm.MlfError):
         mlfilm.query_sizes(q)
-    # one layer must fit a 2 GiB buffer descriptor
-    big = inputs.film_params(1, 8192, 7281, gamma=[1], mu=[1], hstar=0.1)
-    assert mlfilm.query_sizes(mlfilm.make_params(big, "f32"))[0] == 8192 * 7281 * 9 * 4 <= 2 ** 31
-    big["ny"] = 7282
+    # each group of three planes must fit a 2 GiB buffer descriptor
+    big = inputs.film_params(1, 16384, 10922, gamma=[1], mu=[1], hstar=0.1)
+    assert mlfilm.query_sizes(mlfilm.make_params(big, "f32"))[0] == 16384 * 10922 * 9 * 4
+    assert 16384 * 10922 * 3 * 4 <= 2 ** 31
+    big["ny"] = 10923
     with pytest.raises(mlfilm.MlfError) as e:
         mlfilm.query_sizes(mlfilm.make_params(big, "f32"))
     assert e.value.status == "EUNSUPPORTED"

@@ -200,24 +200,24 @@ def test_flat_film_fixed_point(mlf):
 
 def _shift_blob(g, blob, dx, dy):
     """Roll the raw population payload of a checkpoint by a lattice vector
-    (per layer: the rest plane, then eight moving planes)."""
+    (the rest plane, then eight moving planes; each node holds the layers'
+    values next to each other)."""
     from paper_2409_16659_amd import mlfilm
 
     pitch = mlf_pitch(g)
     rb, mb = mlfilm.PLANE_BYTES[g.params.precision]
     raw = {8: np.uint64, 4: np.uint32, 2: np.uint16}
     head = len(blob) - g.pop_bytes
-    plane = g.ny * pitch
-    layer = plane * (rb + 8 * mb)
+    nodes = g.ny * pitch
     out = bytearray(blob[:head])
-    for i in range(g.n):
-        base = head + i * layer
-        for k in range(9):
-            off = base + (0 if k == 0 else plane * (rb + (k - 1) * mb))
-            sz = rb if k == 0 else mb
-            a = np.frombuffer(blob[off:off + plane * sz], dtype=raw[sz]).reshape(g.ny, pitch).copy()
-            a[:, : g.nx] = np.roll(np.roll(a[:, : g.nx], dx, axis=1), dy, axis=0)
-            out += a.tobytes()
+    off = head
+    for k in range(9):
+        sz = rb if k == 0 else mb
+        a = np.frombuffer(blob[off:off + nodes * g.n * sz], dtype=raw[sz]).reshape(g.ny, pitch, g.n).copy()
+        a[:, : g.nx] = np.roll(np.roll(a[:, : g.nx], dx, axis=1), dy, axis=0)
+        out += a.tobytes()
+        off += nodes * g.n * sz
+    assert off == len(blob)
     return bytes(out)
 
 
