@@ -502,6 +502,7 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
       k.sa[l][kk - 1] = C(S * a / (a - b));
       k.sb[l][kk - 1] = C(S * b / (a - b));
       k.sab[l][kk - 1] = C(S * a * b / (a - b));
+      if (S != 0.0) k.pairs |= 1u << (l * 4 + kk - 1);
     }
   for (int kk = 1; kk <= kMaxLayers; ++kk) k.khs[kk - 1] = C(kk * p.hstar);
   k.omega = C(1.0 / p.tau);

@@ -90,6 +90,7 @@ struct StepConsts {
   C omega;                           // 1/tau
   C scale[kMaxLayers], iscale[kMaxLayers];  // storage scale per layer (16-bit formats)
   int ea, eb;                        // runtime exponents (generic path)
+  unsigned pairs;                    // bit l*4 + k-1 set: S_lk != 0
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
 };
 
@@ -422,7 +423,11 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   const int niter = (y1 - y0) + 4;
   const int rstart = dir > 0 ? y0 - 2 : y1 + 1;  // row of iteration 0
 
-  auto body = [&](int it, C (&fc)[NL][kQ], C (&fn)[NL][kQ]) {
+  // store_tag: std::true_type for rows that collide and stream, false_type
+  // for the four warm-up rows of a segment (no output row yet: no P3, no
+  // stores).
+  auto body = [&](auto store_tag, int it, C (&fc)[NL][kQ], C (&fn)[NL][kQ]) {
+    constexpr bool kStore = decltype(store_tag)::value;
     const int r = rstart + dir * it;
     // ---- P1: moments and interface deviations of row r ------------------
     {
@@ -482,6 +487,8 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
       for (int l = 0; l < NL; ++l) {
 #pragma unroll
         for (int kk = 1; kk <= NL - l; ++kk) {
+          // pairs with S_lk = 0 contribute exactly zero (uniform branch)
+          if (!(kc.pairs >> (l * 4 + kk - 1) & 1u)) continue;
           const C d = kc.dbar[l][kk - 1] + (dzv[l + kk] - dzv[l]);
           const C rd = rcp(d);
           const C rr = kc.khs[kk - 1] * rd;
@@ -506,123 +513,125 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     }
     __syncthreads();
     // ---- P3: force, collision and streaming of row y = r - 2 dir ------------
-    const bool st_ok = it >= 4 && act3;
-    const int y = wrap(r - 2 * dir, kc.ny);
-    const uint32_t oC = (uint32_t)y * rowb + bx;
-    const uint32_t oS = (uint32_t)wrap(y - 1, kc.ny) * rowb + bx;
-    const uint32_t oN = (uint32_t)wrap(y + 1, kc.ny) * rowb + bx;
-    const uint32_t oR = (uint32_t)y * rowbr + bxr;
-    C fo[NL][kQ];
-    if (st_ok) {
-      const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
-      const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
-      C h[NL], ux[NL], uy[NL], g[NL + 1];
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        h[i] = kc.hbar[i] + dh2[i];
-        const C rh = rcp(h[i]);
-        ux[i] = qx2[i] * rh;
-        uy[i] = qy2[i] * rh;
-        g[i] = kc.mu[i] * rh;
-      }
-      g[NL] = C(0);
-      // Thomas elimination for the interface velocities (x and y share pivots)
-      C cpr[NL], vx[NL], vy[NL];
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const C diag = C(2) * (g[i] + g[i + 1]);
-        const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
-        const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
-        if (i == 0) {
-          const C im = rcp(diag);
-          cpr[i] = g[i + 1] * im;
-          vx[i] = rx * im;
-          vy[i] = ry * im;
-        } else {
-          const C im = rcp(diag - g[i] * cpr[i - 1]);
-          cpr[i] = g[i + 1] * im;
-          vx[i] = (rx - g[i] * vx[i - 1]) * im;
-          vy[i] = (ry - g[i] * vy[i - 1]) * im;
+    if constexpr (kStore) {
+      const bool st_ok = it >= 4 && act3;
+      const int y = wrap(r - 2 * dir, kc.ny);
+      const uint32_t oC = (uint32_t)y * rowb + bx;
+      const uint32_t oS = (uint32_t)wrap(y - 1, kc.ny) * rowb + bx;
+      const uint32_t oN = (uint32_t)wrap(y + 1, kc.ny) * rowb + bx;
+      const uint32_t oR = (uint32_t)y * rowbr + bxr;
+      C fo[NL][kQ];
+      if (st_ok) {
+        const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
+        const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
+        C h[NL], ux[NL], uy[NL], g[NL + 1];
+  #pragma unroll
+        for (int i = 0; i < NL; ++i) {
+          h[i] = kc.hbar[i] + dh2[i];
+          const C rh = rcp(h[i]);
+          ux[i] = qx2[i] * rh;
+          uy[i] = qy2[i] * rh;
+          g[i] = kc.mu[i] * rh;
         }
-      }
-#pragma unroll
-      for (int i = NL - 2; i >= 0; --i) {
-        vx[i] -= cpr[i] * vx[i + 1];
-        vy[i] -= cpr[i] * vy[i + 1];
-      }
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const C* a = pr + (pS * NL + i) * W + tid;
-        const C* c = pr + (pC * NL + i) * W + tid;
-        const C* n = pr + (pN * NL + i) * W + tid;
-        const C sw = a[-1], s = a[0], se = a[1];
-        const C wv = c[-1], e = c[1];
-        const C nw = n[-1], nn = n[0], ne = n[1];
-        const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
-        const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
-        const C vlo_x = i > 0 ? vx[i - 1] : C(0), vlo_y = i > 0 ? vy[i - 1] : C(0);
-        const C frx = C(6) * g[i] * ((vlo_x + vx[i]) - C(2) * ux[i]);
-        const C fry = C(6) * g[i] * ((vlo_y + vy[i]) - C(2) * uy[i]);
-        const C Fx = -h[i] * gpx + frx;
-        const C Fy = -h[i] * gpy + fry;
-        const C qx = qx2[i], qy = qy2[i];
-        const C qu = qx * ux[i] + qy * uy[i];
-        const C t15 = C(1.5) * qu;
-        // Shallow-water equilibrium with the rest population as deviation
-        // from hbar, split into its even part (quadratic in U, shared by
-        // opposite directions) and odd part c.q/c_s^2 w_k; the forcing
-        // 3 w_k c_k.F is odd too.  With q_k = c_k.q and u_k = c_k.U:
-        //   f^eq_k = w_k (3 q_k + 4.5 q_k u_k - 1.5 q.U),  k >= 1.
-        const C ex = C(1.0 / 9.0) * (C(4.5) * qx * ux[i] - t15);  // axial x, even
-        const C ey = C(1.0 / 9.0) * (C(4.5) * qy * uy[i] - t15);  // axial y, even
-        const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
-        const C ep = C(1.0 / 36.0) * (C(4.5) * spq * spu - t15);  // diagonal (1,1), even
-        const C em = C(1.0 / 36.0) * (C(4.5) * smq * smu - t15);  // diagonal (-1,1), even
-        C ox, oy;                                                  // axial odd parts
-        if constexpr (TAU1) {
-          ox = C(1.0 / 3.0) * (qx + Fx);
-          oy = C(1.0 / 3.0) * (qy + Fy);
-          fo[i][0] = dh2[i] - C(2.0 / 3.0) * qu;
-        } else {
-          const C w = kc.omega;
-          ox = C(1.0 / 3.0) * (w * qx + Fx);
-          oy = C(1.0 / 3.0) * (w * qy + Fy);
-          fo[i][0] = w * (dh2[i] - C(2.0 / 3.0) * qu);
+        g[NL] = C(0);
+        // Thomas elimination for the interface velocities (x and y share pivots)
+        C cpr[NL], vx[NL], vy[NL];
+  #pragma unroll
+        for (int i = 0; i < NL; ++i) {
+          const C diag = C(2) * (g[i] + g[i + 1]);
+          const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
+          const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
+          if (i == 0) {
+            const C im = rcp(diag);
+            cpr[i] = g[i + 1] * im;
+            vx[i] = rx * im;
+            vy[i] = ry * im;
+          } else {
+            const C im = rcp(diag - g[i] * cpr[i - 1]);
+            cpr[i] = g[i + 1] * im;
+            vx[i] = (rx - g[i] * vx[i - 1]) * im;
+            vy[i] = (ry - g[i] * vy[i - 1]) * im;
+          }
         }
-        const C op = C(0.25) * (ox + oy), om = C(0.25) * (oy - ox);  // diagonal odd parts
-        C gx = ex, gy = ey, gp = ep, gm = em;
-        if constexpr (!TAU1) {
-          gx = kc.omega * ex;
-          gy = kc.omega * ey;
-          gp = kc.omega * ep;
-          gm = kc.omega * em;
+  #pragma unroll
+        for (int i = NL - 2; i >= 0; --i) {
+          vx[i] -= cpr[i] * vx[i + 1];
+          vy[i] -= cpr[i] * vy[i + 1];
         }
-        fo[i][1] = gx + ox;
-        fo[i][5] = gx - ox;
-        fo[i][3] = gy + oy;
-        fo[i][7] = gy - oy;
-        fo[i][2] = gp + op;
-        fo[i][6] = gp - op;
-        fo[i][4] = gm + om;
-        fo[i][8] = gm - om;
+  #pragma unroll
+        for (int i = 0; i < NL; ++i) {
+          const C* a = pr + (pS * NL + i) * W + tid;
+          const C* c = pr + (pC * NL + i) * W + tid;
+          const C* n = pr + (pN * NL + i) * W + tid;
+          const C sw = a[-1], s = a[0], se = a[1];
+          const C wv = c[-1], e = c[1];
+          const C nw = n[-1], nn = n[0], ne = n[1];
+          const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
+          const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
+          const C vlo_x = i > 0 ? vx[i - 1] : C(0), vlo_y = i > 0 ? vy[i - 1] : C(0);
+          const C frx = C(6) * g[i] * ((vlo_x + vx[i]) - C(2) * ux[i]);
+          const C fry = C(6) * g[i] * ((vlo_y + vy[i]) - C(2) * uy[i]);
+          const C Fx = -h[i] * gpx + frx;
+          const C Fy = -h[i] * gpy + fry;
+          const C qx = qx2[i], qy = qy2[i];
+          const C qu = qx * ux[i] + qy * uy[i];
+          const C t15 = C(1.5) * qu;
+          // Shallow-water equilibrium with the rest population as deviation
+          // from hbar, split into its even part (quadratic in U, shared by
+          // opposite directions) and odd part c.q/c_s^2 w_k; the forcing
+          // 3 w_k c_k.F is odd too.  With q_k = c_k.q and u_k = c_k.U:
+          //   f^eq_k = w_k (3 q_k + 4.5 q_k u_k - 1.5 q.U),  k >= 1.
+          const C ex = C(1.0 / 9.0) * (C(4.5) * qx * ux[i] - t15);  // axial x, even
+          const C ey = C(1.0 / 9.0) * (C(4.5) * qy * uy[i] - t15);  // axial y, even
+          const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
+          const C ep = C(1.0 / 36.0) * (C(4.5) * spq * spu - t15);  // diagonal (1,1), even
+          const C em = C(1.0 / 36.0) * (C(4.5) * smq * smu - t15);  // diagonal (-1,1), even
+          C ox, oy;                                                  // axial odd parts
+          if constexpr (TAU1) {
+            ox = C(1.0 / 3.0) * (qx + Fx);
+            oy = C(1.0 / 3.0) * (qy + Fy);
+            fo[i][0] = dh2[i] - C(2.0 / 3.0) * qu;
+          } else {
+            const C w = kc.omega;
+            ox = C(1.0 / 3.0) * (w * qx + Fx);
+            oy = C(1.0 / 3.0) * (w * qy + Fy);
+            fo[i][0] = w * (dh2[i] - C(2.0 / 3.0) * qu);
+          }
+          const C op = C(0.25) * (ox + oy), om = C(0.25) * (oy - ox);  // diagonal odd parts
+          C gx = ex, gy = ey, gp = ep, gm = em;
+          if constexpr (!TAU1) {
+            gx = kc.omega * ex;
+            gy = kc.omega * ey;
+            gp = kc.omega * ep;
+            gm = kc.omega * em;
+          }
+          fo[i][1] = gx + ox;
+          fo[i][5] = gx - ox;
+          fo[i][3] = gy + oy;
+          fo[i][7] = gy - oy;
+          fo[i][2] = gp + op;
+          fo[i][6] = gp - op;
+          fo[i][4] = gm + om;
+          fo[i][8] = gm - om;
+        }
+      } else {
+  #pragma unroll
+        for (int i = 0; i < NL; ++i)
+  #pragma unroll
+          for (int k = 0; k < kQ; ++k) fo[i][k] = C(0);
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NL; ++i)
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) fo[i][k] = C(0);
+      if constexpr (!TAU1) {
+        // f* = (1 - omega) f + [omega f^eq + forcing]; the pre-collision
+        // populations of row y are re-read (cache hits: loaded two rows ago)
+        C fy[NL][kQ];
+        load_row(y, st_ok, fy);
+  #pragma unroll
+        for (int i = 0; i < NL; ++i)
+  #pragma unroll
+          for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
+      }
+      store_row(st_ok, oS, oC, oN, oR, fo);
     }
-    if constexpr (!TAU1) {
-      // f* = (1 - omega) f + [omega f^eq + forcing]; the pre-collision
-      // populations of row y are re-read (cache hits: loaded two rows ago)
-      C fy[NL][kQ];
-      load_row(y, st_ok, fy);
-#pragma unroll
-      for (int i = 0; i < NL; ++i)
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
-    }
-    store_row(st_ok, oS, oC, oN, oR, fo);
     // rotate the moment pipeline
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
@@ -636,6 +645,15 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
   };
 
   load_row(rstart, true, fa);
+  int it = 0;
+  if constexpr (TAU1) {
+    // warm-up rows (niter >= 5 always): P1 and P2 only
+    body(std::false_type{}, 0, fa, fb);
+    body(std::false_type{}, 1, fb, fa);
+    body(std::false_type{}, 2, fa, fb);
+    body(std::false_type{}, 3, fb, fa);
+    it = 4;
+  }
   {
     // dropped stores: the loop is entered with the same pending sequence
     // (loads, then stores) as every later iteration
@@ -646,12 +664,11 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
       for (int k = 0; k < kQ; ++k) zero[i][k] = C(0);
     store_row(false, 0, 0, 0, 0, zero);
   }
-  int it = 0;
   for (; it + 1 < niter; it += 2) {
-    body(it, fa, fb);
-    body(it + 1, fb, fa);
+    body(std::true_type{}, it, fa, fb);
+    body(std::true_type{}, it + 1, fb, fa);
   }
-  if (it < niter) body(it, fa, fb);
+  if (it < niter) body(std::true_type{}, it, fa, fb);
 }
 
 }  // namespace mlf
