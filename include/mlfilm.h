@@ -170,6 +170,67 @@ int64_t mlf_steps_done(const mlf_handle* h);
 const char* mlf_last_error(const mlf_handle* h);
 mlf_status mlf_destroy(mlf_handle* h);
 
+/* ---- batches of independent films ------------------------------------
+ * Many films (the paper's parameter sweeps over wavenumber, tension,
+ * contact angle and layer count, Sec. IV) advanced together: every step
+ * is ONE kernel launch over a work list of (film, tile) items, largest
+ * film first, with each film's constants in a device table; films may
+ * differ in size, layer count and every physical parameter but share the
+ * precision, tau and the wetting exponents.  Results of each film are
+ * bit-identical to stepping it alone with the same launch shape.
+ * Conventions as above; device memory is caller-owned. */
+typedef struct mlf_batch mlf_batch;
+
+/* Sizes of each of the two population buffers (the films' buffers back to
+ * back, 256-byte aligned) and of the scratch buffer.  EINVAL / EUNSUPPORTED
+ * as mlf_query_sizes, also for films that do not share precision, tau and
+ * exponents, or n outside 1..4096. */
+mlf_status mlf_batch_query_sizes(const mlf_params* films, int32_t n, size_t* pop_bytes, size_t* scratch_bytes);
+
+/* Bind n films to caller-owned buffers (sizes from mlf_batch_query_sizes,
+ * 256-byte aligned) and a stream.  A non-default stream is needed for
+ * mlf_batch_capture. */
+mlf_status mlf_batch_create(const mlf_params* films, int32_t n, void* pop_a, void* pop_b, void* scratch,
+                            void* stream, mlf_batch** out);
+
+/* Initialise film `film` exactly as mlf_init does for one film (same
+ * checks and errors).  Every film must be initialised before stepping. */
+mlf_status mlf_batch_init(mlf_batch* b, int32_t film, const double* hgt, const double* ux, const double* uy);
+
+/* Advance every film by nsteps >= 0 steps: one launch per step, or replays
+ * of the captured graph where it fits.  The guard flags of all films are
+ * read at the end; a tripped film gives ENONPOSITIVE / ENONFINITE and
+ * mlf_batch_failed_film names it. */
+mlf_status mlf_batch_step(mlf_batch* b, int64_t nsteps);
+
+/* Capture `steps` (even, > 0) consecutive batch launches into a HIP graph
+ * that mlf_batch_step replays; 0 drops the graph.  Changing the launch
+ * shape drops it too.  EUNSUPPORTED on the default stream. */
+mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps);
+
+/* Read-back and FP64 per-layer mass of one film, as mlf_read and
+ * mlf_layer_mass (synchronise). */
+mlf_status mlf_batch_read(mlf_batch* b, int32_t film, double* hgt, double* ux, double* uy);
+mlf_status mlf_batch_layer_mass(mlf_batch* b, int32_t film, double* mass);
+
+/* Launch shape shared by all films: block_w in {64, 128, 192, 256}, seg_h
+ * >= 1 rows (clamped to each film's ny), persistent != 0: as many
+ * workgroups as fit the device at once, each taking work items in turn;
+ * 0: one workgroup per item.  0 for block_w / seg_h selects 256 / 8.
+ * EINVAL if the work list would exceed its scratch area. */
+mlf_status mlf_batch_set_launch(mlf_batch* b, int32_t block_w, int32_t seg_h, int32_t persistent);
+mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* seg_h, int32_t* persistent);
+
+/* Autotuner over block_w x seg_h x persistent, `reps` timed launches each
+ * from the current buffer into the other (state unchanged); keeps the
+ * fastest.  Drops a captured graph.  Synchronises. */
+mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int32_t* seg_h, int32_t* persistent);
+
+int64_t mlf_batch_steps_done(const mlf_batch* b);
+int32_t mlf_batch_failed_film(const mlf_batch* b);  /* -1 if none */
+const char* mlf_batch_last_error(const mlf_batch* b);
+mlf_status mlf_batch_destroy(mlf_batch* b);
+
 /* ---- host helpers (no device work) ---------------------------------- */
 
 /* Spreading coefficients from a full symmetric tension table

@@ -16,9 +16,12 @@ HEADERS = [os.path.join(CSRC, "step_kernel.hpp"), os.path.join(ROOT, "include", 
 ARCH = os.environ.get("MLF_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code; -O3 would
-# otherwise form them from scalar float code.
+# otherwise form them from scalar float code.  Multiply-adds are fused only
+# within one source expression (-ffp-contract=on), so that the same kernel
+# body rounds identically in every kernel it is inlined into (single film,
+# batch).
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
 ]

@@ -1124,3 +1124,479 @@ mlf_status mlf_friction_matrix(int32_t n, const double* hh, const double* mu, do
 }
 
 }  // extern "C"
+
+// ============================================================ batches ====
+// Many independent films advanced together: one launch per step over a
+// work list of (film, tile) items, per-film step constants in a device
+// table, optionally replayed from a captured HIP graph.  Each film is
+// served by an internal single-film handle on its slice of the batch
+// buffers, which provides initialisation, read-back and mass.
+
+namespace {
+
+constexpr int kMaxFilms = 4096;
+constexpr size_t kBatchFlagOff = (kScratchBytes + 255) / 256 * 256;        // int flags[kMaxFilms]
+constexpr size_t kBatchTableOff = kBatchFlagOff + kMaxFilms * sizeof(int);  // BatchFilm<C>[n]
+constexpr size_t kBatchTableBytes = 4u << 20;
+constexpr size_t kBatchItemOff = kBatchTableOff + kBatchTableBytes;         // int2[n_items]
+constexpr size_t kBatchItemBytes = 12u << 20;
+constexpr size_t kBatchScratchBytes = kBatchItemOff + kBatchItemBytes;
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+}  // namespace
+
+struct mlf_batch {
+  int n;
+  mlf_params p0;                     // precision, tau and exponents shared by all films
+  std::vector<mlf_handle*> film;
+  std::vector<size_t> offset;        // byte offset of each film in a population buffer
+  std::vector<int> order;            // films, most layer-node updates first
+  std::vector<bool> ready;
+  unsigned char* pop[2];
+  int cur;
+  unsigned char* scratch;
+  hipStream_t stream;
+  int block_w, seg_h, persistent;
+  int max_nl;
+  int n_items;
+  bool table_dirty;
+  hipGraphExec_t graph;
+  int graph_steps, graph_parity;
+  int64_t steps;
+  int failed;
+  std::string err;
+};
+
+namespace {
+
+mlf_status bfail(mlf_batch* b, mlf_status st, const std::string& m) {
+  if (b) b->err = m;
+  return st;
+}
+
+mlf_status bhip(mlf_batch* b, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MLF_OK;
+  return bfail(b, MLF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BHIPCHK(call)                                             \
+  do {                                                            \
+    mlf_status _s = bhip(b, (call), #call);                       \
+    if (_s != MLF_OK) return _s;                                  \
+  } while (0)
+
+mlf_status validate_batch(const mlf_params* films, int n, std::string* why) {
+  if (!films || n < 1 || n > kMaxFilms) {
+    if (why) *why = "need 1..4096 films";
+    return MLF_EINVAL;
+  }
+  for (int f = 0; f < n; ++f) {
+    mlf_status st = validate(&films[f], why);
+    if (st != MLF_OK) return st;
+    if (films[f].precision != films[0].precision || films[f].tau != films[0].tau ||
+        films[f].exp_a != films[0].exp_a || films[f].exp_b != films[0].exp_b) {
+      if (why) *why = "films of a batch share precision, tau and exponents";
+      return MLF_EUNSUPPORTED;
+    }
+  }
+  return MLF_OK;
+}
+
+size_t film_bytes(const mlf_params* p) {
+  return align256(buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny));
+}
+
+bool batch_double(const mlf_batch* b) { return b->p0.precision == MLF_F64; }
+
+size_t batch_table_entry(const mlf_batch* b) {
+  return batch_double(b) ? sizeof(mlf::BatchFilm<double>) : sizeof(mlf::BatchFilm<float>);
+}
+
+int* batch_flags(mlf_batch* b) { return reinterpret_cast<int*>(b->scratch + kBatchFlagOff); }
+
+// Tiles of film f under the batch's launch shape.
+long long film_tiles(const mlf_batch* b, int f, int bw, int sh) {
+  const mlf_params& p = b->film[f]->p;
+  const int s = std::min(sh, p.ny);
+  return (long long)mlf::strip_count(p.nx, bw) * ((p.ny + s - 1) / s);
+}
+
+long long batch_items(const mlf_batch* b, int bw, int sh) {
+  long long t = 0;
+  for (int f = 0; f < b->n; ++f) t += film_tiles(b, f, bw, sh);
+  return t;
+}
+
+// Device table and work list for the current launch shape (synchronous).
+template <typename C>
+mlf_status upload_table_t(mlf_batch* b) {
+  std::vector<mlf::BatchFilm<C>> tab(b->n);
+  std::vector<int2> items;
+  items.reserve((size_t)b->n_items);
+  for (int f = 0; f < b->n; ++f) {
+    mlf_handle* h = b->film[f];
+    h->block_w = b->block_w;
+    h->seg_h = std::min(b->seg_h, h->p.ny);
+    std::memset(&tab[f], 0, sizeof(tab[f]));
+    tab[f].kc = make_consts<C>(h);
+    tab[f].kc.flag = batch_flags(b) + f;
+    tab[f].offset = (long long)b->offset[f];
+    tab[f].nl = h->p.n_layers;
+  }
+  for (int f : b->order) {
+    const int nt = tab[f].kc.nstrip * tab[f].kc.nseg;
+    for (int t = 0; t < nt; ++t) items.push_back(make_int2(f, t));
+  }
+  BHIPCHK(hipMemcpyAsync(b->scratch + kBatchTableOff, tab.data(), tab.size() * sizeof(tab[0]),
+                         hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(hipMemcpyAsync(b->scratch + kBatchItemOff, items.data(), items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  b->n_items = (int)items.size();
+  b->table_dirty = false;
+  return MLF_OK;
+}
+
+mlf_status upload_table(mlf_batch* b) {
+  b->n_items = (int)batch_items(b, b->block_w, b->seg_h);
+  return batch_double(b) ? upload_table_t<double>(b) : upload_table_t<float>(b);
+}
+
+template <typename R, typename S, typename C, bool T1, int EA, int EB>
+hipError_t launch_batch_t(const mlf_batch* b, int flip, int* occ) {
+  auto kern = mlf::batch_kernel<R, S, C, T1, EA, EB>;
+  const size_t lds = (size_t)8 * b->max_nl * b->block_w * sizeof(C);
+  if (occ) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, b->block_w, lds);
+    *occ = nb;
+    return e;
+  }
+  int grid = (b->n_items + mlf::kXcds - 1) / mlf::kXcds * mlf::kXcds;
+  if (b->persistent) {
+    int nb = 0, dev = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, b->block_w, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int slots = std::max(1, nb) * std::max(1, ncu) / mlf::kXcds * mlf::kXcds;
+    grid = std::max(mlf::kXcds, std::min(grid, slots));
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)b->block_w), lds, b->stream,
+                     reinterpret_cast<const mlf::BatchFilm<C>*>(b->scratch + kBatchTableOff),
+                     reinterpret_cast<const int2*>(b->scratch + kBatchItemOff), b->n_items, b->pop[0], b->pop[1],
+                     flip);
+  return hipGetLastError();
+}
+
+template <typename R, typename S, typename C>
+hipError_t launch_batch_sc(const mlf_batch* b, int flip, int* occ) {
+  const bool t1 = b->p0.tau == 1.0;
+  const bool e93 = b->p0.exp_a == 9 && b->p0.exp_b == 3;
+  if (t1 && e93) return launch_batch_t<R, S, C, true, 9, 3>(b, flip, occ);
+  if (t1) return launch_batch_t<R, S, C, true, 0, 0>(b, flip, occ);
+  if (e93) return launch_batch_t<R, S, C, false, 9, 3>(b, flip, occ);
+  return launch_batch_t<R, S, C, false, 0, 0>(b, flip, occ);
+}
+
+// One step of every film from buffer `flip` into the other one.
+hipError_t launch_batch(const mlf_batch* b, int flip) {
+  hipError_t e = hipSuccess;
+  by_storage(b->film[0], [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    using C = std::conditional_t<std::is_same_v<S, double>, double, float>;
+    e = launch_batch_sc<R, S, C>(b, flip, nullptr);
+  });
+  return e;
+}
+
+void drop_graph(mlf_batch* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_steps = 0;
+}
+
+mlf_status batch_ready(mlf_batch* b) {
+  for (int f = 0; f < b->n; ++f)
+    if (!b->ready[f]) return bfail(b, MLF_EINVAL, "film " + std::to_string(f) + " is not initialised");
+  if (b->table_dirty) return upload_table(b);
+  return MLF_OK;
+}
+
+mlf_status batch_guard(mlf_batch* b) {
+  std::vector<int> flags(b->n);
+  BHIPCHK(hipMemcpyAsync(flags.data(), batch_flags(b), b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  for (int f = 0; f < b->n; ++f)
+    if (flags[f] != 0) {
+      b->failed = f;
+      const std::string where = "film " + std::to_string(f) + " at or before step " + std::to_string(b->steps);
+      if (flags[f] == 1) return bfail(b, MLF_ENONPOSITIVE, "a layer height became <= 0 in " + where);
+      return bfail(b, MLF_ENONFINITE, "a layer height or flux became non-finite in " + where);
+    }
+  return MLF_OK;
+}
+
+mlf_status film_index(mlf_batch* b, int f) {
+  if (f < 0 || f >= b->n) return bfail(b, MLF_EINVAL, "film index out of range");
+  return MLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlf_status mlf_batch_query_sizes(const mlf_params* films, int32_t n, size_t* pop_bytes, size_t* scratch_bytes) {
+  mlf_status st = validate_batch(films, n, nullptr);
+  if (st != MLF_OK) return st;
+  size_t total = 0;
+  for (int f = 0; f < n; ++f) total += film_bytes(&films[f]);
+  if (pop_bytes) *pop_bytes = total;
+  if (scratch_bytes) *scratch_bytes = kBatchScratchBytes;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_create(const mlf_params* films, int32_t n, void* pop_a, void* pop_b, void* scratch,
+                            void* stream, mlf_batch** out) {
+  if (!out) return MLF_EINVAL;
+  *out = nullptr;
+  std::string why;
+  mlf_status st = validate_batch(films, n, &why);
+  if (st != MLF_OK) return st;
+  if (!pop_a || !pop_b || !scratch || pop_a == pop_b) return MLF_EINVAL;
+  auto aligned = [](void* v) { return (reinterpret_cast<uintptr_t>(v) & 255) == 0; };
+  if (!aligned(pop_a) || !aligned(pop_b) || !aligned(scratch)) return MLF_EINVAL;
+  mlf_batch* b = new (std::nothrow) mlf_batch();
+  if (!b) return MLF_EINVAL;
+  b->n = n;
+  b->p0 = films[0];
+  b->pop[0] = static_cast<unsigned char*>(pop_a);
+  b->pop[1] = static_cast<unsigned char*>(pop_b);
+  b->cur = 0;
+  b->scratch = static_cast<unsigned char*>(scratch);
+  b->stream = static_cast<hipStream_t>(stream);
+  b->max_nl = 1;
+  size_t off = 0;
+  for (int f = 0; f < n; ++f) {
+    mlf_handle* h = nullptr;
+    st = mlf_create(&films[f], b->pop[0] + off, b->pop[1] + off, scratch, stream, &h);
+    if (st != MLF_OK) {
+      for (mlf_handle* g : b->film) mlf_destroy(g);
+      delete b;
+      return st;
+    }
+    b->film.push_back(h);
+    b->offset.push_back(off);
+    off += film_bytes(&films[f]);
+    b->max_nl = std::max(b->max_nl, films[f].n_layers);
+  }
+  b->ready.assign(n, false);
+  b->order.resize(n);
+  for (int f = 0; f < n; ++f) b->order[f] = f;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
+    auto lu = [&](int f) { return (long long)films[f].n_layers * films[f].nx * films[f].ny; };
+    return lu(a) > lu(c);
+  });
+  b->block_w = 256;
+  b->seg_h = 8;
+  b->persistent = 0;
+  if (batch_items(b, b->block_w, b->seg_h) * (long long)sizeof(int2) > (long long)kBatchItemBytes ||
+      (size_t)n * batch_table_entry(b) > kBatchTableBytes) {
+    for (mlf_handle* g : b->film) mlf_destroy(g);
+    delete b;
+    return MLF_EUNSUPPORTED;
+  }
+  b->table_dirty = true;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+  b->graph_parity = 0;
+  b->steps = 0;
+  b->failed = -1;
+  *out = b;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_init(mlf_batch* b, int32_t film, const double* hgt, const double* ux, const double* uy) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  b->ready[film] = false;
+  st = mlf_init(h, hgt, ux, uy);
+  if (st != MLF_OK) return bfail(b, st, "film " + std::to_string(film) + ": " + h->err);
+  BHIPCHK(hipMemsetAsync(batch_flags(b) + film, 0, sizeof(int), b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  b->ready[film] = true;
+  b->table_dirty = true;  // reference heights and scales changed
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_step(mlf_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return MLF_EINVAL;
+  mlf_status st = batch_ready(b);
+  if (st != MLF_OK) return st;
+  b->failed = -1;
+  int64_t left = nsteps;
+  while (left > 0) {
+    if (b->graph && b->cur == b->graph_parity && left >= b->graph_steps) {
+      BHIPCHK(hipGraphLaunch(b->graph, b->stream));
+      left -= b->graph_steps;
+      b->steps += b->graph_steps;
+    } else {
+      BHIPCHK(launch_batch(b, b->cur));
+      b->cur ^= 1;
+      left -= 1;
+      b->steps += 1;
+    }
+  }
+  return batch_guard(b);
+}
+
+mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps) {
+  if (!b) return MLF_EINVAL;
+  drop_graph(b);
+  if (steps == 0) return MLF_OK;
+  if (steps < 0 || steps % 2 != 0) return bfail(b, MLF_EINVAL, "graph steps must be even and >= 0");
+  if (!b->stream) return bfail(b, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
+  mlf_status st = batch_ready(b);
+  if (st != MLF_OK) return st;
+  BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int t = 0; t < steps && le == hipSuccess; ++t) le = launch_batch(b, (b->cur + t) & 1);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(b->stream, &g);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bhip(b, le != hipSuccess ? le : ee, "graph capture");
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return bhip(b, ie, "hipGraphInstantiate");
+  b->graph = ex;
+  b->graph_steps = steps;
+  b->graph_parity = b->cur;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_read(mlf_batch* b, int32_t film, double* hgt, double* ux, double* uy) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  st = mlf_read(h, hgt, ux, uy);
+  return st == MLF_OK ? st : bfail(b, st, h->err);
+}
+
+mlf_status mlf_batch_layer_mass(mlf_batch* b, int32_t film, double* mass) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  st = mlf_layer_mass(h, mass);
+  return st == MLF_OK ? st : bfail(b, st, h->err);
+}
+
+mlf_status mlf_batch_set_launch(mlf_batch* b, int32_t block_w, int32_t seg_h, int32_t persistent) {
+  if (!b) return MLF_EINVAL;
+  const int bw = block_w == 0 ? 256 : block_w, sh = seg_h == 0 ? 8 : seg_h;
+  if (bw != 64 && bw != 128 && bw != 192 && bw != 256)
+    return bfail(b, MLF_EINVAL, "block_w must be 64, 128, 192 or 256");
+  if (sh < 1) return bfail(b, MLF_EINVAL, "seg_h must be >= 1");
+  if (batch_items(b, bw, sh) * (long long)sizeof(int2) > (long long)kBatchItemBytes)
+    return bfail(b, MLF_EINVAL, "launch shape gives too many work items");
+  b->block_w = bw;
+  b->seg_h = sh;
+  b->persistent = persistent != 0;
+  b->table_dirty = true;
+  drop_graph(b);
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* seg_h, int32_t* persistent) {
+  if (!b) return MLF_EINVAL;
+  if (block_w) *block_w = b->block_w;
+  if (seg_h) *seg_h = b->seg_h;
+  if (persistent) *persistent = b->persistent;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int32_t* seg_h, int32_t* persistent) {
+  if (!b || reps < 1) return MLF_EINVAL;
+  mlf_status st = batch_ready(b);
+  if (st != MLF_OK) return st;
+  drop_graph(b);
+  const int keep_w = b->block_w, keep_h = b->seg_h, keep_p = b->persistent;
+  struct Cand {
+    int w, h, p;
+  };
+  std::vector<Cand> cand;
+  for (int w : {64, 128, 192, 256})
+    for (int h : {2, 4, 6, 8, 12, 16, 24, 32, 64})
+      for (int pp : {0, 1})
+        if (batch_items(b, w, h) * (long long)sizeof(int2) <= (long long)kBatchItemBytes) cand.push_back({w, h, pp});
+  hipEvent_t e0, e1;
+  BHIPCHK(hipEventCreate(&e0));
+  BHIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  Cand pick{keep_w, keep_h, keep_p};
+  for (const Cand& c : cand) {
+    b->block_w = c.w;
+    b->seg_h = c.h;
+    b->persistent = c.p;
+    if ((st = upload_table(b)) != MLF_OK) break;
+    // current -> other buffer, never swapped: the state is left unchanged
+    if ((st = bhip(b, launch_batch(b, b->cur), "autotune launch")) != MLF_OK) break;
+    if ((st = bhip(b, hipEventRecord(e0, b->stream), "hipEventRecord")) != MLF_OK) break;
+    for (int r = 0; r < reps && st == MLF_OK; ++r) st = bhip(b, launch_batch(b, b->cur), "autotune launch");
+    if (st != MLF_OK) break;
+    if ((st = bhip(b, hipEventRecord(e1, b->stream), "hipEventRecord")) != MLF_OK) break;
+    if ((st = bhip(b, hipEventSynchronize(e1), "hipEventSynchronize")) != MLF_OK) break;
+    float ms = 0.f;
+    if ((st = bhip(b, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != MLF_OK) break;
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == MLF_OK) {
+    b->block_w = pick.w;
+    b->seg_h = pick.h;
+    b->persistent = pick.p;
+  } else {
+    b->block_w = keep_w;
+    b->seg_h = keep_h;
+    b->persistent = keep_p;
+  }
+  b->table_dirty = true;
+  mlf_status up = upload_table(b);
+  if (st != MLF_OK) return st;
+  if (up != MLF_OK) return up;
+  if (block_w) *block_w = pick.w;
+  if (seg_h) *seg_h = pick.h;
+  if (persistent) *persistent = pick.p;
+  return MLF_OK;
+}
+
+int64_t mlf_batch_steps_done(const mlf_batch* b) { return b ? b->steps : -1; }
+
+int32_t mlf_batch_failed_film(const mlf_batch* b) { return b ? b->failed : -1; }
+
+const char* mlf_batch_last_error(const mlf_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+mlf_status mlf_batch_destroy(mlf_batch* b) {
+  if (!b) return MLF_EINVAL;
+  drop_graph(b);
+  for (mlf_handle* h : b->film) mlf_destroy(h);
+  delete b;
+  return MLF_OK;
+}
+
+}  // extern "C"

@@ -304,13 +304,13 @@ __device__ inline int tile_of_block(int b, int nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// One tile (strip x segment) of one step: the whole workgroup marches the
+// segment's rows.  `tile` is uniform and < kc.nstrip * kc.nseg.
 template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
-__global__ void __launch_bounds__(256)
-step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
+__device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                                 const StepConsts<C>& kc, int tile) {
   const int W = blockDim.x;
   const int tid = threadIdx.x;
-  const int tile = tile_of_block(blockIdx.x, gridDim.x);
-  if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)
   const int strip = tile % kc.nstrip;
   const int seg = tile / kc.nstrip;
   const int x0 = strip * kc.wout;
@@ -525,7 +525,7 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
         const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
         const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
         C h[NL], ux[NL], uy[NL], g[NL + 1];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < NL; ++i) {
           h[i] = kc.hbar[i] + dh2[i];
           const C rh = rcp(h[i]);
@@ -536,7 +536,7 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
         g[NL] = C(0);
         // Thomas elimination for the interface velocities (x and y share pivots)
         C cpr[NL], vx[NL], vy[NL];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < NL; ++i) {
           const C diag = C(2) * (g[i] + g[i + 1]);
           const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
@@ -553,12 +553,12 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
             vy[i] = (ry - g[i] * vy[i - 1]) * im;
           }
         }
-  #pragma unroll
+#pragma unroll
         for (int i = NL - 2; i >= 0; --i) {
           vx[i] -= cpr[i] * vx[i + 1];
           vy[i] -= cpr[i] * vy[i + 1];
         }
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < NL; ++i) {
           const C* a = pr + (pS * NL + i) * W + tid;
           const C* c = pr + (pC * NL + i) * W + tid;
@@ -615,9 +615,9 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
           fo[i][8] = gm - om;
         }
       } else {
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < NL; ++i)
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < kQ; ++k) fo[i][k] = C(0);
       }
       if constexpr (!TAU1) {
@@ -625,9 +625,9 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
         // populations of row y are re-read (cache hits: loaded two rows ago)
         C fy[NL][kQ];
         load_row(y, st_ok, fy);
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < NL; ++i)
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
       }
       store_row(st_ok, oS, oC, oN, oR, fo);
@@ -669,6 +669,52 @@ step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     body(std::true_type{}, it + 1, fb, fa);
   }
   if (it < niter) body(std::true_type{}, it, fa, fb);
+}
+
+template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(256)
+step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
+  const int tile = tile_of_block(blockIdx.x, gridDim.x);
+  if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)
+  step_tile<R, S, C, NL, TAU1, EA, EB>(src, dst, kc, tile);
+}
+
+// ---- batches of independent films -----------------------------------------
+// Per-film entry of the device table: step constants (launch geometry
+// included), byte offset of the film's populations in both buffers, and
+// its layer count.
+template <typename C>
+struct BatchFilm {
+  StepConsts<C> kc;
+  long long offset;
+  int nl;
+  int pad;
+};
+
+// One launch advances every film of a batch by one step.  Work item w
+// (film, tile) is items[w]; items are ordered largest film first.  With
+// gridDim.x < n_items the workgroups are persistent and take items
+// w = r * gridDim.x + tile_of_block(blockIdx.x, gridDim.x), r = 0, 1, ...;
+// either way consecutive items run on one XCD.  `flip` selects the source
+// buffer (0: a -> b, 1: b -> a).
+template <typename R, typename S, typename C, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(256)
+batch_kernel(const BatchFilm<C>* __restrict__ films, const int2* __restrict__ items, int n_items,
+             unsigned char* __restrict__ buf_a, unsigned char* __restrict__ buf_b, int flip) {
+  const int slot = tile_of_block(blockIdx.x, gridDim.x);
+  for (int w = slot; w < n_items; w += gridDim.x) {
+    const int2 item = items[w];
+    const BatchFilm<C>& bf = films[item.x];
+    const unsigned char* src = (flip ? buf_b : buf_a) + bf.offset;
+    unsigned char* dst = (flip ? buf_a : buf_b) + bf.offset;
+    switch (bf.nl) {
+      case 1: step_tile<R, S, C, 1, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
+      case 2: step_tile<R, S, C, 2, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
+      case 3: step_tile<R, S, C, 3, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
+      default: step_tile<R, S, C, 4, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
+    }
+    __syncthreads();  // LDS rings are reused by the next item
+  }
 }
 
 }  // namespace mlf

@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "film_params", "young_spreading", "multimode_noise", "uniform_noise",
-    "lognormal_heights", "initial_heights", "WORKLOADS", "workload",
+    "lognormal_heights", "initial_heights", "WORKLOADS", "workload", "batch_scan",
 ]
 
 
@@ -147,6 +147,36 @@ WORKLOADS = {
                          hbar=(1.0, 0.8, 0.6, 0.4), noise="lognormal", amp=1e-3,
                          seed=4, steps=50_000, precision="f16mix"),
 }
+
+
+def batch_scan(count=256, seed=3, side_min=64, side_max=512, hstar=0.15):
+    """Films of a stability scan (the paper's parameter sweeps, Sec. IV):
+    square side uniform on the multiples of 16 in [side_min, side_max],
+    N uniform in {2, 3, 4}, gamma_i ~ U[0.5, 1.5]e-2, contact angle theta ~
+    U[10, 30] degrees giving S_l1 = gamma_{l+1}(cos theta - 1) (multi-layer
+    S = 0), mean heights (1, 0.8, 0.6, 0.4)[:N], a single mode
+    1e-3 cos(2 pi m x / s) with m ~ U{1..s/16} plus U(-1e-5, 1e-5) noise,
+    h* = 0.15 and mu_i = 0.09 h*^2 U[0.5, 1] (with every layer at h* the
+    largest friction rate stays below 1 for N <= 4).
+    Returns a list of (film, h0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = np.arange(side_min, side_max + 1, 16)
+    out = []
+    for _ in range(count):
+        s = int(rng.choice(sides))
+        n = int(rng.integers(2, 5))
+        gam = list(rng.uniform(0.5e-2, 1.5e-2, size=n))
+        theta = float(rng.uniform(10.0, 30.0))
+        mu = list(0.09 * hstar * hstar * rng.uniform(0.5, 1.0, size=n))
+        spread = {(l, 1): young_spreading(gam[l], theta) for l in range(n)}
+        film = film_params(n, s, s, gamma=gam, mu=mu, hstar=hstar, spread=spread)
+        m = int(rng.integers(1, s // 16 + 1))
+        x = np.arange(s, dtype=np.float64)
+        mode = 1e-3 * np.cos(2.0 * math.pi * m * x / s)
+        hbar = (1.0, 0.8, 0.6, 0.4)[:n]
+        h0 = np.stack([hbar[i] + mode[None, :] + uniform_noise(rng, (s, s), 1e-5) for i in range(n)])
+        out.append((film, h0))
+    return out
 
 
 def workload(name: str, nx=None, ny=None):

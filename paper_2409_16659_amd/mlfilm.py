@@ -91,6 +91,21 @@ def load_library():
         "mlf_steps_done": (C.c_int64, [H]),
         "mlf_last_error": (C.c_char_p, [H]),
         "mlf_destroy": (st, [H]),
+        "mlf_batch_query_sizes": (st, [P, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "mlf_batch_create": (st, [P, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(H)]),
+        "mlf_batch_init": (st, [H, C.c_int32, _D, _D, _D]),
+        "mlf_batch_step": (st, [H, C.c_int64]),
+        "mlf_batch_capture": (st, [H, C.c_int32]),
+        "mlf_batch_read": (st, [H, C.c_int32, _D, _D, _D]),
+        "mlf_batch_layer_mass": (st, [H, C.c_int32, _D]),
+        "mlf_batch_set_launch": (st, [H, C.c_int32, C.c_int32, C.c_int32]),
+        "mlf_batch_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mlf_batch_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
+        "mlf_batch_steps_done": (C.c_int64, [H]),
+        "mlf_batch_failed_film": (C.c_int32, [H]),
+        "mlf_batch_last_error": (C.c_char_p, [H]),
+        "mlf_batch_destroy": (st, [H]),
         "mlf_spreading_from_tensions": (st, [C.c_int32, _D, _D]),
         "mlf_friction_matrix": (st, [C.c_int32, _D, _D, _D, _D]),
         "mlf_version": (C.c_char_p, []),
@@ -303,3 +318,110 @@ class Film:
         a, b = C.c_int32(), C.c_int32()
         self._check(self.lib.mlf_get_launch(self.h, C.byref(a), C.byref(b)), "mlf_get_launch")
         return a.value, b.value
+
+
+def batch_query_sizes(params_list):
+    """(pop_bytes, scratch_bytes) of a batch of films (list of Params)."""
+    lib = load_library()
+    arr = (Params * len(params_list))(*params_list)
+    a, b = C.c_size_t(), C.c_size_t()
+    rc = lib.mlf_batch_query_sizes(arr, len(params_list), C.byref(a), C.byref(b))
+    if rc:
+        raise MlfError(rc, "mlf_batch_query_sizes")
+    return a.value, b.value
+
+
+class Batch:
+    """Many independent films advanced by one launch per step (C ABI
+    mlf_batch_*).  Films share the storage precision, tau and exponents.
+    Buffers are torch uint8 tensors owned by this object; the batch runs on
+    its own (default-priority) stream so that its step loop can be
+    captured into a HIP graph."""
+
+    def __init__(self, films, precision="f32", allow_unstable=False, stream=None, device=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.films = [dict(f) for f in films]
+        self.params = [make_params(f, precision, 0, allow_unstable) for f in films]
+        self.n = len(films)
+        arr = (Params * self.n)(*self.params)
+        pop_bytes, scratch_bytes = batch_query_sizes(self.params)
+        self.pop_bytes, self.scratch_bytes = pop_bytes, scratch_bytes
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = dev
+        self.pop_a = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.pop_b = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        h = C.c_void_p()
+        rc = self.lib.mlf_batch_create(arr, self.n, C.c_void_p(self.pop_a.data_ptr()),
+                                       C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.scratch.data_ptr()),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise MlfError(rc, "mlf_batch_create")
+        # buffers allocated on the current stream are used on the batch's stream
+        torch.cuda.current_stream(dev).synchronize()
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()  # the buffers are freed on torch's stream after this
+            self.lib.mlf_batch_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc, what):
+        if rc:
+            detail = self.lib.mlf_batch_last_error(self.h)
+            raise MlfError(rc, what, detail.decode() if detail else "")
+
+    def init(self, f, h, ux=None, uy=None):
+        p = self.params[f]
+        h = _f64(h)
+        assert h.shape == (p.n_layers, p.ny, p.nx)
+        ux = None if ux is None else _f64(ux)
+        uy = None if uy is None else _f64(uy)
+        self._check(self.lib.mlf_batch_init(self.h, int(f), _dp(h), _dp(ux), _dp(uy)), "mlf_batch_init")
+
+    def step(self, n=1):
+        self._check(self.lib.mlf_batch_step(self.h, int(n)), "mlf_batch_step")
+
+    def capture(self, steps):
+        self._check(self.lib.mlf_batch_capture(self.h, int(steps)), "mlf_batch_capture")
+
+    def read(self, f):
+        p = self.params[f]
+        shape = (p.n_layers, p.ny, p.nx)
+        h, ux, uy = np.empty(shape), np.empty(shape), np.empty(shape)
+        self._check(self.lib.mlf_batch_read(self.h, int(f), _dp(h), _dp(ux), _dp(uy)), "mlf_batch_read")
+        return h, ux, uy
+
+    def mass(self, f):
+        m = np.empty(self.params[f].n_layers)
+        self._check(self.lib.mlf_batch_layer_mass(self.h, int(f), _dp(m)), "mlf_batch_layer_mass")
+        return m
+
+    def set_launch(self, block_w=0, seg_h=0, persistent=0):
+        self._check(self.lib.mlf_batch_set_launch(self.h, int(block_w), int(seg_h), int(persistent)),
+                    "mlf_batch_set_launch")
+
+    def get_launch(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.mlf_batch_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)),
+                    "mlf_batch_get_launch")
+        return a.value, b.value, c.value
+
+    def autotune(self, reps=3):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.mlf_batch_autotune(self.h, int(reps), C.byref(a), C.byref(b), C.byref(c)),
+                    "mlf_batch_autotune")
+        return a.value, b.value, c.value
+
+    @property
+    def steps_done(self) -> int:
+        return int(self.lib.mlf_batch_steps_done(self.h))
+
+    @property
+    def failed_film(self) -> int:
+        return int(self.lib.mlf_batch_failed_film(self.h))
