@@ -84,6 +84,77 @@ def cpu_baseline(film, h0, budget_s: float):
                       f"({el:.1f} s)"}
 
 
+def bench_batch(args):
+    """Batched scan: summed layer-node updates per second of one launch per
+    step over all films, and the same films run back to back through the
+    single-film kernel (each film all its steps, best case for reuse)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_16659_amd import inputs, mlfilm
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    films = inputs.batch_scan(count=args.batch_films, seed=3)
+    n_lu = sum(f["n_layers"] * f["nx"] * f["ny"] for f, _ in films)
+    steps, warm = args.batch_steps, max(2, args.warmup // 2 * 2)
+    b = mlfilm.Batch([f for f, _ in films], "f32")
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    launch = b.autotune(reps=2)
+    if args.graph_steps:
+        b.capture(args.graph_steps)
+    print(f"[bench] batch of {len(films)} films, {n_lu / 1e6:.1f} M LU/step, launch {launch}, "
+          f"graph {args.graph_steps}", file=sys.stderr, flush=True)
+    b.step(warm)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / steps
+    assert all(np.all(np.isfinite(b.mass(i))) for i in range(len(films)))
+    del b
+
+    # the same films, one single-film kernel launch per film and step
+    gs = []
+    for f, h0 in films:
+        g = mlfilm.Film(f, "f32", check_every=-1)
+        g.set_launch(launch[0], launch[1])
+        g.init(h0)
+        gs.append(g)
+    for g in gs:
+        g.step(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in gs:
+        g.step(steps)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    print(f"[bench] plain back-to-back: {wall_p:.3f} s", file=sys.stderr, flush=True)
+    del gs
+
+    value = n_lu * steps / wall_b
+    achieved = 72 * n_lu / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "batched scan: summed layer-lattice updates/s (one launch per step, graph-captured)",
+        "value": value, "unit": "LU/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": wall_b * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch_scan_{len(films)}", "films": len(films), "lu_per_step": n_lu,
+                   "launch": list(launch), "graph_steps": args.graph_steps},
+        "plain": {"value": n_lu * steps / wall_p, "unit": "LU/s", "ms_per_step": wall_p * 1e3 / steps,
+                  "launches_per_step": len(films)},
+        "speedup_vs_plain": wall_p / wall_b,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_lu": 72,
+                     "kernel_ms": kern_ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +169,13 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="always run the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget; 0 disables it")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched stability scan instead: 256 uneven films, one launch per step "
+                         "(graph-captured, autotuned) against the same films stepped back to back "
+                         "through the single-film kernel")
+    ap.add_argument("--batch-films", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--graph-steps", type=int, default=100, help="steps per captured graph (even; 0: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of one population buffer instead (copy ceiling; "
                          "the reference kernel for scaling rocprofv3 byte counters)")
@@ -110,6 +188,9 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.batch:
+        return bench_batch(args)
 
     from paper_2409_16659_amd import inputs, mlfilm
 

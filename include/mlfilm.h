@@ -166,6 +166,13 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
  * Synchronises. */
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h);
 
+/* Capture `steps` (even, > 0) consecutive step launches into a HIP graph
+ * that mlf_step replays whenever at least `steps` steps remain (guard polls
+ * then fall on replay boundaries); 0 drops it.  The graph holds the step
+ * constants: mlf_init, mlf_init_device, mlf_load, mlf_set_launch and
+ * mlf_autotune drop it.  EUNSUPPORTED on the default stream. */
+mlf_status mlf_capture(mlf_handle* h, int32_t steps);
+
 int64_t mlf_steps_done(const mlf_handle* h);
 const char* mlf_last_error(const mlf_handle* h);
 mlf_status mlf_destroy(mlf_handle* h);

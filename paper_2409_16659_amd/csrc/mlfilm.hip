@@ -358,6 +358,8 @@ struct mlf_handle {
   int64_t steps;
   int block_w, seg_h;
   bool initialised;
+  hipGraphExec_t graph;  // captured step loop (constants baked in), or null
+  int graph_steps, graph_parity;
   std::string err;
 };
 
@@ -447,6 +449,14 @@ Layers layers_of(const mlf_handle* h) {
 mlf_status fail(mlf_handle* h, mlf_status st, const std::string& m) {
   if (h) h->err = m;
   return st;
+}
+
+// The captured graph holds the step constants as kernel arguments: every
+// change of reference heights, scales or launch shape drops it.
+void drop_single_graph(mlf_handle* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->graph_steps = 0;
 }
 
 mlf_status hip_check(mlf_handle* h, hipError_t e, const char* what) {
@@ -744,12 +754,17 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0, h->scale[i] = 1.0;
   h->steps = 0;
   h->initialised = false;
+  h->graph = nullptr;
+  h->graph_steps = 0;
+  h->graph_parity = 0;
   default_launch(p, &h->block_w, &h->seg_h);
   *out = h;
   return MLF_OK;
 }
 
 mlf_status mlf_destroy(mlf_handle* h) {
+  if (!h) return MLF_EINVAL;
+  drop_single_graph(h);
   delete h;
   return MLF_OK;
 }
@@ -760,6 +775,7 @@ const char* mlf_last_error(const mlf_handle* h) { return h ? h->err.c_str() : "n
 
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h) {
   if (!h) return MLF_EINVAL;
+  drop_single_graph(h);
   int bw, sh;
   default_launch(&h->p, &bw, &sh);
   if (block_w != 0) {
@@ -786,6 +802,7 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h) {
   if (!h || reps < 1) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "autotune before init");
+  drop_single_graph(h);
   const mlf_params& p = h->p;
   int dev = 0, ncu = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -845,6 +862,7 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
 
 mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const double* uy) {
   if (!h || !hgt) return MLF_EINVAL;
+  drop_single_graph(h);
   const mlf_params& p = h->p;
   const long long nn = (long long)p.nx * p.ny;
   h->initialised = false;
@@ -892,6 +910,7 @@ mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const do
 
 mlf_status mlf_init_device(mlf_handle* h, const double* hgt, const double* ux, const double* uy) {
   if (!h || !hgt) return MLF_EINVAL;
+  drop_single_graph(h);
   const mlf_params& p = h->p;
   const long long nn = (long long)p.nx * p.ny;
   h->initialised = false;
@@ -925,16 +944,55 @@ mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
   if (!h || nsteps < 0) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_step before mlf_init");
   const int every = h->p.check_every;
-  for (int64_t t = 0; t < nsteps; ++t) {
-    HIPCHK(launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]));
-    h->cur ^= 1;
-    h->steps += 1;
-    if (every > 0 && (t + 1) % every == 0 && t + 1 < nsteps) {
+  int64_t left = nsteps, since = 0;
+  while (left > 0) {
+    int64_t adv = 1;
+    if (h->graph && h->cur == h->graph_parity && left >= h->graph_steps) {
+      HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      adv = h->graph_steps;
+    } else {
+      HIPCHK(launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]));
+      h->cur ^= 1;
+    }
+    left -= adv;
+    since += adv;
+    h->steps += adv;
+    if (every > 0 && since >= every && left > 0) {
+      since = 0;
       mlf_status s = check_guard(h);
       if (s != MLF_OK) return s;
     }
   }
   if (every >= 0) return check_guard(h);
+  return MLF_OK;
+}
+
+mlf_status mlf_capture(mlf_handle* h, int32_t steps) {
+  if (!h) return MLF_EINVAL;
+  drop_single_graph(h);
+  if (steps == 0) return MLF_OK;
+  if (steps < 0 || steps % 2 != 0) return fail(h, MLF_EINVAL, "graph steps must be even and >= 0");
+  if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_capture before mlf_init");
+  if (!h->stream) return fail(h, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int t = 0; t < steps && le == hipSuccess; ++t) {
+    const int c = (h->cur + t) & 1;
+    le = launch_step(h, h->pop[c], h->pop[c ^ 1]);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(h->stream, &g);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_check(h, le != hipSuccess ? le : ee, "graph capture");
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return hip_check(h, ie, "hipGraphInstantiate");
+  h->graph = ex;
+  h->graph_steps = steps;
+  h->graph_parity = h->cur;
   return MLF_OK;
 }
 
@@ -1078,6 +1136,7 @@ mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes) {
 
 mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes) {
   if (!h || !blob) return MLF_EINVAL;
+  drop_single_graph(h);
   if (bytes < sizeof(BlobHeader)) return fail(h, MLF_EINVAL, "checkpoint too small");
   BlobHeader hd;
   std::memcpy(&hd, blob, sizeof hd);

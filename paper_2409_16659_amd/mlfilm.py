@@ -88,6 +88,7 @@ def load_library():
         "mlf_set_launch": (st, [H, C.c_int32, C.c_int32]),
         "mlf_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mlf_capture": (st, [H, C.c_int32]),
         "mlf_steps_done": (C.c_int64, [H]),
         "mlf_last_error": (C.c_char_p, [H]),
         "mlf_destroy": (st, [H]),
@@ -223,6 +224,10 @@ class Film:
         self.pop_b = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
         self.scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._own_stream = stream is not None
+        if self._own_stream:
+            # the buffers come from torch's allocator on the current stream
+            torch.cuda.current_stream(dev).synchronize()
         h = C.c_void_p()
         rc = self.lib.mlf_create(C.byref(self.params), C.c_void_p(self.pop_a.data_ptr()),
                                  C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.scratch.data_ptr()),
@@ -233,6 +238,8 @@ class Film:
 
     def __del__(self):
         if getattr(self, "h", None):
+            if getattr(self, "_own_stream", False):
+                self.stream.synchronize()  # the buffers are freed on torch's stream after this
             self.lib.mlf_destroy(self.h)
             self.h = None
 
@@ -259,6 +266,11 @@ class Film:
 
     def step(self, n=1):
         self._check(self.lib.mlf_step(self.h, int(n)), "mlf_step")
+
+    def capture(self, steps):
+        """Replay `steps` (even) step launches from a HIP graph; 0 drops it.
+        Needs a non-default stream (pass stream=torch.cuda.Stream())."""
+        self._check(self.lib.mlf_capture(self.h, int(steps)), "mlf_capture")
 
     @property
     def steps_done(self) -> int:

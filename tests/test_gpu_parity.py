@@ -348,3 +348,41 @@ def test_autotune_keeps_state(mlf):
         b.init(h0)
         b.step(15)
         assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_single_film(mlf, torch_cuda, prec):
+    """A captured 6-step graph, replayed with eager steps, guard polls and
+    synchronising read-backs in between, gives every time the state of a
+    film stepped eagerly; re-initialising drops the graph."""
+    film = small_film(3, 90, 40, seed=32)
+    h0 = noisy(3, 90, 40, seed=33)
+    a = mlf.Film(film, prec, check_every=4, stream=torch_cuda.cuda.Stream())
+    e = mlf.Film(film, prec, check_every=4)
+    for g in (a, e):
+        g.set_launch(128, 7)
+        g.init(h0)
+    a.capture(6)
+    for chunk in (6, 12, 5, 6, 1, 18, 7):
+        a.step(chunk)
+        e.step(chunk)
+        assert a.steps_done == e.steps_done
+        assert np.array_equal(a.populations(), e.populations()), chunk
+    h1 = noisy(3, 90, 40, seed=34)
+    a.init(h1)   # new reference heights: the graph is dropped
+    e.init(h1)
+    a.step(9)
+    e.step(9)
+    assert np.array_equal(a.populations(), e.populations())
+
+
+def test_graph_capture_needs_a_stream_of_its_own(mlf):
+    film = small_film(2, 30, 8, seed=35)
+    g = mlf.Film(film, "f32")   # torch's default stream
+    g.init(noisy(2, 30, 8, seed=36))
+    if g.stream.cuda_stream == 0:
+        with pytest.raises(mlf.MlfError) as e:
+            g.capture(4)
+        assert e.value.status == "EUNSUPPORTED"
+    with pytest.raises(mlf.MlfError):
+        g.capture(3)
