@@ -1,0 +1,666 @@
+// surrogate.hip -- C ABI of the learned surrogate (declared in
+// include/mlf_surrogate.h): a convolutional neural operator that maps the
+// layer heights h(t) of a periodic multilayer film to h(t + K).
+//
+// Network (all convolutions periodic):
+//   x_i  = (h_i - mean(h_i)) / s                            (per sample, layer)
+//   r_0  = E * patches_4x4(x) + b_E                         (latent grid ny/4 x nx/4, C channels)
+//   r_{l+1} = r_l + W2_l (*) gelu(W1_l (*) r_l + b1_l) + b2_l,   l < L   (3x3 convs)
+//   D    = pixel_shuffle(W_D r_L + b_D)                     (N x ny x nx)
+//   Delta_i = D_i - mean(D_i)                               (no net mass change)
+//   h'   = h + s Delta
+// Training minimises mean((Delta - (h(t+K) - h(t)) / s)^2) with Adam.
+// The 3x3 convolutions run on BF16 MFMA with FP32 accumulation
+// (nop_kernels.hpp); everything else is FP32 on the VALU.  Master weights,
+// gradients and Adam moments are FP32.
+#include "../../include/mlf_surrogate.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nop_kernels.hpp"
+
+namespace {
+
+constexpr int kPatch = 4;
+constexpr int kRedBlocks = 512;  // partial sums of the pixel reductions
+
+// ---- elementwise and reduction kernels (FP32) ------------------------------
+
+// mean over the grid of each (sample, layer) plane: out[bi] (one block each)
+__global__ void __launch_bounds__(256) plane_mean(const float* __restrict__ a, float* __restrict__ out, long long n) {
+  __shared__ float red[256];
+  const float* p = a + (long long)blockIdx.x * n;
+  float s = 0.f;
+  for (long long t = threadIdx.x; t < n; t += 256) s += p[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0] / (float)n;
+}
+
+// y = (a - mean[plane]) * scale
+__global__ void center_scale(const float* __restrict__ a, const float* __restrict__ mean, float* __restrict__ y,
+                             long long n_plane, long long total, float scale) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
+    y[t] = (a[t] - mean[t / n_plane]) * scale;
+}
+
+// h_out = h + s * delta
+__global__ void axpy_out(const float* __restrict__ h, const float* __restrict__ d, float* __restrict__ o, float s,
+                         long long total) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
+    o[t] = h[t] + s * d[t];
+}
+
+// target increment (h1 - h0) / s
+__global__ void target_inc(const float* __restrict__ h0, const float* __restrict__ h1, float* __restrict__ o,
+                           float inv_s, long long total) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
+    o[t] = (h1[t] - h0[t]) * inv_s;
+}
+
+// patch encoder: r[b][py][px][c] = be[c] + sum_j We[j][c] x[b][i][4py+u][4px+v], j = (i*4+u)*4+v
+__global__ void enc_fwd(const float* __restrict__ x, const float* __restrict__ We, const float* __restrict__ be,
+                        float* __restrict__ r, __bf16* __restrict__ rb, int nl, int ny, int nx, int C, int batch) {
+  const int gy = ny / kPatch, gx = nx / kPatch;
+  const long long total = (long long)batch * gy * gx * C;
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const int c = (int)(t % C);
+    const long long pix = t / C;
+    const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+    float s = be[c];
+    for (int i = 0; i < nl; ++i)
+      for (int u = 0; u < kPatch; ++u)
+        for (int v = 0; v < kPatch; ++v)
+          s += We[(long long)((i * kPatch + u) * kPatch + v) * C + c] *
+               x[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v];
+    r[t] = s;
+    rb[t] = (__bf16)s;
+  }
+}
+
+// decoder + pixel shuffle: D[b][i][4py+u][4px+v] = bd[j] + sum_c Wd[j][c] r[b][py][px][c], j = (i*4+u)*4+v
+__global__ void dec_fwd(const float* __restrict__ r, const float* __restrict__ Wd, const float* __restrict__ bd,
+                        float* __restrict__ D, int nl, int ny, int nx, int C, int batch) {
+  const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
+  const long long total = (long long)batch * gy * gx * J;
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const int j = (int)(t % J);
+    const long long pix = t / J;
+    const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+    const float* rp = r + pix * C;
+    const float* wp = Wd + (long long)j * C;
+    float s = bd[j];
+    for (int c = 0; c < C; ++c) s += wp[c] * rp[c];
+    const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
+    D[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v] = s;
+  }
+}
+
+// decoder input gradient: dr[b][py][px][c] = sum_j Wd[j][c] dD[b][i][4py+u][4px+v]
+__global__ void dec_bwd_in(const float* __restrict__ dD, const float* __restrict__ Wd, float* __restrict__ dr,
+                           int nl, int ny, int nx, int C, int batch) {
+  const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
+  const long long total = (long long)batch * gy * gx * C;
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const int c = (int)(t % C);
+    const long long pix = t / C;
+    const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+    float s = 0.f;
+    for (int j = 0; j < J; ++j) {
+      const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
+      s += Wd[(long long)j * C + c] * dD[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v];
+    }
+    dr[t] = s;
+  }
+}
+
+// partial outer-product sums over pixels for the patch layers:
+//   part[blk][j][c] = sum_{pix in slice} P[pix][j] Q[pix][c]
+// where P[pix][j] is value j of the 4x4 patch of latent pixel pix in a
+// full-resolution tensor (the encoder input, or the decoder output
+// gradient) and Q a latent tensor.
+__global__ void __launch_bounds__(256) patch_outer(const float* __restrict__ img, const float* __restrict__ lat,
+                                                   float* __restrict__ part, int nl, int ny, int nx, int C,
+                                                   long long npix) {
+  const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
+  const long long per = (npix + gridDim.x - 1) / gridDim.x;
+  const long long p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
+  for (int e = threadIdx.x; e < J * C; e += 256) {
+    const int j = e / C, c = e % C;
+    const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
+    float s = 0.f;
+    for (long long pix = p0; pix < p1; ++pix) {
+      const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+      s += img[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v] * lat[pix * C + c];
+    }
+    part[(long long)blockIdx.x * J * C + e] = s;
+  }
+}
+
+// partial patch sums: part[blk][j] = sum_{pix in slice} P[pix][j]
+__global__ void __launch_bounds__(256) patch_sum(const float* __restrict__ img, float* __restrict__ part, int nl,
+                                                 int ny, int nx, long long npix) {
+  const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
+  const long long per = (npix + gridDim.x - 1) / gridDim.x;
+  const long long p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
+  for (int j = threadIdx.x; j < J; j += 256) {
+    const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
+    float s = 0.f;
+    for (long long pix = p0; pix < p1; ++pix) {
+      const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+      s += img[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v];
+    }
+    part[(long long)blockIdx.x * J + j] = s;
+  }
+}
+
+// partial column sums: part[blk][c] = sum_{pix in slice} a[pix][c]
+__global__ void __launch_bounds__(256) col_partial(const float* __restrict__ a, float* __restrict__ part, int C,
+                                                   long long npix) {
+  const long long per = (npix + gridDim.x - 1) / gridDim.x;
+  const long long p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float s = 0.f;
+    for (long long pix = p0; pix < p1; ++pix) s += a[pix * C + c];
+    part[(long long)blockIdx.x * C + c] = s;
+  }
+}
+
+// out[k] (+)= sum_r part[r][k]  (fixed order)
+__global__ void sum_rows(const float* __restrict__ part, float* __restrict__ out, int rows, long long K, int add) {
+  for (long long k = blockIdx.x * 256LL + threadIdx.x; k < K; k += (long long)gridDim.x * 256) {
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[(long long)r * K + k];
+    out[k] = add ? out[k] + s : s;
+  }
+}
+
+__device__ inline float gelu_f(float a, float* dg) {
+  const float k0 = 0.7978845608028654f, k1 = 0.044715f;
+  const float u = k0 * (a + k1 * a * a * a);
+  const float th = tanhf(u);
+  if (dg) *dg = 0.5f * (1.f + th) + 0.5f * a * (1.f - th * th) * k0 * (1.f + 3.f * k1 * a * a);
+  return 0.5f * a * (1.f + th);
+}
+
+__global__ void gelu_fwd(const float* __restrict__ a, __bf16* __restrict__ gb, long long n) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256)
+    gb[t] = (__bf16)gelu_f(a[t], nullptr);
+}
+
+// da = dg * gelu'(a), FP32 and BF16
+__global__ void gelu_bwd(const float* __restrict__ dg, const float* __restrict__ a, float* __restrict__ da,
+                         __bf16* __restrict__ dab, long long n) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    float d;
+    gelu_f(a[t], &d);
+    const float v = dg[t] * d;
+    da[t] = v;
+    dab[t] = (__bf16)v;
+  }
+}
+
+// r1 = r0 + c (FP32 and BF16 copy)
+__global__ void resid_add(const float* __restrict__ r0, const float* __restrict__ c, float* __restrict__ r1,
+                          __bf16* __restrict__ r1b, long long n) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const float v = r0[t] + c[t];
+    r1[t] = v;
+    r1b[t] = (__bf16)v;
+  }
+}
+
+// y (+)= a; optional BF16 copy of the result
+__global__ void add_into(float* __restrict__ y, const float* __restrict__ a, __bf16* __restrict__ yb, long long n) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const float v = y[t] + a[t];
+    y[t] = v;
+    if (yb) yb[t] = (__bf16)v;
+  }
+}
+
+__global__ void to_bf16(const float* __restrict__ a, __bf16* __restrict__ b, long long n) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) b[t] = (__bf16)a[t];
+}
+
+// BF16 conv weights: w[o][co][ci] and the flipped transpose wt[o][ci][co] = w[8-o][co][ci]
+__global__ void conv_weights(const float* __restrict__ w, __bf16* __restrict__ wb, __bf16* __restrict__ wt, int C) {
+  const long long n = 9LL * C * C;
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const int o = (int)(t / ((long long)C * C));
+    const int co = (int)((t / C) % C), ci = (int)(t % C);
+    wb[t] = (__bf16)w[t];
+    wt[((long long)(8 - o) * C + ci) * C + co] = (__bf16)w[t];
+  }
+}
+
+// d = d - mean[plane]
+__global__ void sub_plane_mean(float* __restrict__ d, const float* __restrict__ mean, long long n_plane,
+                               long long total) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
+    d[t] -= mean[t / n_plane];
+}
+
+// loss partials: part[blk] = sum (delta - target)^2 over a slice; grad = 2 (delta - target) / n
+__global__ void __launch_bounds__(256) mse(const float* __restrict__ d, const float* __restrict__ tgt,
+                                           float* __restrict__ grad, float* __restrict__ part, long long n) {
+  __shared__ float red[256];
+  float s = 0.f;
+  const float k = 2.f / (float)n;
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const float e = d[t] - tgt[t];
+    s += e * e;
+    if (grad) grad[t] = k * e;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                     long long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const float gg = g[t];
+    const float mm = b1 * m[t] + (1.f - b1) * gg;
+    const float vv = b2 * v[t] + (1.f - b2) * gg * gg;
+    m[t] = mm;
+    v[t] = vv;
+    p[t] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+unsigned grid1(long long n) { return (unsigned)std::max(1LL, std::min((n + 255) / 256, 16384LL)); }
+
+}  // namespace
+
+// ============================================================= handle ====
+struct mlf_nop {
+  mlf_nop_params p;
+  int C, L, J, gy, gx;
+  long long npar;
+  // parameter offsets (floats)
+  long long oWe, obe, oW1, ob1, oW2, ob2, oWd, obd;  // oW1/ob1/oW2/ob2: block 0, stride per block
+  long long blk_stride;
+  unsigned char* ws;
+  hipStream_t stream;
+  // workspace regions
+  float *par, *grad, *am, *av;
+  __bf16 *w1b, *w1t, *w2b, *w2t;  // [L][9][C][C]
+  float *x, *tgt, *D, *dD, *mean, *loss_part;
+  float *r, *a, *c, *dr, *tmp;   // r: [L+1][lat], a: [L][lat]
+  __bf16 *rb, *gb, *cb;          // rb: [L+1][lat], gb: [L][lat], cb: [lat]
+  float *part;
+  long long lat, img;            // floats per latent tensor / per image batch tensor (max batch)
+  long long part_floats;
+  int adam_t;
+  std::string err;
+};
+
+namespace {
+
+mlf_status nfail(mlf_nop* m, mlf_status st, const std::string& s) {
+  if (m) m->err = s;
+  return st;
+}
+
+mlf_status nhip(mlf_nop* m, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MLF_OK;
+  return nfail(m, MLF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NHIP(call)                                                \
+  do {                                                            \
+    mlf_status _s = nhip(m, (call), #call);                       \
+    if (_s != MLF_OK) return _s;                                  \
+  } while (0)
+
+#define NLAUNCH(...)                                              \
+  do {                                                            \
+    hipLaunchKernelGGL(__VA_ARGS__);                              \
+    NHIP(hipGetLastError());                                      \
+  } while (0)
+
+mlf_status check_params(const mlf_nop_params* p) {
+  if (!p) return MLF_EINVAL;
+  if (p->n_layers < 1 || p->n_layers > 4) return MLF_EINVAL;
+  if (p->nx < 64 * kPatch || p->nx % (64 * kPatch) || p->ny < 4 * kPatch || p->ny % (4 * kPatch)) return MLF_EINVAL;
+  if (p->width != 64 && p->width != 128) return MLF_EUNSUPPORTED;
+  if (p->blocks < 0 || p->blocks > 32 || p->batch < 1 || p->batch > 4096) return MLF_EINVAL;
+  if (!(p->scale > 0.0) || !std::isfinite(p->scale)) return MLF_EINVAL;
+  return MLF_OK;
+}
+
+struct Layout {
+  long long npar, oWe, obe, oW1, ob1, oW2, ob2, blk, oWd, obd;
+  long long lat, img, part_floats;
+  size_t bytes;
+  size_t off[32];
+};
+
+long long a64(long long v) { return (v + 63) / 64 * 64; }
+
+Layout layout_of(const mlf_nop_params* p) {
+  Layout s;
+  const long long C = p->width, N = p->n_layers, J = N * kPatch * kPatch, L = p->blocks;
+  s.oWe = 0;
+  s.obe = s.oWe + C * J;
+  s.oW1 = s.obe + C;
+  s.ob1 = s.oW1 + 9 * C * C;
+  s.oW2 = s.ob1 + C;
+  s.ob2 = s.oW2 + 9 * C * C;
+  s.blk = 2 * (9 * C * C + C);
+  s.oWd = s.oW1 + L * s.blk;
+  s.obd = s.oWd + J * C;
+  s.npar = s.obd + J;
+  const long long gy = p->ny / kPatch, gx = p->nx / kPatch;
+  s.lat = (long long)p->batch * gy * gx * C;
+  s.img = (long long)p->batch * N * p->ny * p->nx;
+  s.part_floats = std::max<long long>({(long long)p->batch * 9 * C * C, (long long)kRedBlocks * J * C,
+                                       (long long)kRedBlocks * C, (long long)kRedBlocks});
+  // regions: floats then bf16, 256-byte aligned
+  const long long npa = a64(s.npar);
+  std::vector<long long> sz = {
+      npa * 4, npa * 4, npa * 4, npa * 4,                                   // par grad am av
+      a64(L * 9 * C * C) * 2 * 4,                                           // w1b w1t w2b w2t (bf16 each)
+      a64(s.img) * 4, a64(s.img) * 4, a64(s.img) * 4, a64(s.img) * 4,       // x tgt D dD
+      a64(p->batch * N) * 4, a64(kRedBlocks) * 4,                           // mean loss_part
+      a64((L + 1) * s.lat) * 4, a64(std::max(1LL, L) * s.lat) * 4,          // r a
+      a64(s.lat) * 4, a64(s.lat) * 4, a64(s.lat) * 4,                       // c dr tmp
+      a64((L + 1) * s.lat) * 2, a64(std::max(1LL, L) * s.lat) * 2, a64(s.lat) * 2,  // rb gb cb
+      a64(s.part_floats) * 4};
+  size_t o = 0;
+  for (size_t i = 0; i < sz.size(); ++i) {
+    s.off[i] = o;
+    o += (size_t)((sz[i] + 255) / 256 * 256);
+  }
+  s.bytes = o;
+  return s;
+}
+
+template <int C>
+mlf_status conv_fwd_t(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, const float* bias, float* out) {
+  const int blocks = batch * (m->gy / 4) * (m->gx / 64);
+  NLAUNCH(nop::conv3x3_fwd<C>, dim3(blocks), dim3(256), 0, m->stream, in, w, bias, out, m->gy, m->gx);
+  return MLF_OK;
+}
+
+mlf_status conv_fwd(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, const float* bias, float* out) {
+  return m->C == 64 ? conv_fwd_t<64>(m, batch, in, w, bias, out) : conv_fwd_t<128>(m, batch, in, w, bias, out);
+}
+
+// dW (FP32, [9][C][C]) = sum over the batch of the weight gradient
+mlf_status conv_wgrad(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout, float* dw) {
+  if (m->C == 64)
+    NLAUNCH(nop::conv3x3_wgrad<64>, dim3(batch * 9), dim3(256), 0, m->stream, in, dout, m->part, m->gy, m->gx);
+  else
+    NLAUNCH(nop::conv3x3_wgrad<128>, dim3(batch * 9), dim3(256), 0, m->stream, in, dout, m->part, m->gy, m->gx);
+  const long long K = 9LL * m->C * m->C;
+  NLAUNCH(sum_rows, dim3(grid1(K)), dim3(256), 0, m->stream, m->part, dw, batch, K, 0);
+  return MLF_OK;
+}
+
+// bias gradient: db[c] = sum over pixels of a[pix][c]
+mlf_status bias_grad(mlf_nop* m, long long npix, const float* a, float* db) {
+  NLAUNCH(col_partial, dim3(kRedBlocks), dim3(256), 0, m->stream, a, m->part, m->C, npix);
+  NLAUNCH(sum_rows, dim3(grid1(m->C)), dim3(256), 0, m->stream, m->part, db, kRedBlocks, (long long)m->C, 0);
+  return MLF_OK;
+}
+
+mlf_status refresh_weights(mlf_nop* m) {
+  const long long cc = 9LL * m->C * m->C;
+  for (int l = 0; l < m->L; ++l) {
+    NLAUNCH(conv_weights, dim3(grid1(cc)), dim3(256), 0, m->stream, m->par + m->oW1 + l * m->blk_stride,
+            m->w1b + l * cc, m->w1t + l * cc, m->C);
+    NLAUNCH(conv_weights, dim3(grid1(cc)), dim3(256), 0, m->stream, m->par + m->oW2 + l * m->blk_stride,
+            m->w2b + l * cc, m->w2t + l * cc, m->C);
+  }
+  return MLF_OK;
+}
+
+// forward to the projected increment m->D; keeps the activations
+mlf_status forward(mlf_nop* m, int batch, const float* h) {
+  const int N = m->p.n_layers;
+  const long long plane = (long long)m->p.ny * m->p.nx, img = (long long)batch * N * plane;
+  const long long npix = (long long)batch * m->gy * m->gx, lat = npix * m->C;
+  NLAUNCH(plane_mean, dim3(batch * N), dim3(256), 0, m->stream, h, m->mean, plane);
+  NLAUNCH(center_scale, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->mean, m->x, plane, img,
+          (float)(1.0 / m->p.scale));
+  NLAUNCH(enc_fwd, dim3(grid1(lat)), dim3(256), 0, m->stream, m->x, m->par + m->oWe, m->par + m->obe, m->r, m->rb, N,
+          m->p.ny, m->p.nx, m->C, batch);
+  const long long cc = 9LL * m->C * m->C;
+  for (int l = 0; l < m->L; ++l) {
+    float* rl = m->r + l * m->lat;
+    __bf16* rlb = m->rb + l * m->lat;
+    float* al = m->a + l * m->lat;
+    __bf16* glb = m->gb + l * m->lat;
+    mlf_status st = conv_fwd(m, batch, rlb, m->w1b + l * cc, m->par + m->ob1 + l * m->blk_stride, al);
+    if (st != MLF_OK) return st;
+    NLAUNCH(gelu_fwd, dim3(grid1(lat)), dim3(256), 0, m->stream, al, glb, lat);
+    st = conv_fwd(m, batch, glb, m->w2b + l * cc, m->par + m->ob2 + l * m->blk_stride, m->c);
+    if (st != MLF_OK) return st;
+    NLAUNCH(resid_add, dim3(grid1(lat)), dim3(256), 0, m->stream, rl, m->c, m->r + (l + 1) * m->lat,
+            m->rb + (l + 1) * m->lat, lat);
+  }
+  const long long J = m->J;
+  NLAUNCH(dec_fwd, dim3(grid1(npix * J)), dim3(256), 0, m->stream, m->r + m->L * m->lat, m->par + m->oWd,
+          m->par + m->obd, m->D, N, m->p.ny, m->p.nx, m->C, batch);
+  NLAUNCH(plane_mean, dim3(batch * N), dim3(256), 0, m->stream, m->D, m->mean, plane);
+  NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->D, m->mean, plane, img);
+  return MLF_OK;
+}
+
+// loss of the current m->D against the increment target, gradient into m->dD
+mlf_status loss_and_grad(mlf_nop* m, int batch, const float* h0, const float* h1, bool want_grad, double* loss) {
+  const int N = m->p.n_layers;
+  const long long plane = (long long)m->p.ny * m->p.nx, img = (long long)batch * N * plane;
+  NLAUNCH(target_inc, dim3(grid1(img)), dim3(256), 0, m->stream, h0, h1, m->tgt, (float)(1.0 / m->p.scale), img);
+  NLAUNCH(mse, dim3(kRedBlocks), dim3(256), 0, m->stream, m->D, m->tgt, want_grad ? m->dD : nullptr, m->loss_part,
+          img);
+  float parts[kRedBlocks];
+  NHIP(hipMemcpyAsync(parts, m->loss_part, sizeof parts, hipMemcpyDeviceToHost, m->stream));
+  NHIP(hipStreamSynchronize(m->stream));
+  double s = 0.0;
+  for (int i = 0; i < kRedBlocks; ++i) s += parts[i];
+  *loss = s / (double)img;
+  return MLF_OK;
+}
+
+// gradient of the loss w.r.t. all parameters into m->grad (after forward
+// and loss_and_grad with the gradient)
+mlf_status backward(mlf_nop* m, int batch) {
+  const int N = m->p.n_layers;
+  const long long plane = (long long)m->p.ny * m->p.nx, img = (long long)batch * N * plane;
+  const long long npix = (long long)batch * m->gy * m->gx, lat = npix * m->C, J = m->J, C = m->C;
+  const long long cc = 9LL * C * C;
+  // the projection (no net mass change) is symmetric: project the gradient
+  NLAUNCH(plane_mean, dim3(batch * N), dim3(256), 0, m->stream, m->dD, m->mean, plane);
+  NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->dD, m->mean, plane, img);
+  // decoder: weights, bias, input gradient
+  NLAUNCH(patch_outer, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->r + m->L * m->lat, m->part, N, m->p.ny,
+          m->p.nx, m->C, npix);
+  NLAUNCH(sum_rows, dim3(grid1(J * C)), dim3(256), 0, m->stream, m->part, m->grad + m->oWd, kRedBlocks, J * C, 0);
+  NLAUNCH(patch_sum, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->part, N, m->p.ny, m->p.nx, npix);
+  NLAUNCH(sum_rows, dim3(grid1(J)), dim3(256), 0, m->stream, m->part, m->grad + m->obd, kRedBlocks, J, 0);
+  NLAUNCH(dec_bwd_in, dim3(grid1(lat)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, m->dr, N, m->p.ny, m->p.nx,
+          m->C, batch);
+  // residual blocks, last to first; m->dr holds dL/dr_{l+1}
+  for (int l = m->L - 1; l >= 0; --l) {
+    const long long ob = l * m->blk_stride;
+    mlf_status st;
+    NLAUNCH(to_bf16, dim3(grid1(lat)), dim3(256), 0, m->stream, m->dr, m->cb, lat);
+    if ((st = bias_grad(m, npix, m->dr, m->grad + m->ob2 + ob)) != MLF_OK) return st;
+    if ((st = conv_wgrad(m, batch, m->gb + l * m->lat, m->cb, m->grad + m->oW2 + ob)) != MLF_OK) return st;
+    if ((st = conv_fwd(m, batch, m->cb, m->w2t + l * cc, nullptr, m->tmp)) != MLF_OK) return st;
+    NLAUNCH(gelu_bwd, dim3(grid1(lat)), dim3(256), 0, m->stream, m->tmp, m->a + l * m->lat, m->c, m->cb, lat);
+    if ((st = bias_grad(m, npix, m->c, m->grad + m->ob1 + ob)) != MLF_OK) return st;
+    if ((st = conv_wgrad(m, batch, m->rb + l * m->lat, m->cb, m->grad + m->oW1 + ob)) != MLF_OK) return st;
+    if ((st = conv_fwd(m, batch, m->cb, m->w1t + l * cc, nullptr, m->tmp)) != MLF_OK) return st;
+    NLAUNCH(add_into, dim3(grid1(lat)), dim3(256), 0, m->stream, m->dr, m->tmp, nullptr, lat);
+  }
+  // encoder
+  NLAUNCH(patch_outer, dim3(kRedBlocks), dim3(256), 0, m->stream, m->x, m->dr, m->part, N, m->p.ny, m->p.nx, m->C,
+          npix);
+  NLAUNCH(sum_rows, dim3(grid1(J * C)), dim3(256), 0, m->stream, m->part, m->grad + m->oWe, kRedBlocks, J * C, 0);
+  return bias_grad(m, npix, m->dr, m->grad + m->obe);
+}
+
+mlf_status check_batch(mlf_nop* m, int batch) {
+  if (batch < 1 || batch > m->p.batch) return nfail(m, MLF_EINVAL, "batch must be 1..the batch it was created for");
+  return MLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlf_status mlf_nop_query_sizes(const mlf_nop_params* p, size_t* param_count, size_t* workspace_bytes) {
+  mlf_status st = check_params(p);
+  if (st != MLF_OK) return st;
+  const Layout s = layout_of(p);
+  if (param_count) *param_count = (size_t)s.npar;
+  if (workspace_bytes) *workspace_bytes = s.bytes;
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_create(const mlf_nop_params* p, void* workspace, void* stream, mlf_nop** out) {
+  if (!out) return MLF_EINVAL;
+  *out = nullptr;
+  mlf_status st = check_params(p);
+  if (st != MLF_OK) return st;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return MLF_EINVAL;
+  mlf_nop* m = new (std::nothrow) mlf_nop();
+  if (!m) return MLF_EINVAL;
+  const Layout s = layout_of(p);
+  m->p = *p;
+  m->C = p->width;
+  m->L = p->blocks;
+  m->J = p->n_layers * kPatch * kPatch;
+  m->gy = p->ny / kPatch;
+  m->gx = p->nx / kPatch;
+  m->npar = s.npar;
+  m->oWe = s.oWe, m->obe = s.obe, m->oW1 = s.oW1, m->ob1 = s.ob1, m->oW2 = s.oW2, m->ob2 = s.ob2;
+  m->blk_stride = s.blk, m->oWd = s.oWd, m->obd = s.obd;
+  m->lat = s.lat, m->img = s.img, m->part_floats = s.part_floats;
+  m->ws = static_cast<unsigned char*>(workspace);
+  m->stream = static_cast<hipStream_t>(stream);
+  unsigned char* w = m->ws;
+  const long long cc = 9LL * m->C * m->C * m->L;
+  m->par = reinterpret_cast<float*>(w + s.off[0]);
+  m->grad = reinterpret_cast<float*>(w + s.off[1]);
+  m->am = reinterpret_cast<float*>(w + s.off[2]);
+  m->av = reinterpret_cast<float*>(w + s.off[3]);
+  __bf16* wb = reinterpret_cast<__bf16*>(w + s.off[4]);
+  m->w1b = wb;
+  m->w1t = wb + cc;
+  m->w2b = wb + 2 * cc;
+  m->w2t = wb + 3 * cc;
+  m->x = reinterpret_cast<float*>(w + s.off[5]);
+  m->tgt = reinterpret_cast<float*>(w + s.off[6]);
+  m->D = reinterpret_cast<float*>(w + s.off[7]);
+  m->dD = reinterpret_cast<float*>(w + s.off[8]);
+  m->mean = reinterpret_cast<float*>(w + s.off[9]);
+  m->loss_part = reinterpret_cast<float*>(w + s.off[10]);
+  m->r = reinterpret_cast<float*>(w + s.off[11]);
+  m->a = reinterpret_cast<float*>(w + s.off[12]);
+  m->c = reinterpret_cast<float*>(w + s.off[13]);
+  m->dr = reinterpret_cast<float*>(w + s.off[14]);
+  m->tmp = reinterpret_cast<float*>(w + s.off[15]);
+  m->rb = reinterpret_cast<__bf16*>(w + s.off[16]);
+  m->gb = reinterpret_cast<__bf16*>(w + s.off[17]);
+  m->cb = reinterpret_cast<__bf16*>(w + s.off[18]);
+  m->part = reinterpret_cast<float*>(w + s.off[19]);
+  m->adam_t = 0;
+  *out = m;
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_set_params(mlf_nop* m, const float* host) {
+  if (!m || !host) return MLF_EINVAL;
+  const size_t bytes = (size_t)m->npar * sizeof(float);
+  NHIP(hipMemcpyAsync(m->par, host, bytes, hipMemcpyHostToDevice, m->stream));
+  NHIP(hipMemsetAsync(m->am, 0, bytes, m->stream));
+  NHIP(hipMemsetAsync(m->av, 0, bytes, m->stream));
+  mlf_status st = refresh_weights(m);
+  if (st != MLF_OK) return st;
+  NHIP(hipStreamSynchronize(m->stream));
+  m->adam_t = 0;
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_get_params(mlf_nop* m, float* host) {
+  if (!m || !host) return MLF_EINVAL;
+  NHIP(hipMemcpyAsync(host, m->par, (size_t)m->npar * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+  NHIP(hipStreamSynchronize(m->stream));
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_predict(mlf_nop* m, int32_t batch, const float* h, float* out) {
+  if (!m || !h || !out) return MLF_EINVAL;
+  mlf_status st = check_batch(m, batch);
+  if (st != MLF_OK) return st;
+  if ((st = forward(m, batch, h)) != MLF_OK) return st;
+  const long long img = (long long)batch * m->p.n_layers * m->p.ny * m->p.nx;
+  NLAUNCH(axpy_out, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->D, out, (float)m->p.scale, img);
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_loss(mlf_nop* m, int32_t batch, const float* h0, const float* h1, double* loss) {
+  if (!m || !h0 || !h1 || !loss) return MLF_EINVAL;
+  mlf_status st = check_batch(m, batch);
+  if (st != MLF_OK) return st;
+  if ((st = forward(m, batch, h0)) != MLF_OK) return st;
+  return loss_and_grad(m, batch, h0, h1, false, loss);
+}
+
+mlf_status mlf_nop_gradient(mlf_nop* m, int32_t batch, const float* h0, const float* h1, float* host_grad,
+                            double* loss) {
+  if (!m || !h0 || !h1 || !loss) return MLF_EINVAL;
+  mlf_status st = check_batch(m, batch);
+  if (st != MLF_OK) return st;
+  if ((st = forward(m, batch, h0)) != MLF_OK) return st;
+  if ((st = loss_and_grad(m, batch, h0, h1, true, loss)) != MLF_OK) return st;
+  if ((st = backward(m, batch)) != MLF_OK) return st;
+  if (host_grad) {
+    NHIP(hipMemcpyAsync(host_grad, m->grad, (size_t)m->npar * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    NHIP(hipStreamSynchronize(m->stream));
+  }
+  return MLF_OK;
+}
+
+mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const float* h1, float lr, double* loss) {
+  if (!(lr > 0.f)) return nfail(m, MLF_EINVAL, "learning rate must be > 0");
+  mlf_status st = mlf_nop_gradient(m, batch, h0, h1, nullptr, loss);
+  if (st != MLF_OK) return st;
+  m->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)m->adam_t), c2 = 1.f - std::pow(b2, (float)m->adam_t);
+  NLAUNCH(adam, dim3(grid1(m->npar)), dim3(256), 0, m->stream, m->par, m->grad, m->am, m->av, m->npar, lr, b1, b2,
+          1e-8f, c1, c2);
+  return refresh_weights(m);
+}
+
+int32_t mlf_nop_steps_done(const mlf_nop* m) { return m ? m->adam_t : -1; }
+
+const char* mlf_nop_last_error(const mlf_nop* m) { return m ? m->err.c_str() : "null surrogate"; }
+
+mlf_status mlf_nop_destroy(mlf_nop* m) {
+  if (!m) return MLF_EINVAL;
+  delete m;
+  return MLF_OK;
+}
+
+}  // extern "C"

@@ -33,6 +33,11 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFIN
           -5: "ENONPOSITIVE", -6: "EUNSTABLE"}
 
 
+class NopParams(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("width", C.c_int32),
+                ("blocks", C.c_int32), ("batch", C.c_int32), ("scale", C.c_double)]
+
+
 class MlfError(RuntimeError):
     def __init__(self, code: int, what: str, detail: str = ""):
         super().__init__(f"{what} failed: {STATUS.get(code, code)}" + (f" ({detail})" if detail else ""))
@@ -107,6 +112,18 @@ def load_library():
         "mlf_batch_failed_film": (C.c_int32, [H]),
         "mlf_batch_last_error": (C.c_char_p, [H]),
         "mlf_batch_destroy": (st, [H]),
+        "mlf_nop_query_sizes": (st, [C.POINTER(NopParams), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "mlf_nop_create": (st, [C.POINTER(NopParams), C.c_void_p, C.c_void_p, C.POINTER(H)]),
+        "mlf_nop_set_params": (st, [H, C.POINTER(C.c_float)]),
+        "mlf_nop_get_params": (st, [H, C.POINTER(C.c_float)]),
+        "mlf_nop_predict": (st, [H, C.c_int32, C.c_void_p, C.c_void_p]),
+        "mlf_nop_loss": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+        "mlf_nop_gradient": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
+                                  C.POINTER(C.c_double)]),
+        "mlf_nop_train_step": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_float, C.POINTER(C.c_double)]),
+        "mlf_nop_steps_done": (C.c_int32, [H]),
+        "mlf_nop_last_error": (C.c_char_p, [H]),
+        "mlf_nop_destroy": (st, [H]),
         "mlf_spreading_from_tensions": (st, [C.c_int32, _D, _D]),
         "mlf_friction_matrix": (st, [C.c_int32, _D, _D, _D, _D]),
         "mlf_version": (C.c_char_p, []),
@@ -437,3 +454,89 @@ class Batch:
     @property
     def failed_film(self) -> int:
         return int(self.lib.mlf_batch_failed_film(self.h))
+
+
+class Surrogate:
+    """The learned surrogate (C ABI mlf_nop_*): a convolutional neural
+    operator advancing layer heights by one window.  Heights are torch
+    float32 CUDA tensors [batch][N][ny][nx]; parameters are a float32 numpy
+    vector in the ABI's packing order."""
+
+    def __init__(self, n_layers, nx, ny, width=128, blocks=3, batch=64, scale=1e-2, stream=None, device=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.p = NopParams(int(n_layers), int(nx), int(ny), int(width), int(blocks), int(batch), float(scale))
+        n, w = C.c_size_t(), C.c_size_t()
+        rc = self.lib.mlf_nop_query_sizes(C.byref(self.p), C.byref(n), C.byref(w))
+        if rc:
+            raise MlfError(rc, "mlf_nop_query_sizes")
+        self.param_count, self.workspace_bytes = n.value, w.value
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = dev
+        self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = C.c_void_p()
+        rc = self.lib.mlf_nop_create(C.byref(self.p), C.c_void_p(self.ws.data_ptr()),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise MlfError(rc, "mlf_nop_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.mlf_nop_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc, what):
+        if rc:
+            d = self.lib.mlf_nop_last_error(self.h)
+            raise MlfError(rc, what, d.decode() if d else "")
+
+    def _dev(self, t):
+        t = self.torch.as_tensor(t)
+        assert t.dtype == self.torch.float32 and t.is_cuda and t.is_contiguous()
+        assert t.dim() == 4 and tuple(t.shape[1:]) == (self.p.n_layers, self.p.ny, self.p.nx)
+        return t
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        assert v.size == self.param_count
+        self._check(self.lib.mlf_nop_set_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float))), "mlf_nop_set_params")
+
+    def get_params(self):
+        v = np.empty(self.param_count, dtype=np.float32)
+        self._check(self.lib.mlf_nop_get_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float))), "mlf_nop_get_params")
+        return v
+
+    def predict(self, h, out=None):
+        h = self._dev(h)
+        out = self.torch.empty_like(h) if out is None else out
+        self._check(self.lib.mlf_nop_predict(self.h, h.shape[0], C.c_void_p(h.data_ptr()), C.c_void_p(out.data_ptr())),
+                    "mlf_nop_predict")
+        return out
+
+    def loss(self, h0, h1):
+        h0, h1 = self._dev(h0), self._dev(h1)
+        v = C.c_double()
+        self._check(self.lib.mlf_nop_loss(self.h, h0.shape[0], C.c_void_p(h0.data_ptr()), C.c_void_p(h1.data_ptr()),
+                                          C.byref(v)), "mlf_nop_loss")
+        return v.value
+
+    def gradient(self, h0, h1):
+        h0, h1 = self._dev(h0), self._dev(h1)
+        g = np.empty(self.param_count, dtype=np.float32)
+        v = C.c_double()
+        self._check(self.lib.mlf_nop_gradient(self.h, h0.shape[0], C.c_void_p(h0.data_ptr()),
+                                              C.c_void_p(h1.data_ptr()), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                              C.byref(v)), "mlf_nop_gradient")
+        return v.value, g
+
+    def train_step(self, h0, h1, lr):
+        h0, h1 = self._dev(h0), self._dev(h1)
+        v = C.c_double()
+        self._check(self.lib.mlf_nop_train_step(self.h, h0.shape[0], C.c_void_p(h0.data_ptr()),
+                                                C.c_void_p(h1.data_ptr()), float(lr), C.byref(v)),
+                    "mlf_nop_train_step")
+        return v.value

@@ -15,9 +15,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    txt = open(os.path.join(ROOT, "include", "mlfilm.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mlf_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", hdr)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mlf_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -172,3 +176,20 @@ def test_set_launch_validation():
         assert b.value == 40
     finally:
         lib.mlf_destroy(h)
+
+
+def test_surrogate_sizes_and_validation():
+    from oracle import nop
+
+    p = mlfilm.NopParams(3, 256, 256, 128, 3, 64, 1e-2)
+    n, w = C.c_size_t(), C.c_size_t()
+    lib = mlfilm.load_library()
+    assert lib.mlf_nop_query_sizes(C.byref(p), C.byref(n), C.byref(w)) == 0
+    assert n.value == nop.layout(3, 128, 3)[1]
+    assert 800_000 < n.value < 1_100_000  # about one million parameters
+    for field, val in [("nx", 200), ("ny", 250), ("n_layers", 5), ("batch", 0), ("blocks", -1), ("scale", 0.0)]:
+        q = mlfilm.NopParams(3, 256, 256, 128, 3, 64, 1e-2)
+        setattr(q, field, val)
+        assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -1, field
+    q = mlfilm.NopParams(3, 256, 256, 96, 3, 64, 1e-2)
+    assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -2

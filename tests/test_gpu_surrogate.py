@@ -1,0 +1,124 @@
+"""The learned surrogate's HIP path (BF16 MFMA convolutions, FP32 elsewhere)
+against the FP64 reference network, which rounds to bfloat16 at the same
+points (oracle/nop.py).
+
+Tolerances.  Both sides round the same values to bfloat16; they differ by
+FP32 versus FP64 accumulation (relative ~1e-6 over the 9C-term sums),
+which now and then moves a value across a bfloat16 rounding boundary (one
+bfloat16 ulp, 2^-8 relative); such flips pass through the following
+layers and are amplified by their gain.  Measured as relative L2 norms
+over whole tensors on these random networks: increments 4e-4 (C = 64) and
+6e-4 (C = 128), three times closer than to the unrounded FP64 network;
+gradients at most 2.1e-3 (first convolution of a block).  The tests allow
+2e-3 for increments and 1e-2 for gradients, and compare the Adam update on
+the GPU's own gradient to 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import nop
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mlf(torch_cuda):
+    from paper_2409_16659_amd import mlfilm
+
+    mlfilm.load_library()
+    return mlfilm
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def setup(mlf, torch, C, L=2, B=2, N=3, ny=16, nx=256, seed=0):
+    rng = np.random.default_rng(seed)
+    vec = nop.init_params(rng, N, C, L)
+    vec += rng.normal(0, 0.01, vec.size)  # every block non-trivial
+    vec = vec.astype(np.float32).astype(np.float64)
+    h0 = (1.0 + 1e-2 * rng.normal(size=(B, N, ny, nx))).astype(np.float32)
+    h1 = (h0 + 1e-3 * rng.normal(size=h0.shape)).astype(np.float32)
+    s = mlf.Surrogate(N, nx, ny, width=C, blocks=L, batch=B, scale=1e-2)
+    s.set_params(vec)
+    net = nop.Net(N, C, L, 1e-2, use_bf16=True)
+    t0 = torch.from_numpy(h0).cuda()
+    t1 = torch.from_numpy(h1).cuda()
+    return s, net, vec, h0.astype(np.float64), h1.astype(np.float64), t0, t1
+
+
+@pytest.mark.parametrize("C", [64, 128])
+def test_predict_matches_reference(mlf, torch_cuda, C):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C)
+    out = s.predict(t0).cpu().numpy().astype(np.float64)
+    d_gpu = (out - h0) / 1e-2
+    d_ref, _ = net.forward(vec, h0)
+    d_64, _ = nop.Net(3, C, 2, 1e-2, use_bf16=False).forward(vec, h0)
+    e = rel(d_gpu, d_ref)
+    print(f"C={C} increment rel L2 {e:.2e} (vs unrounded FP64 network {rel(d_gpu, d_64):.2e})", flush=True)
+    assert e <= 2e-3
+    # each layer's mass is unchanged (FP32 sums)
+    assert np.abs(out.sum(axis=(2, 3)) - h0.sum(axis=(2, 3))).max() <= 1e-6 * h0.sum(axis=(2, 3)).max()
+
+
+@pytest.mark.parametrize("C", [64, 128])
+def test_gradient_matches_reference(mlf, torch_cuda, C):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C, seed=1)
+    loss_g, g_gpu = s.gradient(t0, t1)
+    loss_r, g_ref = net.gradient(vec, h0, h1)
+    assert abs(loss_g - loss_r) <= 2e-3 * loss_r
+    off, n = nop.layout(3, C, 2)
+    assert g_gpu.size == n
+    worst = 0.0
+    for name, (o, sz) in off.items():
+        e = rel(g_gpu[o:o + sz], g_ref[o:o + sz])
+        worst = max(worst, e)
+        print(f"   C={C} {name}: rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-2, name
+    print(f"C={C} worst gradient rel L2 {worst:.2e}", flush=True)
+
+
+def test_adam_step_matches_reference_update(mlf, torch_cuda):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, 64, seed=2)
+    _, g = s.gradient(t0, t1)
+    s.train_step(t0, t1, 1e-3)
+    want, _, _ = nop.adam_step(vec, g.astype(np.float64), np.zeros_like(vec), np.zeros_like(vec), 1, 1e-3)
+    got = s.get_params().astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-6
+
+
+def test_shift_by_whole_patches(mlf, torch_cuda):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, 64, seed=3)
+    t0s = torch_cuda.roll(t0, (4, 8), (2, 3)).contiguous()
+    da = (s.predict(t0).cpu().numpy().astype(np.float64) - h0) / 1e-2
+    db = (s.predict(t0s).cpu().numpy().astype(np.float64) - t0s.cpu().numpy()) / 1e-2
+    # the convolutions see the same values; only the per-layer means sum in another order
+    assert rel(np.roll(da, (4, 8), (2, 3)), db) <= 1e-4
+
+
+def test_training_reduces_the_loss(mlf, torch_cuda):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, 64, seed=4)
+    first = s.loss(t0, t1)
+    for _ in range(30):
+        s.train_step(t0, t1, 3e-3)
+    last = s.loss(t0, t1)
+    print(f"loss {first:.4e} -> {last:.4e}", flush=True)
+    assert last < 0.5 * first
+
+
+def test_batch_limit(mlf, torch_cuda):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, 64, B=2)
+    big = torch_cuda.cat([t0, t0, t0]).contiguous()
+    with pytest.raises(mlf.MlfError) as e:
+        s.predict(big)
+    assert e.value.status == "EINVAL"

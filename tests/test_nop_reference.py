@@ -1,0 +1,88 @@
+"""Pins of the surrogate network's FP64 reference (oracle/nop.py) against
+facts that do not come from the reference itself: central finite
+differences of its loss, exact conservation of each layer's mass by the
+predicted increment, equivariance under periodic shifts by whole patches,
+bfloat16 rounding as torch implements it, and Adam written out for one
+scalar."""
+import numpy as np
+import pytest
+
+from oracle import nop
+
+
+def tiny(use_bf16=False, N=2, C=4, L=2, ny=8, nx=8, B=2, seed=0):
+    rng = np.random.default_rng(seed)
+    net = nop.Net(N, C, L, scale=1e-2, use_bf16=use_bf16)
+    vec = nop.init_params(rng, N, C, L)
+    vec += rng.normal(0, 0.2, vec.size)  # away from the small-output start
+    h0 = 1.0 + 1e-2 * rng.normal(size=(B, N, ny, nx))
+    h1 = h0 + 1e-3 * rng.normal(size=(B, N, ny, nx))
+    return net, vec, h0, h1
+
+
+def test_gradient_matches_central_differences():
+    net, vec, h0, h1 = tiny()
+    loss, g = net.gradient(vec, h0, h1)
+    eps = 1e-6
+    fd = np.empty_like(vec)
+    for k in range(vec.size):
+        e = np.zeros_like(vec)
+        e[k] = eps
+        fd[k] = (net.loss(vec + e, h0, h1)[0] - net.loss(vec - e, h0, h1)[0]) / (2 * eps)
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    assert err < 1e-6, err
+    # every parameter block receives gradient
+    off, _ = nop.layout(2, 4, 2)
+    for name, (o, s) in off.items():
+        assert np.abs(g[o:o + s]).max() > 0, name
+
+
+def test_increment_conserves_each_layer_mass():
+    net, vec, h0, _ = tiny()
+    out = net.predict(vec, h0)
+    assert np.abs(out.sum(axis=(2, 3)) - h0.sum(axis=(2, 3))).max() < 1e-12
+
+
+def test_equivariant_under_patch_shifts():
+    net, vec, h0, _ = tiny(ny=16, nx=12)
+    a = net.predict(vec, h0)
+    for dy, dx in ((4, 0), (0, 8), (12, 4)):
+        b = net.predict(vec, np.roll(h0, (dy, dx), axis=(2, 3)))
+        assert np.abs(np.roll(a, (dy, dx), axis=(2, 3)) - b).max() < 1e-12
+
+
+def test_conv_adjoints():
+    """<conv(X, W), Y> = <X, conv^T(Y, W)> = <W, wgrad(X, Y)>."""
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(2, 5, 6, 3))
+    Y = rng.normal(size=(2, 5, 6, 4))
+    W = rng.normal(size=(9, 4, 3))
+    lhs = np.sum(nop.conv3x3(X, W) * Y)
+    assert abs(lhs - np.sum(X * nop.conv3x3_input_grad(Y, W))) < 1e-10
+    assert abs(lhs - np.sum(W * nop.conv3x3_weight_grad(X, Y))) < 1e-10
+
+
+def test_patch_shuffle_round_trip():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(2, 3, 8, 12))
+    P = nop.patches(x)
+    assert P.shape == (2, 2, 3, 48)
+    assert np.array_equal(nop.unpatch(P, 3), x)
+    # value j = (i * 4 + u) * 4 + v of latent pixel (py, px)
+    assert P[1, 1, 2, (2 * 4 + 3) * 4 + 1] == x[1, 2, 4 + 3, 8 + 1]
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    a = np.concatenate([rng.normal(size=1000) * 10.0 ** rng.integers(-8, 8, 1000),
+                        [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 65504.0]])
+    ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(nop.bf16(a), ref)
+
+
+def test_adam_one_scalar():
+    v, m, s = nop.adam_step(np.array([1.0]), np.array([0.5]), np.zeros(1), np.zeros(1), 1, lr=0.1)
+    # first step: m_hat = g, v_hat = g^2, update = lr * g / (|g| + eps)
+    assert abs(v[0] - (1.0 - 0.1 * 0.5 / (0.5 + 1e-8))) < 1e-15
+    assert abs(m[0] - 0.05) < 1e-15 and abs(s[0] - 0.00025) < 1e-15
