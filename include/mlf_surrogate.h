@@ -72,6 +72,13 @@ mlf_status mlf_nop_gradient(mlf_nop* m, int32_t batch, const float* h0, const fl
  * the loss before the step; synchronises. */
 mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const float* h1, float lr, double* loss);
 
+/* Event-timed average duration (ms) of one 3x3 convolution of the first
+ * block on `batch` samples: forward (also the input-gradient kernel) and
+ * weight gradient, `reps` launches each, on the activations as they stand
+ * (run mlf_nop_predict first).  Overwrites scratch activations only.
+ * Synchronises. */
+mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad);
+
 int32_t mlf_nop_steps_done(const mlf_nop* m);
 const char* mlf_nop_last_error(const mlf_nop* m);
 mlf_status mlf_nop_destroy(mlf_nop* m);

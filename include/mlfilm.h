@@ -203,6 +203,12 @@ mlf_status mlf_batch_create(const mlf_params* films, int32_t n, void* pop_a, voi
 /* Initialise film `film` exactly as mlf_init does for one film (same
  * checks and errors).  Every film must be initialised before stepping. */
 mlf_status mlf_batch_init(mlf_batch* b, int32_t film, const double* hgt, const double* ux, const double* uy);
+/* As mlf_batch_init from device FP64 arrays (as mlf_init_device). */
+mlf_status mlf_batch_init_device(mlf_batch* b, int32_t film, const double* hgt, const double* ux, const double* uy);
+/* Every film at once from device FP64 heights (U = 0): hgts is a host
+ * array of n device pointers, hgts[f] of film f's shape [N][ny][nx].  Same
+ * checks as mlf_init for each film, one synchronisation for all. */
+mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts);
 
 /* Advance every film by nsteps >= 0 steps: one launch per step, or replays
  * of the captured graph where it fits.  The guard flags of all films are
@@ -218,6 +224,11 @@ mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps);
 /* Read-back and FP64 per-layer mass of one film, as mlf_read and
  * mlf_layer_mass (synchronise). */
 mlf_status mlf_batch_read(mlf_batch* b, int32_t film, double* hgt, double* ux, double* uy);
+/* As mlf_batch_read into device FP64 arrays; asynchronous on the stream. */
+mlf_status mlf_batch_read_device(mlf_batch* b, int32_t film, double* hgt, double* ux, double* uy);
+/* Heights of every film into device FP64 arrays outs[f] (host array of n
+ * device pointers); asynchronous on the stream. */
+mlf_status mlf_batch_read_device_all(mlf_batch* b, double* const* outs);
 mlf_status mlf_batch_layer_mass(mlf_batch* b, int32_t film, double* mass);
 
 /* Launch shape shared by all films: block_w in {64, 128, 192, 256}, seg_h

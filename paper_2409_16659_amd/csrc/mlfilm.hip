@@ -1199,7 +1199,8 @@ constexpr size_t kBatchTableOff = kBatchFlagOff + kMaxFilms * sizeof(int);  // B
 constexpr size_t kBatchTableBytes = 4u << 20;
 constexpr size_t kBatchItemOff = kBatchTableOff + kBatchTableBytes;         // int2[n_items]
 constexpr size_t kBatchItemBytes = 12u << 20;
-constexpr size_t kBatchScratchBytes = kBatchItemOff + kBatchItemBytes;
+constexpr size_t kBatchSumOff = kBatchItemOff + kBatchItemBytes;          // double sums[kMaxFilms][4]
+constexpr size_t kBatchScratchBytes = kBatchSumOff + kMaxFilms * kMaxLayers * sizeof(double);
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -1493,6 +1494,87 @@ mlf_status mlf_batch_init(mlf_batch* b, int32_t film, const double* hgt, const d
   return MLF_OK;
 }
 
+mlf_status mlf_batch_init_device(mlf_batch* b, int32_t film, const double* hgt, const double* ux, const double* uy) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  b->ready[film] = false;
+  st = mlf_init_device(h, hgt, ux, uy);
+  if (st != MLF_OK) return bfail(b, st, "film " + std::to_string(film) + ": " + h->err);
+  BHIPCHK(hipMemsetAsync(batch_flags(b) + film, 0, sizeof(int), b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  b->ready[film] = true;
+  b->table_dirty = true;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
+  if (!b || !hgts) return MLF_EINVAL;
+  double* sums = reinterpret_cast<double*>(b->scratch + kBatchSumOff);
+  for (int f = 0; f < b->n; ++f) {
+    if (!hgts[f]) return bfail(b, MLF_EINVAL, "null height array");
+    mlf_handle* h = b->film[f];
+    const long long nn = (long long)h->p.nx * h->p.ny;
+    b->ready[f] = false;
+    h->initialised = false;
+    drop_single_graph(h);
+    // per-film sums: the partials area is reused in stream order
+    hipLaunchKernelGGL(field_partials, dim3(kRedBlocks), dim3(256), 0, b->stream, hgts[f], part_ptr(h), nn,
+                       h->p.n_layers);
+    BHIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, b->stream, part_ptr(h), sums + (size_t)f * kMaxLayers,
+                       kRedBlocks, h->p.n_layers);
+    BHIPCHK(hipGetLastError());
+  }
+  std::vector<double> hs((size_t)b->n * kMaxLayers);
+  BHIPCHK(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  for (int f = 0; f < b->n; ++f) {
+    mlf_handle* h = b->film[f];
+    const long long nn = (long long)h->p.nx * h->p.ny;
+    for (int i = 0; i < h->p.n_layers; ++i) {
+      h->hbar[i] = hs[(size_t)f * kMaxLayers + i] / (double)nn;
+      if (!std::isfinite(h->hbar[i])) return bfail(b, MLF_ENONFINITE, "film " + std::to_string(f) + ": not finite");
+      if (!(h->hbar[i] > 0.0)) return bfail(b, MLF_ENONPOSITIVE, "film " + std::to_string(f) + ": height <= 0");
+    }
+    set_scales(h);
+    mlf_status st = check_stability(h);
+    if (st != MLF_OK) return bfail(b, st, "film " + std::to_string(f) + ": " + h->err);
+  }
+  for (int f = 0; f < b->n; ++f) {
+    mlf_handle* h = b->film[f];
+    h->cur = b->cur;
+    mlf_status st = zero_buffers(h);
+    if (st == MLF_OK) st = launch_init(h, hgts[f], nullptr, nullptr, (long long)h->p.nx * h->p.ny, 0, 0, h->p.ny);
+    if (st != MLF_OK) return bfail(b, st, h->err);
+  }
+  BHIPCHK(hipMemsetAsync(batch_flags(b), 0, b->n * sizeof(int), b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  for (int f = 0; f < b->n; ++f) {
+    b->film[f]->steps = 0;
+    b->film[f]->initialised = true;
+    b->ready[f] = true;
+  }
+  b->table_dirty = true;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_read_device_all(mlf_batch* b, double* const* outs) {
+  if (!b || !outs) return MLF_EINVAL;
+  for (int f = 0; f < b->n; ++f) {
+    if (!b->ready[f]) return bfail(b, MLF_EINVAL, "film " + std::to_string(f) + " is not initialised");
+    if (!outs[f]) return bfail(b, MLF_EINVAL, "null output array");
+    mlf_handle* h = b->film[f];
+    h->cur = b->cur;
+    const long long nn = (long long)h->p.nx * h->p.ny;
+    mlf_status st = launch_read(h, outs[f], nullptr, nullptr, nn, 0, 0, h->p.ny);
+    if (st != MLF_OK) return bfail(b, st, h->err);
+  }
+  return MLF_OK;
+}
+
 mlf_status mlf_batch_step(mlf_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return MLF_EINVAL;
   mlf_status st = batch_ready(b);
@@ -1548,6 +1630,16 @@ mlf_status mlf_batch_read(mlf_batch* b, int32_t film, double* hgt, double* ux, d
   mlf_handle* h = b->film[film];
   h->cur = b->cur;
   st = mlf_read(h, hgt, ux, uy);
+  return st == MLF_OK ? st : bfail(b, st, h->err);
+}
+
+mlf_status mlf_batch_read_device(mlf_batch* b, int32_t film, double* hgt, double* ux, double* uy) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  st = mlf_read_device(h, hgt, ux, uy);
   return st == MLF_OK ? st : bfail(b, st, h->err);
 }
 

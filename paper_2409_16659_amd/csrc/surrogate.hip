@@ -69,58 +69,110 @@ __global__ void target_inc(const float* __restrict__ h0, const float* __restrict
 }
 
 // patch encoder: r[b][py][px][c] = be[c] + sum_j We[j][c] x[b][i][4py+u][4px+v], j = (i*4+u)*4+v
-__global__ void enc_fwd(const float* __restrict__ x, const float* __restrict__ We, const float* __restrict__ be,
-                        float* __restrict__ r, __bf16* __restrict__ rb, int nl, int ny, int nx, int C, int batch) {
+// A wave takes 64 latent pixels (one per lane) and 32 channels, so the
+// weights are the same for all its lanes (scalar loads).
+__global__ void __launch_bounds__(256) enc_fwd(const float* __restrict__ x, const float* __restrict__ We,
+                                               const float* __restrict__ be, float* __restrict__ r,
+                                               __bf16* __restrict__ rb, int nl, int ny, int nx, int C, int batch) {
   const int gy = ny / kPatch, gx = nx / kPatch;
-  const long long total = (long long)batch * gy * gx * C;
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-    const int c = (int)(t % C);
-    const long long pix = t / C;
+  const long long npix = (long long)batch * gy * gx;
+  const int groups = C / 32;
+  const long long waves = (npix + 63) / 64 * groups;
+  const int lane = threadIdx.x & 63;
+  for (long long wv = blockIdx.x * 4LL + (threadIdx.x >> 6); wv < waves; wv += gridDim.x * 4LL) {
+    const int c0 = (int)(wv % groups) * 32;
+    const long long pix = (wv / groups) * 64 + lane;
+    if (pix >= npix) continue;
     const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
-    float s = be[c];
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = be[c0 + c];
     for (int i = 0; i < nl; ++i)
-      for (int u = 0; u < kPatch; ++u)
-        for (int v = 0; v < kPatch; ++v)
-          s += We[(long long)((i * kPatch + u) * kPatch + v) * C + c] *
-               x[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v];
-    r[t] = s;
-    rb[t] = (__bf16)s;
+      for (int u = 0; u < kPatch; ++u) {
+        const float4 xv = *reinterpret_cast<const float4*>(
+            x + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
+        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float* wr = We + (long long)((i * kPatch + u) * kPatch + v) * C + c0;
+#pragma unroll
+          for (int c = 0; c < 32; ++c) acc[c] += wr[c] * xs[v];
+        }
+      }
+    float* ro = r + pix * C + c0;
+    __bf16* rbo = rb + pix * C + c0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      ro[c] = acc[c];
+      rbo[c] = (__bf16)acc[c];
+    }
   }
 }
 
 // decoder + pixel shuffle: D[b][i][4py+u][4px+v] = bd[j] + sum_c Wd[j][c] r[b][py][px][c], j = (i*4+u)*4+v
-__global__ void dec_fwd(const float* __restrict__ r, const float* __restrict__ Wd, const float* __restrict__ bd,
-                        float* __restrict__ D, int nl, int ny, int nx, int C, int batch) {
+// One lane per latent pixel computes its 16N outputs; the weights are the
+// same for the whole wave (scalar loads).  Requires 16N <= 64.
+__global__ void __launch_bounds__(256) dec_fwd(const float* __restrict__ r, const float* __restrict__ Wd,
+                                               const float* __restrict__ bd, float* __restrict__ D, int nl, int ny,
+                                               int nx, int C, int batch) {
   const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
-  const long long total = (long long)batch * gy * gx * J;
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-    const int j = (int)(t % J);
-    const long long pix = t / J;
+  const long long npix = (long long)batch * gy * gx;
+  for (long long pix = blockIdx.x * 256LL + threadIdx.x; pix < npix; pix += (long long)gridDim.x * 256) {
     const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+    float acc[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) acc[j] = j < J ? bd[j] : 0.f;
     const float* rp = r + pix * C;
-    const float* wp = Wd + (long long)j * C;
-    float s = bd[j];
-    for (int c = 0; c < C; ++c) s += wp[c] * rp[c];
-    const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
-    D[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v] = s;
+    for (int c = 0; c < C; c += 4) {
+      const float4 rv = *reinterpret_cast<const float4*>(rp + c);
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        if (j < J) {
+          const float* wp = Wd + (long long)j * C + c;
+          acc[j] += wp[0] * rv.x + wp[1] * rv.y + wp[2] * rv.z + wp[3] * rv.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (j < J) {
+        const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
+        D[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v] = acc[j];
+      }
   }
 }
 
 // decoder input gradient: dr[b][py][px][c] = sum_j Wd[j][c] dD[b][i][4py+u][4px+v]
-__global__ void dec_bwd_in(const float* __restrict__ dD, const float* __restrict__ Wd, float* __restrict__ dr,
-                           int nl, int ny, int nx, int C, int batch) {
-  const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
-  const long long total = (long long)batch * gy * gx * C;
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-    const int c = (int)(t % C);
-    const long long pix = t / C;
+// A wave takes 64 latent pixels and 32 channels (scalar weight loads).
+__global__ void __launch_bounds__(256) dec_bwd_in(const float* __restrict__ dD, const float* __restrict__ Wd,
+                                                  float* __restrict__ dr, int nl, int ny, int nx, int C, int batch) {
+  const int gy = ny / kPatch, gx = nx / kPatch;
+  const long long npix = (long long)batch * gy * gx;
+  const int groups = C / 32;
+  const long long waves = (npix + 63) / 64 * groups;
+  const int lane = threadIdx.x & 63;
+  for (long long wv = blockIdx.x * 4LL + (threadIdx.x >> 6); wv < waves; wv += gridDim.x * 4LL) {
+    const int c0 = (int)(wv % groups) * 32;
+    const long long pix = (wv / groups) * 64 + lane;
+    if (pix >= npix) continue;
     const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
-    float s = 0.f;
-    for (int j = 0; j < J; ++j) {
-      const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
-      s += Wd[(long long)j * C + c] * dD[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v];
-    }
-    dr[t] = s;
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
+    for (int i = 0; i < nl; ++i)
+      for (int u = 0; u < kPatch; ++u) {
+        const float4 dv = *reinterpret_cast<const float4*>(
+            dD + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
+        const float ds[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float* wr = Wd + (long long)((i * kPatch + u) * kPatch + v) * C + c0;
+#pragma unroll
+          for (int c = 0; c < 32; ++c) acc[c] += wr[c] * ds[v];
+        }
+      }
+    float* o = dr + pix * C + c0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) o[c] = acc[c];
   }
 }
 
@@ -128,23 +180,64 @@ __global__ void dec_bwd_in(const float* __restrict__ dD, const float* __restrict
 //   part[blk][j][c] = sum_{pix in slice} P[pix][j] Q[pix][c]
 // where P[pix][j] is value j of the 4x4 patch of latent pixel pix in a
 // full-resolution tensor (the encoder input, or the decoder output
-// gradient) and Q a latent tensor.
+// gradient) and Q a latent tensor.  Chunks of 32 pixels are staged in LDS;
+// each thread accumulates an 8 x 4 tile of (j, c).  Requires 16N <= 64 and
+// C <= 128.
 __global__ void __launch_bounds__(256) patch_outer(const float* __restrict__ img, const float* __restrict__ lat,
                                                    float* __restrict__ part, int nl, int ny, int nx, int C,
                                                    long long npix) {
+  constexpr int CH = 32;
+  __shared__ float sp[CH][64];
+  __shared__ float sq[CH][128];
   const int gy = ny / kPatch, gx = nx / kPatch, J = nl * kPatch * kPatch;
   const long long per = (npix + gridDim.x - 1) / gridDim.x;
   const long long p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
-  for (int e = threadIdx.x; e < J * C; e += 256) {
-    const int j = e / C, c = e % C;
-    const int i = j / (kPatch * kPatch), u = (j / kPatch) % kPatch, v = j % kPatch;
-    float s = 0.f;
-    for (long long pix = p0; pix < p1; ++pix) {
+  const int jg = threadIdx.x / 32, cg = threadIdx.x % 32;  // j0 = 8 jg, c0 = 4 cg
+  float acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[a][q] = 0.f;
+  for (long long q0 = p0; q0 < p1; q0 += CH) {
+    const int n = (int)min((long long)CH, p1 - q0);
+    // stage patches: 4-float rows (i, u) of each pixel
+    for (int t = threadIdx.x; t < n * nl * kPatch; t += 256) {
+      const int k = t / (nl * kPatch), iu = t % (nl * kPatch), i = iu / kPatch, u = iu % kPatch;
+      const long long pix = q0 + k;
       const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
-      s += img[(((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px + v] * lat[pix * C + c];
+      const float4 v = *reinterpret_cast<const float4*>(
+          img + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
+      float* d = &sp[k][(i * kPatch + u) * kPatch];
+      d[0] = v.x, d[1] = v.y, d[2] = v.z, d[3] = v.w;
     }
-    part[(long long)blockIdx.x * J * C + e] = s;
+    for (int t = threadIdx.x; t < n * (C / 4); t += 256) {
+      const int k = t / (C / 4), c4 = (t % (C / 4)) * 4;
+      const float4 v = *reinterpret_cast<const float4*>(lat + (q0 + k) * C + c4);
+      sq[k][c4] = v.x, sq[k][c4 + 1] = v.y, sq[k][c4 + 2] = v.z, sq[k][c4 + 3] = v.w;
+    }
+    __syncthreads();
+    if (8 * jg < J && 4 * cg < C)
+      for (int k = 0; k < n; ++k) {
+        float pv[8], qv[4];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) pv[a] = sp[k][8 * jg + a];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) qv[q] = sq[k][4 * cg + q];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[a][q] += pv[a] * qv[q];
+      }
+    __syncthreads();
   }
+  float* o = part + (long long)blockIdx.x * J * C;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = 8 * jg + a, c = 4 * cg + q;
+      if (j < J && c < C) o[(long long)j * C + c] = acc[a][q];
+    }
 }
 
 // partial patch sums: part[blk][j] = sum_{pix in slice} P[pix][j]
@@ -439,8 +532,8 @@ mlf_status forward(mlf_nop* m, int batch, const float* h) {
   NLAUNCH(plane_mean, dim3(batch * N), dim3(256), 0, m->stream, h, m->mean, plane);
   NLAUNCH(center_scale, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->mean, m->x, plane, img,
           (float)(1.0 / m->p.scale));
-  NLAUNCH(enc_fwd, dim3(grid1(lat)), dim3(256), 0, m->stream, m->x, m->par + m->oWe, m->par + m->obe, m->r, m->rb, N,
-          m->p.ny, m->p.nx, m->C, batch);
+  NLAUNCH(enc_fwd, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->x, m->par + m->oWe, m->par + m->obe, m->r,
+          m->rb, N, m->p.ny, m->p.nx, m->C, batch);
   const long long cc = 9LL * m->C * m->C;
   for (int l = 0; l < m->L; ++l) {
     float* rl = m->r + l * m->lat;
@@ -455,8 +548,7 @@ mlf_status forward(mlf_nop* m, int batch, const float* h) {
     NLAUNCH(resid_add, dim3(grid1(lat)), dim3(256), 0, m->stream, rl, m->c, m->r + (l + 1) * m->lat,
             m->rb + (l + 1) * m->lat, lat);
   }
-  const long long J = m->J;
-  NLAUNCH(dec_fwd, dim3(grid1(npix * J)), dim3(256), 0, m->stream, m->r + m->L * m->lat, m->par + m->oWd,
+  NLAUNCH(dec_fwd, dim3(grid1(npix)), dim3(256), 0, m->stream, m->r + m->L * m->lat, m->par + m->oWd,
           m->par + m->obd, m->D, N, m->p.ny, m->p.nx, m->C, batch);
   NLAUNCH(plane_mean, dim3(batch * N), dim3(256), 0, m->stream, m->D, m->mean, plane);
   NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->D, m->mean, plane, img);
@@ -495,8 +587,8 @@ mlf_status backward(mlf_nop* m, int batch) {
   NLAUNCH(sum_rows, dim3(grid1(J * C)), dim3(256), 0, m->stream, m->part, m->grad + m->oWd, kRedBlocks, J * C, 0);
   NLAUNCH(patch_sum, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->part, N, m->p.ny, m->p.nx, npix);
   NLAUNCH(sum_rows, dim3(grid1(J)), dim3(256), 0, m->stream, m->part, m->grad + m->obd, kRedBlocks, J, 0);
-  NLAUNCH(dec_bwd_in, dim3(grid1(lat)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, m->dr, N, m->p.ny, m->p.nx,
-          m->C, batch);
+  NLAUNCH(dec_bwd_in, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, m->dr, N, m->p.ny,
+          m->p.nx, m->C, batch);
   // residual blocks, last to first; m->dr holds dL/dr_{l+1}
   for (int l = m->L - 1; l >= 0; --l) {
     const long long ob = l * m->blk_stride;
@@ -651,6 +743,43 @@ mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const 
   NLAUNCH(adam, dim3(grid1(m->npar)), dim3(256), 0, m->stream, m->par, m->grad, m->am, m->av, m->npar, lr, b1, b2,
           1e-8f, c1, c2);
   return refresh_weights(m);
+}
+
+mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad) {
+  if (!m || reps < 1) return MLF_EINVAL;
+  mlf_status st = check_batch(m, batch);
+  if (st != MLF_OK) return st;
+  if (m->L < 1) return nfail(m, MLF_EINVAL, "no convolution layers");
+  hipEvent_t e0, e1, e2;
+  NHIP(hipEventCreate(&e0));
+  NHIP(hipEventCreate(&e1));
+  NHIP(hipEventCreate(&e2));
+  // operands: the first block's input and weights as they stand
+  st = conv_fwd(m, batch, m->rb, m->w1b, m->par + m->ob1, m->a);
+  if (st == MLF_OK) st = nhip(m, hipEventRecord(e0, m->stream), "hipEventRecord");
+  for (int r = 0; r < reps && st == MLF_OK; ++r) st = conv_fwd(m, batch, m->rb, m->w1b, m->par + m->ob1, m->a);
+  if (st == MLF_OK) st = nhip(m, hipEventRecord(e1, m->stream), "hipEventRecord");
+  for (int r = 0; r < reps && st == MLF_OK; ++r) {
+    if (m->C == 64)
+      hipLaunchKernelGGL(nop::conv3x3_wgrad<64>, dim3(batch * 9), dim3(256), 0, m->stream, m->rb, m->gb, m->part,
+                         m->gy, m->gx);
+    else
+      hipLaunchKernelGGL(nop::conv3x3_wgrad<128>, dim3(batch * 9), dim3(256), 0, m->stream, m->rb, m->gb, m->part,
+                         m->gy, m->gx);
+    st = nhip(m, hipGetLastError(), "conv3x3_wgrad");
+  }
+  if (st == MLF_OK) st = nhip(m, hipEventRecord(e2, m->stream), "hipEventRecord");
+  if (st == MLF_OK) st = nhip(m, hipEventSynchronize(e2), "hipEventSynchronize");
+  float a = 0.f, b = 0.f;
+  if (st == MLF_OK) st = nhip(m, hipEventElapsedTime(&a, e0, e1), "hipEventElapsedTime");
+  if (st == MLF_OK) st = nhip(m, hipEventElapsedTime(&b, e1, e2), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  if (st != MLF_OK) return st;
+  if (ms_fwd) *ms_fwd = a / reps;
+  if (ms_wgrad) *ms_wgrad = b / reps;
+  return MLF_OK;
 }
 
 int32_t mlf_nop_steps_done(const mlf_nop* m) { return m ? m->adam_t : -1; }

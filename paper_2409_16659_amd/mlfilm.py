@@ -104,6 +104,10 @@ def load_library():
         "mlf_batch_capture": (st, [H, C.c_int32]),
         "mlf_batch_read": (st, [H, C.c_int32, _D, _D, _D]),
         "mlf_batch_layer_mass": (st, [H, C.c_int32, _D]),
+        "mlf_batch_read_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "mlf_batch_init_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "mlf_batch_init_device_all": (st, [H, C.POINTER(C.c_void_p)]),
+        "mlf_batch_read_device_all": (st, [H, C.POINTER(C.c_void_p)]),
         "mlf_batch_set_launch": (st, [H, C.c_int32, C.c_int32, C.c_int32]),
         "mlf_batch_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_batch_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -121,6 +125,7 @@ def load_library():
         "mlf_nop_gradient": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
                                   C.POINTER(C.c_double)]),
         "mlf_nop_train_step": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_float, C.POINTER(C.c_double)]),
+        "mlf_nop_time_conv": (st, [H, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mlf_nop_steps_done": (C.c_int32, [H]),
         "mlf_nop_last_error": (C.c_char_p, [H]),
         "mlf_nop_destroy": (st, [H]),
@@ -268,6 +273,8 @@ class Film:
     def init(self, h, ux=None, uy=None):
         t = self.torch
         if isinstance(h, t.Tensor):
+            if self._own_stream:
+                t.cuda.current_stream(self.device).synchronize()
             args = [None if a is None else C.c_void_p(a.data_ptr()) for a in (h, ux, uy)]
             for a in (h, ux, uy):
                 if a is not None:
@@ -407,6 +414,15 @@ class Batch:
 
     def init(self, f, h, ux=None, uy=None):
         p = self.params[f]
+        t = self.torch
+        if isinstance(h, t.Tensor):
+            assert h.dtype == t.float64 and h.is_cuda and h.is_contiguous()
+            assert tuple(h.shape) == (p.n_layers, p.ny, p.nx) and ux is None and uy is None
+            # h comes from torch's stream; the batch reads it on its own
+            t.cuda.current_stream(self.device).synchronize()
+            self._check(self.lib.mlf_batch_init_device(self.h, int(f), C.c_void_p(h.data_ptr()), None, None),
+                        "mlf_batch_init_device")
+            return
         h = _f64(h)
         assert h.shape == (p.n_layers, p.ny, p.nx)
         ux = None if ux is None else _f64(ux)
@@ -425,6 +441,47 @@ class Batch:
         h, ux, uy = np.empty(shape), np.empty(shape), np.empty(shape)
         self._check(self.lib.mlf_batch_read(self.h, int(f), _dp(h), _dp(ux), _dp(uy)), "mlf_batch_read")
         return h, ux, uy
+
+    def read_device(self, f, out=None):
+        """Heights of film f as a device FP64 tensor [N][ny][nx], written
+        asynchronously on the batch's stream: synchronise that stream before
+        using it on another one."""
+        p = self.params[f]
+        t = self.torch
+        if out is None:
+            out = t.empty((p.n_layers, p.ny, p.nx), dtype=t.float64, device=self.device)
+        assert out.dtype == t.float64 and out.is_contiguous() and tuple(out.shape) == (p.n_layers, p.ny, p.nx)
+        self._check(self.lib.mlf_batch_read_device(self.h, int(f), C.c_void_p(out.data_ptr()), None, None),
+                    "mlf_batch_read_device")
+        return out
+
+    def _ptrs(self, t):
+        """Device pointers of the per-film slices of a [films][N][ny][nx] FP64 tensor."""
+        p0 = self.params[0]
+        T = self.torch
+        assert all((p.n_layers, p.ny, p.nx) == (p0.n_layers, p0.ny, p0.nx) for p in self.params)
+        assert t.dtype == T.float64 and t.is_cuda and t.is_contiguous()
+        assert tuple(t.shape) == (self.n, p0.n_layers, p0.ny, p0.nx)
+        step = t[0].numel() * 8
+        return (C.c_void_p * self.n)(*[t.data_ptr() + f * step for f in range(self.n)])
+
+    def init_all(self, h):
+        """Initialise every film (all of one shape) from a device FP64 tensor
+        [films][N][ny][nx], with one synchronisation."""
+        ptrs = self._ptrs(h)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._check(self.lib.mlf_batch_init_device_all(self.h, ptrs), "mlf_batch_init_device_all")
+
+    def read_all(self, out=None):
+        """Heights of every film (all of one shape) as a device FP64 tensor
+        [films][N][ny][nx]; the batch's stream is synchronised before return."""
+        p0 = self.params[0]
+        if out is None:
+            out = self.torch.empty((self.n, p0.n_layers, p0.ny, p0.nx), dtype=self.torch.float64,
+                                   device=self.device)
+        self._check(self.lib.mlf_batch_read_device_all(self.h, self._ptrs(out)), "mlf_batch_read_device_all")
+        self.stream.synchronize()
+        return out
 
     def mass(self, f):
         m = np.empty(self.params[f].n_layers)
@@ -532,6 +589,17 @@ class Surrogate:
                                               C.c_void_p(h1.data_ptr()), g.ctypes.data_as(C.POINTER(C.c_float)),
                                               C.byref(v)), "mlf_nop_gradient")
         return v.value, g
+
+    def time_conv(self, batch, reps=20):
+        """Average ms of one MFMA 3x3 convolution (forward, weight gradient)."""
+        a, b = C.c_float(), C.c_float()
+        self._check(self.lib.mlf_nop_time_conv(self.h, int(batch), int(reps), C.byref(a), C.byref(b)),
+                    "mlf_nop_time_conv")
+        return a.value, b.value
+
+    def conv_flops(self, batch):
+        """Multiply-add flops of one 3x3 convolution on `batch` samples."""
+        return 2.0 * batch * (self.p.ny // 4) * (self.p.nx // 4) * 9 * self.p.width ** 2
 
     def train_step(self, h0, h1, lr):
         h0, h1 = self._dev(h0), self._dev(h1)

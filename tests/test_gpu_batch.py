@@ -198,3 +198,26 @@ def test_uninitialised_film_is_rejected(mlf):
     with pytest.raises(mlf.MlfError) as ex:
         b.step(1)
     assert ex.value.status == "EINVAL"
+
+
+def test_init_and_read_all_films_at_once(mlf, torch_cuda):
+    """Batch-wide device init / read equal the per-film calls."""
+    torch = torch_cuda
+    rng = np.random.default_rng(21)
+    films = []
+    for j in range(3):
+        gam = list(rng.uniform(0.5e-2, 1.5e-2, size=3))
+        film = inputs.film_params(3, 96, 64, gamma=gam, mu=[1.5e-3] * 3, hstar=0.15,
+                                  spread={(l, 1): inputs.young_spreading(gam[l], 20.0) for l in range(3)})
+        films.append((film, np.stack([(1.0 - 0.2 * i) + 1e-3 * rng.uniform(-1, 1, (64, 96)) for i in range(3)])))
+    hs = torch.from_numpy(np.stack([h for _, h in films])).cuda()
+    a = mlf.Batch([f for f, _ in films], "f32")
+    b = mlf.Batch([f for f, _ in films], "f32")
+    a.init_all(hs)
+    for i in range(len(films)):
+        b.init(i, hs[i].contiguous())
+    a.step(17)
+    b.step(17)
+    ra = a.read_all().cpu().numpy()
+    for i in range(len(films)):
+        assert np.array_equal(ra[i], b.read(i)[0]), i

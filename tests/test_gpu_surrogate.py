@@ -57,13 +57,13 @@ def setup(mlf, torch, C, L=2, B=2, N=3, ny=16, nx=256, seed=0):
     return s, net, vec, h0.astype(np.float64), h1.astype(np.float64), t0, t1
 
 
-@pytest.mark.parametrize("C", [64, 128])
-def test_predict_matches_reference(mlf, torch_cuda, C):
-    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C)
+@pytest.mark.parametrize("C,N", [(64, 3), (128, 3), (64, 4), (64, 1)])
+def test_predict_matches_reference(mlf, torch_cuda, C, N):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C, N=N)
     out = s.predict(t0).cpu().numpy().astype(np.float64)
     d_gpu = (out - h0) / 1e-2
     d_ref, _ = net.forward(vec, h0)
-    d_64, _ = nop.Net(3, C, 2, 1e-2, use_bf16=False).forward(vec, h0)
+    d_64, _ = nop.Net(N, C, 2, 1e-2, use_bf16=False).forward(vec, h0)
     e = rel(d_gpu, d_ref)
     print(f"C={C} increment rel L2 {e:.2e} (vs unrounded FP64 network {rel(d_gpu, d_64):.2e})", flush=True)
     assert e <= 2e-3
@@ -71,13 +71,13 @@ def test_predict_matches_reference(mlf, torch_cuda, C):
     assert np.abs(out.sum(axis=(2, 3)) - h0.sum(axis=(2, 3))).max() <= 1e-6 * h0.sum(axis=(2, 3)).max()
 
 
-@pytest.mark.parametrize("C", [64, 128])
-def test_gradient_matches_reference(mlf, torch_cuda, C):
-    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C, seed=1)
+@pytest.mark.parametrize("C,N", [(64, 3), (128, 3), (64, 4)])
+def test_gradient_matches_reference(mlf, torch_cuda, C, N):
+    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, C, N=N, seed=1)
     loss_g, g_gpu = s.gradient(t0, t1)
     loss_r, g_ref = net.gradient(vec, h0, h1)
     assert abs(loss_g - loss_r) <= 2e-3 * loss_r
-    off, n = nop.layout(3, C, 2)
+    off, n = nop.layout(N, C, 2)
     assert g_gpu.size == n
     worst = 0.0
     for name, (o, sz) in off.items():
@@ -102,8 +102,9 @@ def test_shift_by_whole_patches(mlf, torch_cuda):
     t0s = torch_cuda.roll(t0, (4, 8), (2, 3)).contiguous()
     da = (s.predict(t0).cpu().numpy().astype(np.float64) - h0) / 1e-2
     db = (s.predict(t0s).cpu().numpy().astype(np.float64) - t0s.cpu().numpy()) / 1e-2
-    # the convolutions see the same values; only the per-layer means sum in another order
-    assert rel(np.roll(da, (4, 8), (2, 3)), db) <= 1e-4
+    # the per-layer means sum in another order; their last-bit differences
+    # move some bfloat16 roundings, as in the comparison with the reference
+    assert rel(np.roll(da, (4, 8), (2, 3)), db) <= 2e-3
 
 
 def test_training_reduces_the_loss(mlf, torch_cuda):
@@ -122,3 +123,25 @@ def test_batch_limit(mlf, torch_cuda):
     with pytest.raises(mlf.MlfError) as e:
         s.predict(big)
     assert e.value.status == "EINVAL"
+
+
+def test_pipeline_end_to_end(mlf, torch_cuda):
+    """Solver-generated windows, a few training steps, and a judged run
+    whose bookkeeping is consistent (small and short; the full workload is
+    timed by the benchmark)."""
+    from paper_2409_16659_amd import surrogate as S
+
+    films = S.films(4, seed0=7000)
+    X0, X1 = S.windows(films, [2000, 2100, 2200], window=100)
+    assert X0.shape == (12, 3, 256, 256)
+    m = mlf.Surrogate(3, 256, 256, width=64, blocks=1, batch=8, scale=1e-2)
+    m.set_params(S.init_params(m, seed=0))
+    losses = S.train(m, X0, X1, 20, batch=8, lr=1e-3)
+    assert np.all(np.isfinite(losses)) and m_steps(m) == 20
+    r = S.judged_run(m, films[:2], 2000, 6, 3, 1e-3)
+    assert r["accepted_windows"] + r["rejected_windows"] == 6
+    assert len(r["judge_errors"]) == 2 and r["solver_s"] > 0 and r["total_s"] > 0
+
+
+def m_steps(m):
+    return int(m.lib.mlf_nop_steps_done(m.h))

@@ -86,3 +86,28 @@ def test_adam_one_scalar():
     # first step: m_hat = g, v_hat = g^2, update = lr * g / (|g| + eps)
     assert abs(v[0] - (1.0 - 0.1 * 0.5 / (0.5 + 1e-8))) < 1e-15
     assert abs(m[0] - 0.05) < 1e-15 and abs(s[0] - 0.00025) < 1e-15
+
+
+def test_package_initial_parameters_follow_the_abi_layout():
+    """The package's seeded initialisation (used by the benchmark) has the
+    reference's layout: blocks start where the reference puts them."""
+    import math
+
+    from paper_2409_16659_amd import surrogate as S
+
+    class Fake:
+        class p:
+            n_layers, width, blocks = 3, 64, 2
+        param_count = nop.layout(3, 64, 2)[1]
+
+    vec = S.init_params(Fake, seed=1)
+    off, n = nop.layout(3, 64, 2)
+    assert vec.size == n
+    for name, (o, s) in off.items():
+        block = vec[o:o + s]
+        if name.startswith("b"):
+            assert not block.any(), name
+        else:
+            expect = {"We": 1 / math.sqrt(48), "Wd": 0.1 / math.sqrt(64)}.get(
+                name, math.sqrt(2 / (9 * 64)) if name.startswith("W1") else 0.1 * math.sqrt(1 / (9 * 64)))
+            assert abs(block.std() / expect - 1) < 0.1, name
