@@ -86,7 +86,7 @@ typedef struct mlf_params {
   int32_t exp_b;
   double gamma[MLF_MAX_LAYERS];  /* gamma_{i,i+1}, i = 1..N (gamma_N: layer N / gas) */
   double mu[MLF_MAX_LAYERS];     /* viscosities mu_1..mu_N > 0                   */
-  double slip[MLF_MAX_LAYERS];   /* slip lengths beta_i; must be 0 (no slip)     */
+  double slip[MLF_MAX_LAYERS];   /* slip lengths beta_i >= 0 (0: no slip)        */
   /* spreading coefficients S_lk packed l-major: l = 0..N-1, k = 1..N-l, i.e.
    * S_01..S_0N, S_11..S_1(N-1), ..., S_(N-1)1 (Eq. spreading_parameters). */
   double spread[MLF_MAX_PAIRS];
@@ -113,8 +113,10 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
  * are NULL).  h, ux, uy: host FP64 [N][ny][nx].  The per-layer reference
  * heights h_ref_i become the means of h_i.  Checks h > 0 and finite
  * (ENONPOSITIVE / ENONFINITE) and, unless allow_unstable, that the explicit
- * friction is stable: every eigenvalue of -K (friction = K q) with each layer
- * at h* or at h_ref must stay below 2 (else EUNSTABLE).  Resets the step
+ * friction is stable: with each layer at h* or at h_ref the spectral radius
+ * of I + K (friction = K q; the per-step amplification of the fluxes) must
+ * stay below 1 (without slip: every eigenvalue of -K below 2), else
+ * EUNSTABLE.  Resets the step
  * counter.  Synchronises. */
 mlf_status mlf_init(mlf_handle* h, const double* hgt, const double* ux, const double* uy);
 
@@ -260,9 +262,16 @@ mlf_status mlf_spreading_from_tensions(int32_t n_layers, const double* g, double
 
 /* Friction matrix K (row-major N x N, friction = K q) of one node with
  * thicknesses h[N] and viscosities mu[N], from the boundary conditions of
- * Sec. II.A.2 (no slip), and the largest eigenvalue of -K. */
+ * Sec. II.A.2 (no slip), and the largest |eigenvalue| of -K. */
 mlf_status mlf_friction_matrix(int32_t n_layers, const double* h, const double* mu,
                                double* K, double* max_rate);
+
+/* As mlf_friction_matrix with slip lengths slip[N] >= 0: each layer's
+ * profile extrapolated slip_i below its base meets the velocity of the layer
+ * beneath (0 at the substrate), the boundary condition of Eq. (no_slip)
+ * with a slip length. */
+mlf_status mlf_friction_matrix_slip(int32_t n_layers, const double* h, const double* mu, const double* slip,
+                                    double* K, double* max_rate);
 
 /* Library version string. */
 const char* mlf_version(void);

@@ -106,54 +106,92 @@ mlf_status validate(const mlf_params* p, std::string* why) {
     return MLF_EUNSUPPORTED;
   }
   for (int i = 0; i < p->n_layers; ++i)
-    if (p->slip[i] != 0.0) {
-      if (why) *why = "slip lengths other than 0 are not supported";
-      return MLF_EUNSUPPORTED;
-    }
+    if (!(p->slip[i] >= 0.0) || !std::isfinite(p->slip[i])) return bad("slip lengths must be finite and >= 0");
   return MLF_OK;
 }
 
 // Friction matrix K (friction = K q) of one node from the interface-velocity
-// form of the boundary conditions (no slip): column j is the response to a
-// unit flux in layer j.
-void friction_matrix(int n, const double* h, const double* mu, double* K) {
-  double g[kMaxLayers + 1];
-  for (int i = 0; i < n; ++i) g[i] = mu[i] / h[i];
-  g[n] = 0.0;
+// form of the boundary conditions, column j being the response to a unit
+// flux in layer j.  Layer i's Poiseuille profile is fixed by its bottom
+// velocity w_i, top velocity v_i and mean U_i; with slip length beta_i the
+// profile extrapolated to beta_i below the layer meets v_{i-1} (v_{-1} = 0),
+// which with rho = beta_i / h_i gives
+//   w_i = [v_{i-1} - rho (3 rho + 2) v_i + 6 rho (rho + 1) U_i] / ((1 + rho)(1 + 3 rho)),
+// and stress continuity g_i (4 v_i + 2 w_i - 6 U_i) + g_{i+1} (4 w_{i+1} +
+// 2 v_{i+1} - 6 U_{i+1}) = 0 (g = mu / h, g_N = 0 at the gas) is tridiagonal
+// in v.  friction_i = 6 g_i (w_i + v_i - 2 U_i).
+void friction_matrix(int n, const double* h, const double* mu, const double* slip, double* K) {
+  double g[kMaxLayers + 1], A[kMaxLayers + 1], B[kMaxLayers + 1], E[kMaxLayers + 1];
+  for (int i = 0; i < n; ++i) {
+    g[i] = mu[i] / h[i];
+    const double r = slip ? slip[i] / h[i] : 0.0, d = (1.0 + r) * (1.0 + 3.0 * r);
+    A[i] = 1.0 / d;
+    B[i] = -r * (3.0 * r + 2.0) / d;
+    E[i] = 6.0 * r * (r + 1.0) / d;
+  }
+  g[n] = 0.0, A[n] = B[n] = E[n] = 0.0;
   for (int j = 0; j < n; ++j) {
-    double U[kMaxLayers] = {0, 0, 0, 0}, v[kMaxLayers], c[kMaxLayers];
+    double U[kMaxLayers + 1] = {0, 0, 0, 0, 0}, v[kMaxLayers], c[kMaxLayers];
     U[j] = 1.0 / h[j];
     for (int i = 0; i < n; ++i) {
-      double diag = 2.0 * (g[i] + g[i + 1]);
-      double rhs = 3.0 * (g[i] * U[i] + (i + 1 < n ? g[i + 1] * U[i + 1] : 0.0));
-      double m = (i == 0) ? diag : diag - g[i] * c[i - 1];
-      c[i] = g[i + 1] / m;
-      v[i] = (i == 0 ? rhs : rhs - g[i] * v[i - 1]) / m;
+      const double sub = 2.0 * g[i] * A[i];
+      const double diag = g[i] * (4.0 + 2.0 * B[i]) + 4.0 * g[i + 1] * A[i + 1];
+      const double sup = g[i + 1] * (4.0 * B[i + 1] + 2.0);
+      const double rhs = g[i] * (6.0 - 2.0 * E[i]) * U[i] + g[i + 1] * (6.0 - 4.0 * E[i + 1]) * U[i + 1];
+      const double m = (i == 0) ? diag : diag - sub * c[i - 1];
+      c[i] = sup / m;
+      v[i] = (i == 0 ? rhs : rhs - sub * v[i - 1]) / m;
     }
     for (int i = n - 2; i >= 0; --i) v[i] -= c[i] * v[i + 1];
-    for (int i = 0; i < n; ++i) K[i * n + j] = 6.0 * g[i] * ((i > 0 ? v[i - 1] : 0.0) + v[i] - 2.0 * U[i]);
+    for (int i = 0; i < n; ++i) {
+      const double w = A[i] * (i > 0 ? v[i - 1] : 0.0) + B[i] * v[i] + E[i] * U[i];
+      K[i * n + j] = 6.0 * g[i] * (w + v[i] - 2.0 * U[i]);
+    }
   }
 }
 
-// Largest eigenvalue of -K.  The eigenvalues are real and positive (P K^-1 T
-// is symmetric), so power iteration converges to it.
-double max_rate(int n, const double* K) {
-  double v[kMaxLayers] = {1, 1, 1, 1}, lam = 0.0;
-  for (int it = 0; it < 2000; ++it) {
-    double w[kMaxLayers] = {0, 0, 0, 0}, nrm = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) w[i] -= K[i * n + j] * v[j];
-    for (int i = 0; i < n; ++i) nrm = std::max(nrm, std::fabs(w[i]));
-    if (nrm == 0.0) return 0.0;
-    double num = 0.0, den = 0.0;
-    for (int i = 0; i < n; ++i) {
-      num += w[i] * v[i];
-      den += v[i] * v[i];
-    }
-    lam = num / den;
-    for (int i = 0; i < n; ++i) v[i] = w[i] / nrm;
+// Spectral radius of an n x n matrix M (n <= 4) by repeated squaring with
+// renormalisation: rho(M) = lim |M^(2^k)|^(1/2^k), tracked in logarithms;
+// valid for complex eigenvalue pairs too.
+double spectral_radius(int n, const double* M) {
+  double A[kMaxLayers * kMaxLayers], Bm[kMaxLayers * kMaxLayers];
+  double s = 0.0;
+  for (int i = 0; i < n * n; ++i) s = std::max(s, std::fabs(M[i]));
+  if (s == 0.0 || !std::isfinite(s)) return s;
+  for (int i = 0; i < n * n; ++i) A[i] = M[i] / s;
+  double L = std::log(s);
+  const int kSquarings = 40;
+  for (int it = 1; it <= kSquarings; ++it) {
+    double t = 0.0;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        double v = 0.0;
+        for (int k = 0; k < n; ++k) v += A[r * n + k] * A[k * n + c];
+        Bm[r * n + c] = v;
+        t = std::max(t, std::fabs(v));
+      }
+    if (t == 0.0) return 0.0;  // nilpotent
+    for (int i = 0; i < n * n; ++i) A[i] = Bm[i] / t;
+    L = 2.0 * L + std::log(t);
   }
-  return lam;
+  return std::exp(L / std::ldexp(1.0, kSquarings));
+}
+
+// Largest |eigenvalue| of -K (the largest friction rate; real and positive
+// without slip).
+double max_rate(int n, const double* K) {
+  double M[kMaxLayers * kMaxLayers];
+  for (int i = 0; i < n * n; ++i) M[i] = -K[i];
+  return spectral_radius(n, M);
+}
+
+// Spectral radius of I + K: the per-step amplification of the fluxes by
+// the explicit friction (q <- q + K q for every tau).
+double friction_amplification(int n, const double* K) {
+  double M[kMaxLayers * kMaxLayers];
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) M[r * n + c] = K[r * n + c] + (r == c ? 1.0 : 0.0);
+  return spectral_radius(n, M);
 }
 
 uint64_t fnv1a(const void* data, size_t n, uint64_t hsh = 1469598103934665603ull) {
@@ -516,6 +554,10 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
     }
   for (int kk = 1; kk <= kMaxLayers; ++kk) k.khs[kk - 1] = C(kk * p.hstar);
   k.omega = C(1.0 / p.tau);
+  for (int i = 0; i < n; ++i) {
+    k.slip[i] = C(p.slip[i]);
+    if (p.slip[i] != 0.0) k.slip_on = 1;
+  }
   for (int i = 0; i < kMaxLayers; ++i) {
     k.scale[i] = C(h->scale[i]);
     k.iscale[i] = C(1.0 / h->scale[i]);
@@ -675,18 +717,22 @@ mlf_status check_guard(mlf_handle* h) {
 mlf_status check_stability(mlf_handle* h) {
   const mlf_params& p = h->p;
   if (p.allow_unstable) return MLF_OK;
-  // explicit friction: every eigenvalue of -K must stay below 2 with each
-  // layer at h* or at its reference thickness
-  double worst = 0.0;
+  // explicit friction: the fluxes' per-step amplification I + K must have
+  // spectral radius below 1 with each layer at h* or at its reference
+  // thickness (without slip: every eigenvalue of -K below 2)
+  double worst = 0.0, rate = 0.0;
   for (int mask = 0; mask < (1 << p.n_layers); ++mask) {
     double hh[kMaxLayers], K[kMaxLayers * kMaxLayers];
     for (int i = 0; i < p.n_layers; ++i) hh[i] = (mask >> i & 1) ? p.hstar : h->hbar[i];
-    friction_matrix(p.n_layers, hh, p.mu, K);
-    worst = std::max(worst, max_rate(p.n_layers, K));
+    friction_matrix(p.n_layers, hh, p.mu, p.slip, K);
+    worst = std::max(worst, friction_amplification(p.n_layers, K));
+    rate = std::max(rate, max_rate(p.n_layers, K));
   }
-  if (!(worst < 2.0)) {
-    char buf[160];
-    std::snprintf(buf, sizeof buf, "explicit friction unstable: largest friction rate %.4g >= 2", worst);
+  if (!(worst < 1.0)) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "explicit friction unstable: flux amplification %.4g >= 1 (largest friction rate %.4g)", worst,
+                  rate);
     return fail(h, MLF_EUNSTABLE, buf);
   }
   return MLF_OK;
@@ -1176,7 +1222,19 @@ mlf_status mlf_friction_matrix(int32_t n, const double* hh, const double* mu, do
   for (int i = 0; i < n; ++i)
     if (!(hh[i] > 0.0) || !(mu[i] > 0.0)) return MLF_EINVAL;
   double k[kMaxLayers * kMaxLayers];
-  friction_matrix(n, hh, mu, k);
+  friction_matrix(n, hh, mu, nullptr, k);
+  if (K) std::memcpy(K, k, sizeof(double) * n * n);
+  if (rate) *rate = max_rate(n, k);
+  return MLF_OK;
+}
+
+mlf_status mlf_friction_matrix_slip(int32_t n, const double* hh, const double* mu, const double* slip, double* K,
+                                    double* rate) {
+  if (n < 1 || n > MLF_MAX_LAYERS || !hh || !mu || !slip) return MLF_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(hh[i] > 0.0) || !(mu[i] > 0.0) || !(slip[i] >= 0.0) || !std::isfinite(slip[i])) return MLF_EINVAL;
+  double k[kMaxLayers * kMaxLayers];
+  friction_matrix(n, hh, mu, slip, k);
   if (K) std::memcpy(K, k, sizeof(double) * n * n);
   if (rate) *rate = max_rate(n, k);
   return MLF_OK;

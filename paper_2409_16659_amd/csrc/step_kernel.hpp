@@ -56,6 +56,8 @@
 //      g_i v_{i-1} + 2 (g_i + g_{i+1}) v_i + g_{i+1} v_{i+1}
 //          = 3 (g_i U_i + g_{i+1} U_{i+1}),   g_i = mu_i / h_i, g_{N+1} = 0,
 //    and friction_i = 2 mu_i h_i a_i = 6 g_i (v_{i-1} + v_i - 2 U_i).
+//    With slip lengths the profile's bottom velocity w_i replaces v_{i-1}
+//    (see the slip branch below); the system stays tridiagonal.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,6 +93,8 @@ struct StepConsts {
   C scale[kMaxLayers], iscale[kMaxLayers];  // storage scale per layer (16-bit formats)
   int ea, eb;                        // runtime exponents (generic path)
   unsigned pairs;                    // bit l*4 + k-1 set: S_lk != 0
+  int slip_on;                       // any slip length != 0
+  C slip[kMaxLayers];                // slip lengths beta_i
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
 };
 
@@ -524,39 +528,92 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
       if (st_ok) {
         const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
         const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
-        C h[NL], ux[NL], uy[NL], g[NL + 1];
+        C h[NL], ux[NL], uy[NL], g[NL + 1], rh[NL];
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
           h[i] = kc.hbar[i] + dh2[i];
-          const C rh = rcp(h[i]);
-          ux[i] = qx2[i] * rh;
-          uy[i] = qy2[i] * rh;
-          g[i] = kc.mu[i] * rh;
+          rh[i] = rcp(h[i]);
+          ux[i] = qx2[i] * rh[i];
+          uy[i] = qy2[i] * rh[i];
+          g[i] = kc.mu[i] * rh[i];
         }
         g[NL] = C(0);
-        // Thomas elimination for the interface velocities (x and y share pivots)
-        C cpr[NL], vx[NL], vy[NL];
+        // Thomas elimination for the interface velocities v (x and y share
+        // pivots) and the bottom velocities w of the layers' profiles
+        C cpr[NL], vx[NL], vy[NL], wx[NL], wy[NL];
+        if (!kc.slip_on) {
+          // no slip: w_i = v_{i-1}
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-          const C diag = C(2) * (g[i] + g[i + 1]);
-          const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
-          const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
-          if (i == 0) {
-            const C im = rcp(diag);
-            cpr[i] = g[i + 1] * im;
-            vx[i] = rx * im;
-            vy[i] = ry * im;
-          } else {
-            const C im = rcp(diag - g[i] * cpr[i - 1]);
-            cpr[i] = g[i + 1] * im;
-            vx[i] = (rx - g[i] * vx[i - 1]) * im;
-            vy[i] = (ry - g[i] * vy[i - 1]) * im;
+          for (int i = 0; i < NL; ++i) {
+            const C diag = C(2) * (g[i] + g[i + 1]);
+            const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
+            const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
+            if (i == 0) {
+              const C im = rcp(diag);
+              cpr[i] = g[i + 1] * im;
+              vx[i] = rx * im;
+              vy[i] = ry * im;
+            } else {
+              const C im = rcp(diag - g[i] * cpr[i - 1]);
+              cpr[i] = g[i + 1] * im;
+              vx[i] = (rx - g[i] * vx[i - 1]) * im;
+              vy[i] = (ry - g[i] * vy[i - 1]) * im;
+            }
           }
-        }
 #pragma unroll
-        for (int i = NL - 2; i >= 0; --i) {
-          vx[i] -= cpr[i] * vx[i + 1];
-          vy[i] -= cpr[i] * vy[i + 1];
+          for (int i = NL - 2; i >= 0; --i) {
+            vx[i] -= cpr[i] * vx[i + 1];
+            vy[i] -= cpr[i] * vy[i + 1];
+          }
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            wx[i] = i > 0 ? vx[i - 1] : C(0);
+            wy[i] = i > 0 ? vy[i - 1] : C(0);
+          }
+        } else {
+          // slip lengths beta_i, rho = beta_i / h_i:
+          //   w_i = A_i v_{i-1} + B_i v_i + E_i U_i,  A = 1 / ((1 + rho)(1 + 3 rho)),
+          //   B = -rho (3 rho + 2) A,  E = 6 rho (rho + 1) A;
+          // stress continuity g_i (4 v_i + 2 w_i - 6 U_i) + g_{i+1} (4 w_{i+1} + 2 v_{i+1} - 6 U_{i+1}) = 0
+          C sa[NL + 1], sb[NL + 1], se[NL + 1];
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            const C r = kc.slip[i] * rh[i];
+            sa[i] = rcp((C(1) + r) * (C(1) + C(3) * r));
+            sb[i] = -r * (C(3) * r + C(2)) * sa[i];
+            se[i] = C(6) * r * (r + C(1)) * sa[i];
+          }
+          sa[NL] = sb[NL] = se[NL] = C(0);
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            const C sub = C(2) * g[i] * sa[i];
+            const C diag = g[i] * (C(4) + C(2) * sb[i]) + C(4) * g[i + 1] * sa[i + 1];
+            const C sup = g[i + 1] * (C(4) * sb[i + 1] + C(2));
+            const C k0 = g[i] * (C(6) - C(2) * se[i]), k1 = g[i + 1] * (C(6) - C(4) * se[i + 1]);
+            const C rx = k0 * ux[i] + (i + 1 < NL ? k1 * ux[i + 1] : C(0));
+            const C ry = k0 * uy[i] + (i + 1 < NL ? k1 * uy[i + 1] : C(0));
+            if (i == 0) {
+              const C im = rcp(diag);
+              cpr[i] = sup * im;
+              vx[i] = rx * im;
+              vy[i] = ry * im;
+            } else {
+              const C im = rcp(diag - sub * cpr[i - 1]);
+              cpr[i] = sup * im;
+              vx[i] = (rx - sub * vx[i - 1]) * im;
+              vy[i] = (ry - sub * vy[i - 1]) * im;
+            }
+          }
+#pragma unroll
+          for (int i = NL - 2; i >= 0; --i) {
+            vx[i] -= cpr[i] * vx[i + 1];
+            vy[i] -= cpr[i] * vy[i + 1];
+          }
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            wx[i] = sa[i] * (i > 0 ? vx[i - 1] : C(0)) + sb[i] * vx[i] + se[i] * ux[i];
+            wy[i] = sa[i] * (i > 0 ? vy[i - 1] : C(0)) + sb[i] * vy[i] + se[i] * uy[i];
+          }
         }
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
@@ -568,9 +625,8 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
           const C nw = n[-1], nn = n[0], ne = n[1];
           const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
           const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
-          const C vlo_x = i > 0 ? vx[i - 1] : C(0), vlo_y = i > 0 ? vy[i - 1] : C(0);
-          const C frx = C(6) * g[i] * ((vlo_x + vx[i]) - C(2) * ux[i]);
-          const C fry = C(6) * g[i] * ((vlo_y + vy[i]) - C(2) * uy[i]);
+          const C frx = C(6) * g[i] * ((wx[i] + vx[i]) - C(2) * ux[i]);
+          const C fry = C(6) * g[i] * ((wy[i] + vy[i]) - C(2) * uy[i]);
           const C Fx = -h[i] * gpx + frx;
           const C Fy = -h[i] * gpy + fry;
           const C qx = qx2[i], qy = qy2[i];

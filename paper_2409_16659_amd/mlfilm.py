@@ -131,6 +131,7 @@ def load_library():
         "mlf_nop_destroy": (st, [H]),
         "mlf_spreading_from_tensions": (st, [C.c_int32, _D, _D]),
         "mlf_friction_matrix": (st, [C.c_int32, _D, _D, _D, _D]),
+        "mlf_friction_matrix_slip": (st, [C.c_int32, _D, _D, _D, _D, _D]),
         "mlf_version": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -210,13 +211,18 @@ def spreading_from_tensions(n: int, g) -> dict:
     return res
 
 
-def friction_matrix(h, mu):
+def friction_matrix(h, mu, slip=None):
+    """Friction matrix K (friction = K q) of one node and the largest
+    eigenvalue of -K; slip lengths optional."""
     lib = load_library()
     h, mu = _f64(h), _f64(mu)
     n = h.shape[0]
     K = np.zeros((n, n))
     rate = C.c_double()
-    rc = lib.mlf_friction_matrix(n, _dp(h), _dp(mu), _dp(K), C.byref(rate))
+    if slip is None:
+        rc = lib.mlf_friction_matrix(n, _dp(h), _dp(mu), _dp(K), C.byref(rate))
+    else:
+        rc = lib.mlf_friction_matrix_slip(n, _dp(h), _dp(mu), _dp(_f64(slip)), _dp(K), C.byref(rate))
     if rc:
         raise MlfError(rc, "mlf_friction_matrix")
     return K, rate.value

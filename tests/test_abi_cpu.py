@@ -111,9 +111,11 @@ def test_query_sizes_and_validation():
         assert e.value.status == "EINVAL"
     q = mlfilm.make_params(film, "f32")
     q.slip[0] = 0.1
+    mlfilm.query_sizes(q)  # slip lengths >= 0 are supported
+    q.slip[0] = -0.1
     with pytest.raises(mlfilm.MlfError) as e:
         mlfilm.query_sizes(q)
-    assert e.value.status == "EUNSUPPORTED"
+    assert e.value.status == "EINVAL"
 
 
 def _fake_handle(film, precision="f64", allow_unstable=False):
@@ -193,3 +195,31 @@ def test_surrogate_sizes_and_validation():
         assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -1, field
     q = mlfilm.NopParams(3, 256, 256, 96, 3, 64, 1e-2)
     assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -2
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_friction_matrix_with_slip_matches_oracle(oracle_mod, n):
+    """Interface-velocity form with slip lengths against the oracle's
+    3N x 3N elimination of the same boundary conditions."""
+    rng = np.random.default_rng(40 + n)
+    for _ in range(20):
+        h = rng.uniform(0.05, 2.0, n)
+        mu = rng.uniform(1e-3, 1e-1, n)
+        slip = rng.uniform(0.0, 1.0, n) * (rng.uniform(size=n) < 0.7)
+        K, rate = mlfilm.friction_matrix(h, mu, slip)
+        Ko = np.stack([oracle_mod.friction(h, mu, np.eye(n)[j], slip) for j in range(n)], axis=1)
+        assert np.abs(K - Ko).max() <= 1e-12 * np.abs(Ko).max()
+        # with slip the spectrum of -K may hold complex pairs: the rate is the largest modulus
+        assert abs(rate - np.abs(np.linalg.eigvals(-Ko)).max()) <= 1e-9 * rate
+        # zero slip is the no-slip matrix
+        K0, _ = mlfilm.friction_matrix(h, mu, np.zeros(n))
+        assert np.array_equal(K0, mlfilm.friction_matrix(h, mu)[0])
+
+
+def test_single_layer_slip_closed_form():
+    """One layer: the profile u(s) = a s^2 + b s + c with u(-beta) = 0,
+    u'(h) = 0 and mean U gives friction 2 mu h a = -2 mu h U / (2h^2/3 + 2h beta + beta^2)."""
+    for h, mu, beta in [(1.0, 0.1, 0.0), (0.3, 0.02, 0.1), (2.0, 1.0, 5.0)]:
+        K, _ = mlfilm.friction_matrix([h], [mu], [beta])
+        want = -2 * mu * h / (2 * h * h / 3 + 2 * h * beta + beta * beta) / h  # per unit flux q = h U
+        assert abs(K[0, 0] - want) <= 1e-13 * abs(want)

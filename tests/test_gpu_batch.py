@@ -84,6 +84,8 @@ def test_batch_matches_single_films(mlf, prec, persistent):
 
 def test_batch_fp64_against_oracle(mlf, oracle_mod):
     films = scan(3, seed=7, side_max=96)
+    # one film with slip lengths next to no-slip films
+    films[1] = (dict(films[1][0], slip=[0.5] * films[1][0]["n_layers"]), films[1][1])
     b = mlf.Batch([f for f, _ in films], "f64")
     b.set_launch(192, 5, 1)
     for i, (_, h0) in enumerate(films):

@@ -146,6 +146,29 @@ def test_fp64_initial_velocity(mlf, oracle_mod):
     check(g, o, 1e-12, 1e-10)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_fp64_slip_lengths(mlf, oracle_mod, n):
+    """Slip lengths beta_i > 0 on some layers (zero on others): the
+    generalised interface-velocity system against the oracle's profile
+    coefficients."""
+    rng = np.random.default_rng(40 + n)
+    film = small_film(n, 70, 33, seed=20 + n)
+    slip = list(rng.uniform(0.05, 1.5, size=n) * (np.arange(n) % 2 == 0))
+    slip[-1] = 0.4   # at least one slipping layer on every film
+    film["slip"] = slip
+    h0 = noisy(n, 70, 33, seed=60 + n)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 300, "f64", launch=(64, 8))
+    check(g, o, 1e-12, 1e-10)
+
+
+def test_fp32_slip_lengths(mlf, oracle_mod):
+    film = small_film(3, 96, 40, seed=30)
+    film["slip"] = [0.3, 0.0, 1.0]
+    h0 = noisy(3, 96, 40, seed=31)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 200, "f32")
+    check(g, o, 1e-5, 1e-4)
+
+
 # ------------------------------------------------------------------ FP32 --
 def test_fp32_three_layer_crop(mlf, oracle_mod):
     """The 3-layer workload's parameters on a 256x200 crop, 2000 steps."""
