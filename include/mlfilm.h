@@ -140,6 +140,24 @@ mlf_status mlf_read_device(mlf_handle* h, double* hgt, double* ux, double* uy);
  * host array [N].  Synchronises. */
 mlf_status mlf_layer_mass(mlf_handle* h, double* mass);
 
+/* Per-layer minimum height min_x h_i in FP64, host array [N]; the heights
+ * are bit-identical to those mlf_read returns (same summation order).
+ * Synchronises.  A layer has ruptured once it shows its first hole, i.e.
+ * its minimum drops to the precursor scale (Sec. IV.E). */
+mlf_status mlf_layer_min(mlf_handle* h, double* hmin);
+
+/* Rupture detection.  Steps in chunks of check_every (>= 1) steps, up to
+ * max_steps (>= 0) in total, taking the per-layer minimum after each
+ * chunk, and stops after the first chunk at whose end some layer i has
+ * min_x h_i <= threshold[i] (host [N]).  *steps_taken: steps run by this
+ * call; *layer: the first layer at or below its threshold, -1 if none
+ * was.  The time of the event is resolved to check_every steps.  Guard
+ * trips return as from mlf_step (with *steps_taken counting the failed
+ * chunk).  Synchronises after every chunk.  EINVAL for null pointers,
+ * max_steps < 0 or check_every < 1. */
+mlf_status mlf_step_until(mlf_handle* h, int64_t max_steps, int32_t check_every, const double* threshold,
+                          int64_t* steps_taken, int32_t* layer);
+
 /* Absolute populations f_ki in FP64, host [N][9][ny][nx] (read) or set
  * from such an array (write; keeps h_ref).  Synchronise. */
 mlf_status mlf_read_populations(mlf_handle* h, double* f);
@@ -232,6 +250,20 @@ mlf_status mlf_batch_read_device(mlf_batch* b, int32_t film, double* hgt, double
  * device pointers); asynchronous on the stream. */
 mlf_status mlf_batch_read_device_all(mlf_batch* b, double* const* outs);
 mlf_status mlf_batch_layer_mass(mlf_batch* b, int32_t film, double* mass);
+/* Per-layer minimum height of one film, as mlf_layer_min (synchronises). */
+mlf_status mlf_batch_layer_min(mlf_batch* b, int32_t film, double* hmin);
+/* Minima of all films from one pass over the batch: host
+ * [n][MLF_MAX_LAYERS], +inf past a film's layer count.  Synchronises. */
+mlf_status mlf_batch_layer_min_all(mlf_batch* b, double* hmin);
+/* Rupture times of all films: the batch steps in chunks of check_every
+ * (>= 1) until every film has some layer i with min_x h_i <=
+ * threshold[f][i] (host [n][MLF_MAX_LAYERS]) or max_steps have run.
+ * t_hit[f] (host [n]): mlf_batch_steps_done at the end of the chunk in
+ * which film f first did, -1 if it never did; layer_hit[f]: that layer
+ * (-1); *steps_taken: steps run by this call.  Films that have got there
+ * keep stepping with the rest.  Synchronises after every chunk. */
+mlf_status mlf_batch_step_until(mlf_batch* b, int64_t max_steps, int32_t check_every, const double* threshold,
+                                int64_t* t_hit, int32_t* layer_hit, int64_t* steps_taken);
 
 /* Launch shape shared by all films: block_w in {64, 128, 192, 256}, seg_h
  * >= 1 rows (clamped to each film's ny), persistent != 0: as many

@@ -292,6 +292,21 @@ __global__ void init_kernel(PopView<R, S> f, const double* __restrict__ hs, cons
   }
 }
 
+// Height and flux of layer i at node x of the row starting at `row`: the
+// moving planes keep node x's population at column x - c_kx.  One fixed
+// summation order, so that read-back and the minimum see the same heights.
+template <typename R, typename S>
+__device__ inline void node_moments(const PopView<R, S>& f, int i, long long row, int x, int nx, const Layers& L,
+                                    double& h, double& qx, double& qy) {
+  const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+  double v[9];
+  for (int k = 0; k < 9; ++k) v[k] = f.ld(i, k, row + mlf::wrap(x - cx[k], nx), L);
+  const double dh = v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7] + v[8];
+  qx = (v[1] + v[2] + v[8]) - (v[4] + v[5] + v[6]);
+  qy = (v[2] + v[3] + v[4]) - (v[6] + v[7] + v[8]);
+  h = L.hb[i] + dh;
+}
+
 // h = hbar + sum_k f_k, U = q / h in FP64 for rows [ya, yb).
 template <typename R, typename S>
 __global__ void read_kernel(PopView<R, S> f, double* __restrict__ ho, double* __restrict__ uxo,
@@ -303,14 +318,8 @@ __global__ void read_kernel(PopView<R, S> f, double* __restrict__ ho, double* __
     const int i = (int)(t / n);
     const long long rem = t % n;
     const int y = ya + (int)(rem / nx), x = (int)(rem % nx);
-    const long long row = (long long)y * pitch;
-    const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
-    double v[9];
-    for (int k = 0; k < 9; ++k) v[k] = f.ld(i, k, row + mlf::wrap(x - cx[k], nx), L);
-    const double dh = v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7] + v[8];
-    const double qx = (v[1] + v[2] + v[8]) - (v[4] + v[5] + v[6]);
-    const double qy = (v[2] + v[3] + v[4]) - (v[6] + v[7] + v[8]);
-    const double h = L.hb[i] + dh;
+    double h, qx, qy;
+    node_moments(f, i, (long long)y * pitch, x, nx, L, h, qx, qy);
     const long long di = i * lstride + (long long)(y - yoff) * nx + x;
     if (ho) ho[di] = h;
     if (uxo) uxo[di] = qx / h;
@@ -378,6 +387,80 @@ __global__ void finish_partials(const double* __restrict__ part, double* __restr
     for (int b = 0; b < nblocks; ++b) s += part[b * kMaxLayers + i];
     out[i] = s;
   }
+}
+
+__device__ inline double dmin(double a, double b) { return b < a ? b : a; }
+
+// Minimum height per layer over the nodes t = first, first + stride, ...
+// of one film, reduced over the workgroup; lane 0 of the result holds it.
+template <typename R, typename S>
+__device__ void block_min(const PopView<R, S>& f, int nx, int ny, int pitch, int nl, const Layers& L,
+                          long long first, long long stride, double* __restrict__ out) {
+  __shared__ double red[256 / 64][kMaxLayers];
+  const double inf = __builtin_huge_val();
+  double acc[kMaxLayers] = {inf, inf, inf, inf};
+  const long long n = (long long)nx * ny;
+  for (long long t = first; t < n; t += stride) {
+    const int y = (int)(t / nx), x = (int)(t % nx);
+    for (int i = 0; i < nl; ++i) {
+      double h, qx, qy;
+      node_moments(f, i, (long long)y * pitch, x, nx, L, h, qx, qy);
+      acc[i] = dmin(acc[i], h);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = 0; i < nl; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v = dmin(v, __shfl_down(v, off, 64));
+    if (lane == 0) red[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxLayers) {  // +inf past the film's layers
+    double v = inf;
+    if ((int)threadIdx.x < nl)
+      for (int j = 0; j < (int)(blockDim.x >> 6); ++j) v = dmin(v, red[j][threadIdx.x]);
+    out[threadIdx.x] = v;
+  }
+}
+
+// Block minima of the heights per layer: partials[blockIdx.x][i].
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) min_partials(PopView<R, S> f, double* __restrict__ part, int nx, int ny,
+                                                    int pitch, int nl, Layers L) {
+  block_min(f, nx, ny, pitch, nl, L, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+            (long long)gridDim.x * blockDim.x, part + blockIdx.x * kMaxLayers);
+}
+
+// Geometry and reference heights of one film of a batch for the minimum.
+struct MinFilm {
+  long long offset;  // bytes into the population buffer
+  long long plane;   // nodes per plane (ny * pitch)
+  int nx, ny, pitch, nl;
+  Layers L;
+};
+
+constexpr int kMinBlocksPerFilm = 8;
+
+// Minima of every film of a batch: workgroup (x, film) covers nodes
+// x, x + 8 * 256, ... of that film; partials[film][x][i].
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) batch_min_partials(const MinFilm* __restrict__ films,
+                                                          unsigned char* __restrict__ buf,
+                                                          double* __restrict__ part) {
+  const MinFilm m = films[blockIdx.y];
+  const PopView<R, S> f{buf + m.offset, m.plane, m.nl};
+  block_min(f, m.nx, m.ny, m.pitch, m.nl, m.L, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+            (long long)gridDim.x * blockDim.x, part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kMaxLayers);
+}
+
+// out[g][i] = min over nblocks partials of group g (one thread per group and layer).
+__global__ void finish_min(const double* __restrict__ part, double* __restrict__ out, int ngroups, int nblocks) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ngroups * kMaxLayers) return;
+  const int g = t / kMaxLayers, i = t % kMaxLayers;
+  double v = __builtin_huge_val();
+  for (int b = 0; b < nblocks; ++b) v = dmin(v, part[((size_t)g * nblocks + b) * kMaxLayers + i]);
+  out[t] = v;
 }
 
 }  // namespace
@@ -654,7 +737,7 @@ int step_occupancy(const mlf_handle* h) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
     using C = std::conditional_t<std::is_same_v<S, double>, double, float>;
-    launch_sc<R, S, C>(h, nullptr, nullptr, &occ);
+    (void)launch_sc<R, S, C>(h, nullptr, nullptr, &occ);  // occupancy query; 0 on error
   });
   return occ;
 }
@@ -896,8 +979,8 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
       bh = c.second;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   h->block_w = (st == MLF_OK) ? bw : keep_w;
   h->seg_h = (st == MLF_OK) ? bh : keep_h;
   if (st != MLF_OK) return st;
@@ -1106,6 +1189,50 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
   return MLF_OK;
 }
 
+mlf_status mlf_layer_min(mlf_handle* h, double* hmin) {
+  if (!h || !hmin) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "minimum before init");
+  const mlf_params& p = h->p;
+  const Layers L = layers_of(h);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
+    hipLaunchKernelGGL((min_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part_ptr(h), p.nx, p.ny,
+                       h->pitch, p.n_layers, L);
+  });
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(finish_min, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), 1, kRedBlocks);
+  HIPCHK(hipGetLastError());
+  double dev[kMaxLayers];
+  HIPCHK(hipMemcpyAsync(dev, redout_ptr(h), sizeof(dev), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < p.n_layers; ++i) hmin[i] = dev[i];
+  return MLF_OK;
+}
+
+mlf_status mlf_step_until(mlf_handle* h, int64_t max_steps, int32_t check_every, const double* threshold,
+                          int64_t* steps_taken, int32_t* layer) {
+  if (!h || !threshold || !steps_taken || !layer || max_steps < 0 || check_every < 1) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_step_until before mlf_init");
+  *steps_taken = 0;
+  *layer = -1;
+  double hmin[kMaxLayers];
+  while (*steps_taken < max_steps) {
+    const int64_t adv = std::min<int64_t>(check_every, max_steps - *steps_taken);
+    mlf_status st = mlf_step(h, adv);
+    *steps_taken += adv;
+    if (st != MLF_OK) return st;
+    if ((st = mlf_layer_min(h, hmin)) != MLF_OK) return st;
+    for (int i = 0; i < h->p.n_layers; ++i)
+      if (hmin[i] <= threshold[i]) {
+        *layer = i;
+        return MLF_OK;
+      }
+  }
+  return MLF_OK;
+}
+
 mlf_status mlf_read_populations(mlf_handle* h, double* f) {
   if (!h || !f) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "read before init");
@@ -1258,7 +1385,10 @@ constexpr size_t kBatchTableBytes = 4u << 20;
 constexpr size_t kBatchItemOff = kBatchTableOff + kBatchTableBytes;         // int2[n_items]
 constexpr size_t kBatchItemBytes = 12u << 20;
 constexpr size_t kBatchSumOff = kBatchItemOff + kBatchItemBytes;          // double sums[kMaxFilms][4]
-constexpr size_t kBatchScratchBytes = kBatchSumOff + kMaxFilms * kMaxLayers * sizeof(double);
+constexpr size_t kBatchMinTabOff = kBatchSumOff + kMaxFilms * kMaxLayers * sizeof(double);  // MinFilm[n]
+constexpr size_t kBatchMinPartOff = kBatchMinTabOff + (kMaxFilms * sizeof(MinFilm) + 255) / 256 * 256;
+constexpr size_t kBatchScratchBytes =
+    kBatchMinPartOff + (size_t)kMaxFilms * kMinBlocksPerFilm * kMaxLayers * sizeof(double);
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -1709,6 +1839,79 @@ mlf_status mlf_batch_layer_mass(mlf_batch* b, int32_t film, double* mass) {
   h->cur = b->cur;
   st = mlf_layer_mass(h, mass);
   return st == MLF_OK ? st : bfail(b, st, h->err);
+}
+
+mlf_status mlf_batch_layer_min(mlf_batch* b, int32_t film, double* hmin) {
+  if (!b) return MLF_EINVAL;
+  mlf_status st = film_index(b, film);
+  if (st != MLF_OK) return st;
+  mlf_handle* h = b->film[film];
+  h->cur = b->cur;
+  st = mlf_layer_min(h, hmin);
+  return st == MLF_OK ? st : bfail(b, st, h->err);
+}
+
+mlf_status mlf_batch_layer_min_all(mlf_batch* b, double* hmin) {
+  if (!b || !hmin) return MLF_EINVAL;
+  mlf_status st = batch_ready(b);
+  if (st != MLF_OK) return st;
+  std::vector<MinFilm> tab(b->n);
+  for (int f = 0; f < b->n; ++f) {
+    const mlf_handle* h = b->film[f];
+    tab[f] = MinFilm{(long long)b->offset[f], (long long)h->plane, h->p.nx, h->p.ny, h->pitch, h->p.n_layers,
+                     layers_of(h)};
+  }
+  MinFilm* dtab = reinterpret_cast<MinFilm*>(b->scratch + kBatchMinTabOff);
+  double* part = reinterpret_cast<double*>(b->scratch + kBatchMinPartOff);
+  double* out = reinterpret_cast<double*>(b->scratch + kBatchSumOff);
+  BHIPCHK(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(MinFilm), hipMemcpyHostToDevice, b->stream));
+  const dim3 grid(kMinBlocksPerFilm, (unsigned)b->n);
+  unsigned char* buf = b->pop[b->cur];
+  by_storage(b->film[0], [&](auto* rt, auto* st) {  // all films share the storage format
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    hipLaunchKernelGGL((batch_min_partials<R, S>), grid, dim3(256), 0, b->stream, dtab, buf, part);
+  });
+  BHIPCHK(hipGetLastError());
+  const int nt = b->n * kMaxLayers;
+  hipLaunchKernelGGL(finish_min, dim3((nt + 255) / 256), dim3(256), 0, b->stream, part, out, b->n, kMinBlocksPerFilm);
+  BHIPCHK(hipGetLastError());
+  BHIPCHK(hipMemcpyAsync(hmin, out, (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_step_until(mlf_batch* b, int64_t max_steps, int32_t check_every, const double* threshold,
+                                int64_t* t_hit, int32_t* layer_hit, int64_t* steps_taken) {
+  if (!b || !threshold || !t_hit || !layer_hit || !steps_taken || max_steps < 0 || check_every < 1)
+    return MLF_EINVAL;
+  mlf_status st = batch_ready(b);
+  if (st != MLF_OK) return st;
+  for (int f = 0; f < b->n; ++f) {
+    t_hit[f] = -1;
+    layer_hit[f] = -1;
+  }
+  *steps_taken = 0;
+  std::vector<double> hmin((size_t)b->n * kMaxLayers);
+  int open = b->n;
+  while (open > 0 && *steps_taken < max_steps) {
+    const int64_t adv = std::min<int64_t>(check_every, max_steps - *steps_taken);
+    st = mlf_batch_step(b, adv);
+    *steps_taken += adv;
+    if (st != MLF_OK) return st;
+    if ((st = mlf_batch_layer_min_all(b, hmin.data())) != MLF_OK) return st;
+    for (int f = 0; f < b->n; ++f) {
+      if (t_hit[f] >= 0) continue;
+      for (int i = 0; i < b->film[f]->p.n_layers; ++i)
+        if (hmin[(size_t)f * kMaxLayers + i] <= threshold[(size_t)f * kMaxLayers + i]) {
+          t_hit[f] = b->steps;
+          layer_hit[f] = i;
+          --open;
+          break;
+        }
+    }
+  }
+  return MLF_OK;
 }
 
 mlf_status mlf_batch_set_launch(mlf_batch* b, int32_t block_w, int32_t seg_h, int32_t persistent) {

@@ -1,0 +1,141 @@
+"""Droplet relaxation sweep (Sec. IV.B, Fig. relax) on the batched GPU path.
+
+Every (kind, expected angle, initial angle) is one pseudo-1D film of a
+single batch, so the whole sweep advances with one launch per step (and a
+captured graph of the step loop).  After relaxation the host fits a
+circular arc that shares the drop's peak position and height by minimising
+the volume error E(theta) = int |h - H_theta| / int h, as the paper
+measures contact angles, and reports E at the expected angle as well.
+
+Kinds (two-liquid types follow the paper's naming):
+
+* ``sessile``: one liquid on the substrate, S_01 = gamma (cos theta - 1)
+  (Young);
+* ``type1``: a drop of liquid one under a bath of liquid two, flat top
+  surface, S_01 = gamma_12 (cos theta - 1);
+* ``type3``: a drop of liquid two on the substrate, liquid one a precursor
+  underneath; the substrate couples to the top surface through the pair
+  (0, 2): S_02 = gamma_2v (cos theta - 1);
+* ``lens``: a symmetric lens of liquid two floating on a bath of liquid one
+  (gamma_12 = gamma_2v = gamma), Neumann: S_11 = 2 gamma (cos theta - 1).
+
+Type-2 drops (liquid one under a precursor of liquid two) need a stable
+upper precursor, which the printed wetting potentials do not provide with
+these coefficients; they are left out.
+
+With the small-slope free energy the equilibrium slope of a sessile drop is
+tan(theta_eq) = 2 sin(theta / 2) (first integral between precursor and
+drop), slightly below Young's angle: 19.15 degrees for 20.
+"""
+import math
+
+import numpy as np
+
+from . import inputs, mlfilm
+
+KINDS = ("sessile", "type1", "type3", "lens")
+HSTAR, GAMMA, MU, BATH = 0.5, 0.005, 0.02, 36.0
+
+
+def model_angle(theta):
+    """Equilibrium angle (degrees) of the small-slope model for Young's
+    (or Neumann's) angle theta (degrees)."""
+    return math.degrees(math.atan(2.0 * math.sin(math.radians(theta) / 2.0)))
+
+
+def cap(x, x0, half_width, theta):
+    """Circular cap of the given base half-width and contact angle (rad)."""
+    rho = half_width / math.sin(theta)
+    top = rho * (1.0 - math.cos(theta))
+    return np.maximum(np.sqrt(np.maximum(rho * rho - (x - x0) ** 2, 0.0)) - (rho - top), 0.0)
+
+
+def drop(kind, theta, theta0, nx=256, half_width=60.0):
+    """(film, h0) of one drop: expected angle theta, initial angle theta0
+    (degrees), on a periodic strip of nx nodes."""
+    x = np.arange(nx) + 0.5
+    c = cap(x, nx / 2, half_width, math.radians(theta0))
+    ct = math.cos(math.radians(theta)) - 1.0
+    if kind == "sessile":
+        film = inputs.film_params(1, nx, 1, gamma=[GAMMA], mu=[MU], hstar=HSTAR, spread={(0, 1): GAMMA * ct})
+        h = [c + HSTAR]
+    elif kind == "type1":
+        film = inputs.film_params(2, nx, 1, gamma=[GAMMA, GAMMA], mu=[MU, MU], hstar=HSTAR,
+                                  spread={(0, 1): GAMMA * ct, (1, 1): 0.0, (0, 2): 0.0})
+        h1 = c + HSTAR
+        h = [h1, BATH - h1]
+    elif kind == "type3":
+        film = inputs.film_params(2, nx, 1, gamma=[GAMMA, GAMMA], mu=[MU, MU], hstar=HSTAR,
+                                  spread={(0, 1): 0.0, (1, 1): 0.0, (0, 2): GAMMA * ct})
+        h = [np.full(nx, HSTAR), c + HSTAR]
+    elif kind == "lens":
+        film = inputs.film_params(2, nx, 1, gamma=[GAMMA, GAMMA], mu=[2.5 * MU, 2.5 * MU], hstar=HSTAR,
+                                  spread={(0, 1): 0.0, (1, 1): 2 * GAMMA * ct, (0, 2): 0.0})
+        z1 = BATH - c
+        h = [z1, (BATH + c + HSTAR) - z1]
+    else:
+        raise ValueError(f"unknown kind {kind!r}")
+    return film, np.stack(h)[:, None, :]
+
+
+def profiles(kind, h):
+    """Non-negative drop profiles to fit, from heights h[N][1][nx]: the drop
+    above its surroundings (both faces for a lens)."""
+    def far(z):
+        return float(np.median(np.concatenate([z[:8], z[-8:]])))
+
+    if kind == "sessile" or kind == "type1":
+        z = h[0, 0]
+        return {"drop": z - far(z)}
+    if kind == "type3":
+        z = h[1, 0]
+        return {"drop": z - far(z)}
+    z1, z2 = h[0, 0], h[0, 0] + h[1, 0]
+    return {"top": z2 - far(z2), "bottom": far(z1) - z1}
+
+
+def fit_arc(d, lo=2.0, hi=60.0, step=0.05):
+    """(angle in degrees, E at that angle, E as a function of the angle in
+    radians) of the best arc through the peak of profile d."""
+    x = np.arange(len(d), dtype=np.float64)
+    xp = int(np.argmax(d))
+    hp = float(d[xp])
+    vol = float(d.sum())
+
+    def err(theta):
+        rho = hp / (1.0 - math.cos(theta))
+        arc = np.sqrt(np.maximum(rho * rho - (x - xp) ** 2, 0.0)) - (rho - hp)
+        return float(np.abs(d - np.maximum(arc, 0.0)).sum() / vol)
+
+    grid = np.radians(np.arange(lo, hi + step / 2, step))
+    es = np.array([err(t) for t in grid])
+    i = int(np.argmin(es))
+    return math.degrees(grid[i]), float(es[i]), err
+
+
+def sweep(cases, steps=200_000, precision="f32", graph_steps=1000, launch=(64, 1, 0)):
+    """Relax every case (kind, expected angle, initial angle) in one batch
+    and fit the results.  Returns one dict per case and face."""
+    films = [drop(k, th, th0) for k, th, th0 in cases]
+    b = mlfilm.Batch([f for f, _ in films], precision)
+    b.set_launch(*launch)
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    if graph_steps and steps >= graph_steps:
+        b.capture(graph_steps)
+    b.step(steps)
+    rows = []
+    for i, (kind, th, th0) in enumerate(cases):
+        h, ux, _ = b.read(i)
+        for face, d in profiles(kind, h).items():
+            ang, e_best, err = fit_arc(d)
+            rows.append({"kind": kind, "face": face, "expected": th, "start": th0, "measured": ang,
+                         "model": model_angle(th), "fit_error": e_best,
+                         "error_at_expected": err(math.radians(th)), "max_speed": float(np.abs(ux).max())})
+    return rows
+
+
+def paper_cases(thetas=(10.0, 15.0, 20.0, 25.0, 30.0), kinds=KINDS):
+    """Each kind and expected angle started at the angle, twice it (at most
+    45 degrees) and half of it."""
+    return [(k, th, th0) for k in kinds for th in thetas for th0 in (th, min(2 * th, 45.0), th / 2)]

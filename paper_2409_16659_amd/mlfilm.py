@@ -86,6 +86,8 @@ def load_library():
         "mlf_read": (st, [H, _D, _D, _D]),
         "mlf_read_device": (st, [H, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_layer_mass": (st, [H, _D]),
+        "mlf_layer_min": (st, [H, _D]),
+        "mlf_step_until": (st, [H, C.c_int64, C.c_int32, _D, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
         "mlf_read_populations": (st, [H, _D]),
         "mlf_write_populations": (st, [H, _D]),
         "mlf_save": (st, [H, C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -104,6 +106,10 @@ def load_library():
         "mlf_batch_capture": (st, [H, C.c_int32]),
         "mlf_batch_read": (st, [H, C.c_int32, _D, _D, _D]),
         "mlf_batch_layer_mass": (st, [H, C.c_int32, _D]),
+        "mlf_batch_layer_min": (st, [H, C.c_int32, _D]),
+        "mlf_batch_layer_min_all": (st, [H, _D]),
+        "mlf_batch_step_until": (st, [H, C.c_int64, C.c_int32, _D, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int64)]),
         "mlf_batch_read_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_batch_init_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_batch_init_device_all": (st, [H, C.POINTER(C.c_void_p)]),
@@ -228,6 +234,12 @@ def friction_matrix(h, mu, slip=None):
     return K, rate.value
 
 
+def rupture_threshold(film):
+    """Height at or below which a layer counts as ruptured (its first
+    hole): 1.5 h*, the same for every layer."""
+    return np.full(int(film["n_layers"]), 1.5 * float(film["hstar"]))
+
+
 class Film:
     """One film on the current CUDA/HIP device.
 
@@ -325,6 +337,22 @@ class Film:
         m = np.empty(self.n)
         self._check(self.lib.mlf_layer_mass(self.h, _dp(m)), "mlf_layer_mass")
         return m
+
+    def layer_min(self):
+        """Per-layer minimum height (the heights read() returns)."""
+        m = np.empty(self.n)
+        self._check(self.lib.mlf_layer_min(self.h, _dp(m)), "mlf_layer_min")
+        return m
+
+    def step_until(self, max_steps, check_every=100, threshold=None):
+        """Step until some layer's minimum height reaches its threshold
+        (default: the rupture criterion, 1.5 h*), checked every check_every
+        steps.  Returns (steps taken, layer or -1)."""
+        thr = rupture_threshold(self.film) if threshold is None else _f64(threshold)
+        taken, layer = C.c_int64(), C.c_int32()
+        self._check(self.lib.mlf_step_until(self.h, int(max_steps), int(check_every), _dp(thr),
+                                            C.byref(taken), C.byref(layer)), "mlf_step_until")
+        return taken.value, layer.value
 
     def populations(self):
         f = np.empty((self.n, 9, self.ny, self.nx))
@@ -493,6 +521,36 @@ class Batch:
         m = np.empty(self.params[f].n_layers)
         self._check(self.lib.mlf_batch_layer_mass(self.h, int(f), _dp(m)), "mlf_batch_layer_mass")
         return m
+
+    def layer_min(self, f):
+        m = np.empty(self.params[f].n_layers)
+        self._check(self.lib.mlf_batch_layer_min(self.h, int(f), _dp(m)), "mlf_batch_layer_min")
+        return m
+
+    def layer_min_all(self):
+        """Minimum heights of every film, [n][MAX_LAYERS] (+inf past a
+        film's layers), from one pass over the batch."""
+        m = np.empty((self.n, MAX_LAYERS))
+        self._check(self.lib.mlf_batch_layer_min_all(self.h, _dp(m)), "mlf_batch_layer_min_all")
+        return m
+
+    def step_until(self, max_steps, check_every=100, threshold=None):
+        """Step the batch until every film has some layer at or below its
+        threshold (default 1.5 h* per film) or max_steps have run.  Returns
+        (t_hit, layer_hit, steps taken): t_hit[f] is the batch step count at
+        the end of the chunk in which film f first got there (-1: never)."""
+        thr = np.full((self.n, MAX_LAYERS), -np.inf)
+        for f, film in enumerate(self.films):
+            t = rupture_threshold(film) if threshold is None else _f64(threshold[f])
+            thr[f, :len(t)] = t
+        t_hit = np.empty(self.n, dtype=np.int64)
+        layer = np.empty(self.n, dtype=np.int32)
+        taken = C.c_int64()
+        self._check(self.lib.mlf_batch_step_until(
+            self.h, int(max_steps), int(check_every), _dp(thr),
+            t_hit.ctypes.data_as(C.POINTER(C.c_int64)), layer.ctypes.data_as(C.POINTER(C.c_int32)),
+            C.byref(taken)), "mlf_batch_step_until")
+        return t_hit, layer, taken.value
 
     def set_launch(self, block_w=0, seg_h=0, persistent=0):
         self._check(self.lib.mlf_batch_set_launch(self.h, int(block_w), int(seg_h), int(persistent)),

@@ -50,7 +50,7 @@ def unit(prec):
     """Unit roundoffs of the (rest, moving) planes."""
     return tuple(2.0 ** -(m + 1) for m in MANT[prec])
 
-ETA_MAX = 5.2e-4                  # fastest growth rate of the 4-layer film per step (LSA)
+ETA_MAX = 5.2e-4                  # lubrication LSA rate of the 4-layer film; the scheme grows slower (1.7e-4)
 
 
 @pytest.fixture(scope="module")

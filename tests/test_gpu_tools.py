@@ -1,0 +1,193 @@
+"""Diagnostics built on the hot path, on the GPU: per-layer minimum height,
+rupture detection (single films and batches), and the linear growth of
+seeded eigenmodes against the lattice model of the stability tool.
+
+Gates: the minimum equals the minimum of the read-back heights bit for bit
+in every storage format; the rupture step and layer of an FP64 film equal
+the oracle's (same check interval); a batch reports for every film the
+rupture step that the film gives when stepped alone; FP64 eigenmode growth
+rates within 1 % of the lattice model in x and in y (the oracle meets the
+same bar, tests/test_lsa.py), FP32 within 2 %.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2409_16659_amd import inputs, lsa
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mlf(torch_cuda):
+    from paper_2409_16659_amd import mlfilm
+
+    mlfilm.load_library()
+    return mlfilm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_film(n, nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    gam = list(rng.uniform(0.5e-2, 1.5e-2, size=n))
+    return inputs.film_params(n, nx, ny, gamma=gam, mu=list(rng.uniform(2e-3, 5e-3, size=n)), hstar=0.15,
+                              spread={(l, 1): inputs.young_spreading(gam[l], 20.0) for l in range(n)})
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16", "f16mix", "bf16mix"])
+def test_layer_min_is_min_of_read_back(mlf, prec):
+    film = small_film(3, 70, 33, seed=1)
+    rng = np.random.default_rng(2)
+    h0 = np.stack([(1.0 - 0.2 * i) + 0.05 * rng.uniform(-1, 1, (33, 70)) for i in range(3)])
+    g = mlf.Film(film, prec)
+    g.init(h0)
+    g.step(25)
+    h = g.read()[0]
+    assert np.array_equal(g.layer_min(), h.reshape(3, -1).min(axis=1))
+
+
+def test_batch_minima_of_all_films(mlf):
+    rng = np.random.default_rng(3)
+    films = []
+    for j, (n, nx, ny) in enumerate([(2, 64, 64), (4, 37, 5), (1, 200, 1), (3, 96, 80)]):
+        film = small_film(n, nx, ny, seed=10 + j)
+        films.append((film, np.stack([(1.0 - 0.2 * i) + 0.05 * rng.uniform(-1, 1, (ny, nx)) for i in range(n)])))
+    b = mlf.Batch([f for f, _ in films], "f32")
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    b.step(31)
+    allm = b.layer_min_all()
+    for i, (film, _) in enumerate(films):
+        n = film["n_layers"]
+        want = b.read(i)[0].reshape(n, -1).min(axis=1)
+        assert np.array_equal(allm[i, :n], want), i
+        assert np.array_equal(b.layer_min(i), want)
+        assert np.all(np.isinf(allm[i, n:]))
+
+
+def rupture_film():
+    """Four layers (the 4-layer workload's parameters) on a pseudo-1D strip
+    of 192 nodes with 1 % uniform noise: the top layer breaks first, after
+    about 1.9e4 steps."""
+    film = inputs._film4(192, 1)
+    return film, inputs.initial_heights(film, (1.0, 0.8, 0.6, 0.4), "uniform", 11, 1e-2)
+
+
+def test_rupture_step_matches_oracle(mlf, oracle_mod):
+    film, h0 = rupture_film()
+    every, cap = 100, 40_000
+    thr = mlf.rupture_threshold(film)
+    g = mlf.Film(film, "f64")
+    g.init(h0)
+    steps, layer = g.step_until(cap, every)
+    o = oracle_mod.Oracle(film)
+    o.init(h0)
+    o_layer, margin = -1, np.inf
+    while o.steps_done < cap:
+        o.step(every)
+        mn = o.read()[0].reshape(film["n_layers"], -1).min(axis=1)
+        margin = min(margin, float(np.abs(mn - thr).min()))
+        hit = np.nonzero(mn <= thr)[0]
+        if hit.size:
+            o_layer = int(hit[0])
+            break
+    say(f"rupture: GPU step {steps} layer {layer}; oracle step {o.steps_done} layer {o_layer}")
+    assert 0 <= layer == o_layer == film["n_layers"] - 1   # the top layer breaks first
+    # the decision at each check is taken on minima that agree to ~1e-12;
+    # only a minimum within that of the threshold could move it by one check
+    assert steps == o.steps_done or margin < 1e-9
+    assert steps == g.steps_done
+    assert g.layer_min()[layer] <= thr[layer]
+
+
+def test_step_until_stops_at_max_steps(mlf):
+    film, h0 = rupture_film()
+    g = mlf.Film(film, "f32")
+    g.init(h0)
+    steps, layer = g.step_until(1000, 300)
+    assert (steps, layer) == (1000, -1) and g.steps_done == 1000
+    with pytest.raises(mlf.MlfError) as e:
+        g.step_until(10, 0)
+    assert e.value.status == "EINVAL"
+
+
+def test_batch_rupture_times_match_single_films(mlf):
+    """2D films of different sizes, layer counts and noise: the batch's
+    rupture step for each film equals the step the film reports alone
+    (same launch shape, same check interval; the batch keeps stepping films
+    that have ruptured until all have)."""
+    specs = [(inputs._film4, (1.0, 0.8, 0.6, 0.4), 64, 64, 21, 2e-2),
+             (inputs._film4, (1.0, 0.8, 0.6, 0.4), 96, 48, 22, 1e-2),
+             (inputs._film3, (1.0, 0.8, 0.6), 64, 64, 23, 5e-2),
+             (inputs._film4, (1.0, 0.8, 0.6, 0.4), 48, 80, 24, 3e-2)]
+    films = []
+    for make, hbar, nx, ny, seed, amp in specs:
+        film = make(nx, ny)
+        films.append((film, inputs.initial_heights(film, hbar, "uniform", seed, amp)))
+    launch, every, cap = (128, 8), 200, 150_000
+    b = mlf.Batch([f for f, _ in films], "f32")
+    b.set_launch(*launch, 0)
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    t_hit, layer, taken = b.step_until(cap, every)
+    say(f"batch rupture steps {t_hit.tolist()} layers {layer.tolist()} after {taken} steps")
+    assert np.all(t_hit > 0) and taken == t_hit.max()
+    for i, (film, h0) in enumerate(films):
+        g = mlf.Film(film, "f32")
+        g.set_launch(*launch)
+        g.init(h0)
+        steps, lay = g.step_until(cap, every)
+        assert (steps, lay) == (t_hit[i], layer[i]), i
+
+
+def seeded_mode(film, hbar, m, axis, eps):
+    """Heights and velocities of the leading lattice eigenmode of mode m
+    along x (axis 1) or y (axis 0)."""
+    n, nx, ny = film["n_layers"], film["nx"], film["ny"]
+    length = nx if axis == 1 else ny
+    q = 2 * math.pi * m / length
+    rate, dh, w = lsa.leading_mode(film, hbar, q, "lattice")
+    s = np.arange(length)
+    c, sn = np.cos(q * s), np.sin(q * s)
+    shape = (1, 1, nx) if axis == 1 else (1, ny, 1)
+    h0 = np.asarray(hbar)[:, None, None] + eps * dh[:, None, None] * c.reshape(shape)
+    j = eps * w[:, None, None] * sn.reshape(shape)
+    h0 = np.broadcast_to(h0, (n, ny, nx)).copy()
+    u = np.broadcast_to(j / h0, (n, ny, nx)).copy()
+    ux, uy = (u, np.zeros_like(u)) if axis == 1 else (np.zeros_like(u), u)
+    return rate, h0, ux, uy
+
+
+@pytest.mark.parametrize("prec,axis", [("f64", 1), ("f64", 0), ("f32", 1)])
+def test_eigenmode_growth_follows_lattice_model(mlf, prec, axis):
+    film = inputs._film3(256, 16) if axis == 1 else inputs._film3(16, 256)
+    hbar = (1.0, 0.8, 0.6)
+    eps, tol = (1e-7, 0.01) if prec == "f64" else (1e-4, 0.02)
+    for m in (3, 6):
+        rate, h0, ux, uy = seeded_mode(film, hbar, m, axis, eps)
+        g = mlf.Film(film, prec)
+        g.init(h0, ux, uy)
+        amp = []
+        for t in (500, 5000):
+            g.step(t - g.steps_done)
+            h = g.read()[0]
+            prof = h.mean(axis=2) if axis == 0 else h.mean(axis=1)     # [N][length]
+            amp.append(np.fft.fft(prof - np.asarray(hbar)[:, None], axis=1)[:, m])
+        got = math.log(np.linalg.norm(amp[1]) / np.linalg.norm(amp[0])) / 4500
+        say(f"{prec} axis={axis} m={m}: lattice model {rate:.5e} GPU {got:.5e}")
+        assert abs(got - rate) <= tol * rate
