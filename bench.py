@@ -64,10 +64,10 @@ def measured_traffic(workload: str, prec: str, launch):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(film, h0, budget_s: float):
+def cpu_baseline(film, h0, budget_s: float, lattice="d2q9"):
     import oracle
 
-    o = oracle.Oracle(film)
+    o = oracle.Oracle(film, oracle.D1Q3 if lattice == "d1q3" else oracle.D2Q9)
     o.init(h0)
     o.step(1)  # warm-up (page faults, thread start)
     n = 0
@@ -80,8 +80,8 @@ def cpu_baseline(film, h0, budget_s: float):
             break
     lu = film["n_layers"] * film["nx"] * film["ny"] * n
     return {"value": lu / el, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"{n} FP64 steps of the same {film['nx']}x{film['ny']} {film['n_layers']}-layer film "
-                      f"({el:.1f} s)"}
+            "sample": f"{n} FP64 {lattice.upper()} steps of the same {film['nx']}x{film['ny']} "
+                      f"{film['n_layers']}-layer film ({el:.1f} s)"}
 
 
 def bench_batch(args):
@@ -239,6 +239,9 @@ def main():
                     help="learned surrogate instead: solver-generated training windows, training, and judged "
                          "runs against the plain solver (256^2 three-layer films, 100-step windows)")
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--lattice", choices=["d2q9", "d1q3"], default="d2q9",
+                    help="d1q3: pseudo-1D workloads on the D1Q3 lattice (film held in LDS, many steps "
+                         "per launch)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of one population buffer instead (copy ceiling; "
                          "the reference kernel for scaling rocprofv3 byte counters)")
@@ -286,10 +289,13 @@ def main():
                           "bytes_written": nbytes, "us": sec * 1e6, "GBs": 2 * nbytes / sec / 1e9}), flush=True)
         return
 
-    g = mlfilm.Film(film, prec, check_every=-1)
+    d1 = args.lattice == "d1q3"
+    g = mlfilm.Film(film, prec, check_every=-1, lattice=args.lattice)
     g.init(h0)
-    pl = None if args.autotune else profiled_launch(args.workload, prec)
-    if args.block_w or args.seg_h:
+    pl = None if (args.autotune or d1) else profiled_launch(args.workload, prec)
+    if d1:
+        source = "fixed (D1Q3 kernels)"
+    elif args.block_w or args.seg_h:
         g.set_launch(args.block_w, args.seg_h)
         source = "given"
     elif pl:
@@ -319,7 +325,7 @@ def main():
 
     value = n_lu * args.steps / wall
     achieved = bytes_per_lu * n_lu / (kern_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, prec, launch)
+    traffic = None if d1 else measured_traffic(args.workload, prec, launch)
     out = {
         "metric": "layer-lattice updates/s & % HBM roofline; surrogate/batched speedup @1e-3 L2",
         "value": value,
@@ -334,14 +340,20 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32"}.get(prec, "f32"),
         "data": "synthetic",
         "config": {"workload": args.workload, "layers": film["n_layers"], "nx": film["nx"], "ny": film["ny"],
-                   "storage": prec, "lattice": "D2Q9", "tau": film["tau"], "launch": list(launch),
+                   "storage": prec, "lattice": args.lattice.upper(), "tau": film["tau"], "launch": list(launch),
                    "launch_source": source},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_lu": bytes_per_lu, "kernel_ms": kern_ms},
     }
+    if d1:
+        # pseudo-1D films are tiny: the resident D1Q3 kernel keeps the film in
+        # LDS between its first load and last store, so there is no per-step
+        # HBM traffic to price; the figure of merit is us/step
+        out["roofline"] = None
+        out["note"] = "D1Q3 pseudo-1D film: latency-bound (us/step), no HBM roofline"
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(film, h0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(film, h0, args.cpu_seconds, args.lattice)
     print(json.dumps(out), flush=True)
 
 

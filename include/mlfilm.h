@@ -76,6 +76,15 @@ typedef enum {
   MLF_BF16_MIX = 5  /* FP32 rest population, bfloat16 moving ones, FP32 arith.   */
 } mlf_precision;
 
+/* Lattice.  D1Q3 (velocities 0, +1, -1; 3-point stencils) is the pseudo-1D
+ * form of the scheme: it needs ny == 1 and F64 or F32 storage
+ * (EUNSUPPORTED otherwise) and stores three planes (rest, +x, -x).  In
+ * exact arithmetic it equals D2Q9 on a film one row high.  A D1Q3 film whose
+ * state fits one workgroup's LDS (5 N nx values of the storage type within
+ * 64 KiB, nx <= 1024) runs many steps per kernel launch with the film held
+ * on chip; larger ones take one launch per step. */
+typedef enum { MLF_D2Q9 = 0, MLF_D1Q3 = 1 } mlf_lattice;
+
 typedef struct mlf_params {
   int32_t n_layers;   /* N, 1..MLF_MAX_LAYERS                                  */
   int32_t nx, ny;     /* periodic grid, >= 1 each (ny == 1: pseudo-1D film)     */
@@ -92,6 +101,7 @@ typedef struct mlf_params {
   double spread[MLF_MAX_PAIRS];
   int32_t check_every;   /* guard poll interval in steps; 0: only at the end of mlf_step */
   int32_t allow_unstable;/* nonzero: skip the friction-stiffness check in mlf_init */
+  int32_t lattice;       /* mlf_lattice; 0 (zero-initialised) is D2Q9          */
 } mlf_params;
 
 typedef struct mlf_handle mlf_handle;
@@ -158,8 +168,9 @@ mlf_status mlf_layer_min(mlf_handle* h, double* hmin);
 mlf_status mlf_step_until(mlf_handle* h, int64_t max_steps, int32_t check_every, const double* threshold,
                           int64_t* steps_taken, int32_t* layer);
 
-/* Absolute populations f_ki in FP64, host [N][9][ny][nx] (read) or set
- * from such an array (write; keeps h_ref).  Synchronise. */
+/* Absolute populations f_ki in FP64, host [N][Q][ny][nx] with Q = 9 (D2Q9)
+ * or 3 (D1Q3, order rest, +x, -x) (read) or set from such an array (write;
+ * keeps h_ref).  Synchronise. */
 mlf_status mlf_read_populations(mlf_handle* h, double* f);
 mlf_status mlf_write_populations(mlf_handle* h, const double* f);
 
@@ -173,7 +184,8 @@ mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
 /* Launch shape of the step kernel: block_w threads (64, 128, 192 or 256),
  * one per column of a strip of block_w - 4 columns plus two halo columns on
  * each side, and seg_h rows per workgroup (>= 1).  Results do not depend on
- * the shape.  0 = default. */
+ * the shape.  0 = default.  D1Q3 films keep their fixed kernel shapes (the
+ * values are stored and ignored; mlf_autotune returns them unchanged). */
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h);
 mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h);
 
@@ -190,7 +202,8 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
  * that mlf_step replays whenever at least `steps` steps remain (guard polls
  * then fall on replay boundaries); 0 drops it.  The graph holds the step
  * constants: mlf_init, mlf_init_device, mlf_load, mlf_set_launch and
- * mlf_autotune drop it.  EUNSUPPORTED on the default stream. */
+ * mlf_autotune drop it.  EUNSUPPORTED on the default stream and for D1Q3
+ * films (which already run many steps per launch). */
 mlf_status mlf_capture(mlf_handle* h, int32_t steps);
 
 int64_t mlf_steps_done(const mlf_handle* h);

@@ -13,6 +13,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "d1q3_kernel.hpp"
 #include "step_kernel.hpp"
 
 using mlf::kMaxLayers;
@@ -31,6 +32,12 @@ constexpr int kPitchAlign = 64;  // elements
 // x-components of the D2Q9 velocities; plane k stores the population of
 // node x at column x - kCx[k] (see step_kernel.hpp)
 constexpr int kCx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+constexpr int kCx3[3] = {0, 1, -1};  // D1Q3: rest, +x, -x
+
+static_assert(offsetof(mlf_params, lattice) == 224 && sizeof(mlf_params) == 232, "mlf_params layout");
+
+int nq_of(const mlf_params* p) { return p->lattice == MLF_D1Q3 ? 3 : kQ; }
+int cx_of(int nq, int k) { return nq == 3 ? kCx3[k] : kCx[k]; }
 
 // Element format of a population plane.
 enum Fmt { kFmtF64, kFmtF32, kFmtF16, kFmtBF16 };
@@ -66,7 +73,7 @@ size_t node_bytes(int precision, int n, int k) {
 size_t plane_offset(int precision, int n, size_t plane, int k) {
   return k == 0 ? 0 : plane * (node_bytes(precision, n, 0) + (size_t)(k - 1) * node_bytes(precision, n, 1));
 }
-size_t buffer_bytes(int precision, int n, size_t plane) { return plane_offset(precision, n, plane, kQ); }
+size_t buffer_bytes(int precision, int n, size_t plane, int nq) { return plane_offset(precision, n, plane, nq); }
 
 int pitch_of(const mlf_params* p) { return (p->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
 
@@ -97,6 +104,14 @@ mlf_status validate(const mlf_params* p, std::string* why) {
     if (!std::isfinite(p->spread[j])) return bad("spread must be finite");
   size_t plane = (size_t)pitch_of(p) * (size_t)p->ny;
   if (plane * kQ * (size_t)p->n_layers > (size_t)1 << 40) return bad("grid too large");
+  if (p->lattice != MLF_D2Q9 && p->lattice != MLF_D1Q3) return bad("unknown lattice");
+  if (p->lattice == MLF_D1Q3) {
+    if (p->ny != 1) return bad("the D1Q3 lattice needs ny == 1");
+    if (p->precision != MLF_F64 && p->precision != MLF_F32) {
+      if (why) *why = "the D1Q3 lattice supports F64 and F32 storage";
+      return MLF_EUNSUPPORTED;
+    }
+  }
   // the step kernel addresses each group of three planes through a buffer
   // descriptor with 32-bit offsets and masks lanes with offset 2^31
   const size_t g0 = plane_offset(p->precision, p->n_layers, plane, 3);
@@ -248,6 +263,7 @@ struct PopView {
   unsigned char* base;
   long long plane;
   int nl;
+  int nq;  // directions: 9 (D2Q9) or 3 (D1Q3: rest, +x, -x)
   // unscaled value of layer i, direction k at node e
   __device__ double ld(int i, int k, long long e, const Layers& L) const {
     if (k == 0) return double(reinterpret_cast<const R*>(base)[e * nl + i]) / (kIs16<R> ? L.sc[i] : 1.0);
@@ -279,11 +295,17 @@ __global__ void init_kernel(PopView<R, S> f, const double* __restrict__ hs, cons
     const long long si = i * lstride + (long long)(y - yoff) * nx + x;
     const double h = hs[si], ux = uxs ? uxs[si] : 0.0, uy = uys ? uys[si] : 0.0;
     const double uu = ux * ux + uy * uy;
+    const long long row = (long long)y * pitch;
+    if (f.nq == 3) {  // D1Q3: f_0 = h (1 - U^2), f_+- = h (U^2 +- U) / 2
+      f.st(i, 0, row + x, (h - L.hb[i]) - h * ux * ux, L);
+      f.st(i, 1, row + mlf::wrap(x - 1, nx), 0.5 * h * (ux * ux + ux), L);
+      f.st(i, 2, row + mlf::wrap(x + 1, nx), 0.5 * h * (ux * ux - ux), L);
+      continue;
+    }
     const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
     const int cy[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
     // plane k keeps at column x - c_kx the population of node x
-    const long long row = (long long)y * pitch;
     f.st(i, 0, row + x, (h - L.hb[i]) - h * (2.0 / 3.0) * uu, L);
     for (int k = 1; k < 9; ++k) {
       const double cu = cx[k] * ux + cy[k] * uy;
@@ -298,6 +320,14 @@ __global__ void init_kernel(PopView<R, S> f, const double* __restrict__ hs, cons
 template <typename R, typename S>
 __device__ inline void node_moments(const PopView<R, S>& f, int i, long long row, int x, int nx, const Layers& L,
                                     double& h, double& qx, double& qy) {
+  if (f.nq == 3) {
+    const double v0 = f.ld(i, 0, row + x, L), v1 = f.ld(i, 1, row + mlf::wrap(x - 1, nx), L),
+                 v2 = f.ld(i, 2, row + mlf::wrap(x + 1, nx), L);
+    qx = v1 - v2;
+    qy = 0.0;
+    h = L.hb[i] + (v0 + v1 + v2);
+    return;
+  }
   const int cx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
   double v[9];
   for (int k = 0; k < 9; ++k) v[k] = f.ld(i, k, row + mlf::wrap(x - cx[k], nx), L);
@@ -339,7 +369,7 @@ __global__ void __launch_bounds__(256) mass_partials(PopView<R, S> f, double* __
     for (int i = 0; i < nl; ++i) {
       const long long e = (long long)y * pitch + x;
       double s = 0.0;
-      for (int k = 0; k < 9; ++k) s += f.ld(i, k, e, L);  // power-of-two scales: exact
+      for (int k = 0; k < f.nq; ++k) s += f.ld(i, k, e, L);  // power-of-two scales: exact
       acc[i] += s;
     }
   }
@@ -448,7 +478,7 @@ __global__ void __launch_bounds__(256) batch_min_partials(const MinFilm* __restr
                                                           unsigned char* __restrict__ buf,
                                                           double* __restrict__ part) {
   const MinFilm m = films[blockIdx.y];
-  const PopView<R, S> f{buf + m.offset, m.plane, m.nl};
+  const PopView<R, S> f{buf + m.offset, m.plane, m.nl, kQ};  // batches hold D2Q9 films
   block_min(f, m.nx, m.ny, m.pitch, m.nl, m.L, blockIdx.x * (long long)blockDim.x + threadIdx.x,
             (long long)gridDim.x * blockDim.x, part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kMaxLayers);
 }
@@ -731,6 +761,66 @@ hipError_t launch_step(const mlf_handle* h, const void* src, void* dst) {
   return e;
 }
 
+// ---- D1Q3 films (ny == 1): resident multi-step kernel or one step per launch
+
+constexpr int kD1MaxStepsPerLaunch = 65536;  // keeps a resident launch to ~0.1 s
+
+bool d1_resident(const mlf_params& p) {
+  const size_t c = p.precision == MLF_F64 ? 8 : 4;
+  return p.nx <= 2 * mlf::kD1Threads && (size_t)5 * p.n_layers * p.nx * c <= 65536;
+}
+
+int d1_threads(int nx) { return std::min(mlf::kD1Threads, std::max(64, (nx + 63) / 64 * 64)); }
+
+template <typename C, int NL, bool T1, int EA, int EB>
+hipError_t d1_launch_nl(mlf_handle* h, int steps) {
+  mlf::StepConsts<C> kc = make_consts<C>(h);
+  const mlf_params& p = h->p;
+  if (d1_resident(p)) {
+    const C* src = static_cast<const C*>(h->pop[h->cur]);
+    C* dst = static_cast<C*>(h->pop[h->cur ^ 1]);
+    const size_t lds = mlf::d1_resident_lds<C>(p.nx, NL);
+    hipLaunchKernelGGL((mlf::d1q3_resident<C, NL, T1, EA, EB>), dim3(1), dim3((unsigned)d1_threads(p.nx)), lds,
+                       h->stream, src, dst, kc, steps);
+    h->cur ^= 1;
+    return hipGetLastError();
+  }
+  const unsigned grid = (unsigned)((p.nx + mlf::kD1StepThreads - 5) / (mlf::kD1StepThreads - 4));
+  for (int s = 0; s < steps; ++s) {
+    hipLaunchKernelGGL((mlf::d1q3_step<C, NL, T1, EA, EB>), dim3(grid), dim3(mlf::kD1StepThreads), 0, h->stream,
+                       static_cast<const C*>(h->pop[h->cur]), static_cast<C*>(h->pop[h->cur ^ 1]), kc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    h->cur ^= 1;
+  }
+  return hipSuccess;
+}
+
+template <typename C, bool T1, int EA, int EB>
+hipError_t d1_launch_t(mlf_handle* h, int steps) {
+  switch (h->p.n_layers) {
+    case 1: return d1_launch_nl<C, 1, T1, EA, EB>(h, steps);
+    case 2: return d1_launch_nl<C, 2, T1, EA, EB>(h, steps);
+    case 3: return d1_launch_nl<C, 3, T1, EA, EB>(h, steps);
+    default: return d1_launch_nl<C, 4, T1, EA, EB>(h, steps);
+  }
+}
+
+// Advances a D1Q3 film by `steps` (1..kD1MaxStepsPerLaunch); flips h->cur.
+template <typename C>
+hipError_t d1_advance_c(mlf_handle* h, int steps) {
+  const bool t1 = h->p.tau == 1.0;
+  const bool e93 = h->p.exp_a == 9 && h->p.exp_b == 3;
+  if (t1 && e93) return d1_launch_t<C, true, 9, 3>(h, steps);
+  if (t1) return d1_launch_t<C, true, 0, 0>(h, steps);
+  if (e93) return d1_launch_t<C, false, 9, 3>(h, steps);
+  return d1_launch_t<C, false, 0, 0>(h, steps);
+}
+
+hipError_t d1_advance(mlf_handle* h, int steps) {
+  return h->p.precision == MLF_F64 ? d1_advance_c<double>(h, steps) : d1_advance_c<float>(h, steps);
+}
+
 int step_occupancy(const mlf_handle* h) {
   int occ = 0;
   by_storage(h, [&](auto* rt, auto* st) {
@@ -755,7 +845,8 @@ mlf_status launch_init(mlf_handle* h, const double* hs, const double* uxs, const
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers,
+                          nq_of(&p)};
     hipLaunchKernelGGL((init_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, hs, uxs, uys, lstride,
                        yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
   });
@@ -771,7 +862,8 @@ mlf_status launch_read(mlf_handle* h, double* ho, double* uxo, double* uyo, long
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers,
+                          nq_of(&p)};
     hipLaunchKernelGGL((read_kernel<R, S>), dim3(grid_for(n)), dim3(256), 0, h->stream, f, ho, uxo, uyo, lstride,
                        yoff, ya, yb, p.nx, h->pitch, p.n_layers, L);
   });
@@ -847,7 +939,7 @@ const char* mlf_version(void) { return "mlfilm 0.1 gfx950"; }
 mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes) {
   mlf_status st = validate(p, nullptr);
   if (st != MLF_OK) return st;
-  if (pop_bytes) *pop_bytes = buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny);
+  if (pop_bytes) *pop_bytes = buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny, nq_of(p));
   if (scratch_bytes) *scratch_bytes = kScratchBytes;
   return MLF_OK;
 }
@@ -879,7 +971,7 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   h->stream = static_cast<hipStream_t>(stream);
   h->pitch = pitch_of(p);
   h->plane = (size_t)h->pitch * p->ny;
-  h->pop_bytes = buffer_bytes(p->precision, p->n_layers, h->plane);
+  h->pop_bytes = buffer_bytes(p->precision, p->n_layers, h->plane, nq_of(p));
   for (int i = 0; i < kMaxLayers; ++i) h->hbar[i] = 0.0, h->scale[i] = 1.0;
   h->steps = 0;
   h->initialised = false;
@@ -931,6 +1023,11 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h) {
   if (!h || reps < 1) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "autotune before init");
+  if (h->p.lattice == MLF_D1Q3) {  // the D1Q3 kernels have fixed shapes
+    if (block_w) *block_w = h->block_w;
+    if (seg_h) *seg_h = h->seg_h;
+    return MLF_OK;
+  }
   drop_single_graph(h);
   const mlf_params& p = h->p;
   int dev = 0, ncu = 0;
@@ -1073,6 +1170,23 @@ mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
   if (!h || nsteps < 0) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_step before mlf_init");
   const int every = h->p.check_every;
+  if (h->p.lattice == MLF_D1Q3) {
+    int64_t left = nsteps, since = 0;
+    while (left > 0) {
+      int64_t chunk = std::min<int64_t>(left, kD1MaxStepsPerLaunch);
+      if (every > 0) chunk = std::min<int64_t>(chunk, every - since);
+      HIPCHK(d1_advance(h, (int)chunk));
+      left -= chunk;
+      since += chunk;
+      h->steps += chunk;
+      if (every > 0 && since >= every && left > 0) {
+        since = 0;
+        mlf_status s = check_guard(h);
+        if (s != MLF_OK) return s;
+      }
+    }
+    return every >= 0 ? check_guard(h) : MLF_OK;
+  }
   int64_t left = nsteps, since = 0;
   while (left > 0) {
     int64_t adv = 1;
@@ -1102,6 +1216,8 @@ mlf_status mlf_capture(mlf_handle* h, int32_t steps) {
   if (steps == 0) return MLF_OK;
   if (steps < 0 || steps % 2 != 0) return fail(h, MLF_EINVAL, "graph steps must be even and >= 0");
   if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_capture before mlf_init");
+  if (h->p.lattice == MLF_D1Q3)
+    return fail(h, MLF_EUNSUPPORTED, "D1Q3 films run many steps per launch; no graph needed");
   if (!h->stream) return fail(h, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
@@ -1173,7 +1289,8 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers,
+                          nq_of(&p)};
     hipLaunchKernelGGL((mass_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part_ptr(h), p.nx, p.ny,
                        h->pitch, p.n_layers, L);
   });
@@ -1197,7 +1314,8 @@ mlf_status mlf_layer_min(mlf_handle* h, double* hmin) {
   by_storage(h, [&](auto* rt, auto* st) {
     using R = std::remove_pointer_t<decltype(rt)>;
     using S = std::remove_pointer_t<decltype(st)>;
-    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers};
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers,
+                          nq_of(&p)};
     hipLaunchKernelGGL((min_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part_ptr(h), p.nx, p.ny,
                        h->pitch, p.n_layers, L);
   });
@@ -1240,17 +1358,18 @@ mlf_status mlf_read_populations(mlf_handle* h, double* f) {
   std::vector<unsigned char> raw(h->pop_bytes);
   HIPCHK(hipMemcpyAsync(raw.data(), h->pop[h->cur], h->pop_bytes, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  const int nq = nq_of(&p);
   for (int i = 0; i < p.n_layers; ++i)
-    for (int k = 0; k < kQ; ++k)
+    for (int k = 0; k < nq; ++k)
       for (int y = 0; y < p.ny; ++y)
         for (int x = 0; x < p.nx; ++x) {
           const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
-          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - cx_of(nq, k), p.nx);
           const size_t b = plane_offset(p.precision, p.n_layers, h->plane, k) +
                            (e * p.n_layers + i) * fmt_size(fm);
           double v = host_load(fm, raw.data() + b) / (fmt_scaled(fm) ? h->scale[i] : 1.0);
           if (k == 0) v += h->hbar[i];
-          f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x] = v;
+          f[(((size_t)i * nq + k) * p.ny + y) * p.nx + x] = v;
         }
   return MLF_OK;
 }
@@ -1260,15 +1379,16 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f) {
   if (!h->initialised) return fail(h, MLF_EINVAL, "write before init");
   const mlf_params& p = h->p;
   std::vector<unsigned char> raw(h->pop_bytes, 0);
+  const int nq = nq_of(&p);
   for (int i = 0; i < p.n_layers; ++i)
-    for (int k = 0; k < kQ; ++k)
+    for (int k = 0; k < nq; ++k)
       for (int y = 0; y < p.ny; ++y)
         for (int x = 0; x < p.nx; ++x) {
           const Fmt fm = k == 0 ? rest_fmt(p.precision) : move_fmt(p.precision);
-          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - kCx[k], p.nx);
+          const size_t e = (size_t)y * h->pitch + mlf::wrap(x - cx_of(nq, k), p.nx);
           const size_t b = plane_offset(p.precision, p.n_layers, h->plane, k) +
                            (e * p.n_layers + i) * fmt_size(fm);
-          double v = f[(((size_t)i * kQ + k) * p.ny + y) * p.nx + x];
+          double v = f[(((size_t)i * nq + k) * p.ny + y) * p.nx + x];
           if (k == 0) v -= h->hbar[i];
           host_store(fm, raw.data() + b, v * (fmt_scaled(fm) ? h->scale[i] : 1.0));
         }
@@ -1442,6 +1562,10 @@ mlf_status validate_batch(const mlf_params* films, int n, std::string* why) {
   for (int f = 0; f < n; ++f) {
     mlf_status st = validate(&films[f], why);
     if (st != MLF_OK) return st;
+    if (films[f].lattice != MLF_D2Q9) {
+      if (why) *why = "batches hold D2Q9 films";
+      return MLF_EUNSUPPORTED;
+    }
     if (films[f].precision != films[0].precision || films[f].tau != films[0].tau ||
         films[f].exp_a != films[0].exp_a || films[f].exp_b != films[0].exp_b) {
       if (why) *why = "films of a batch share precision, tau and exponents";
@@ -1452,7 +1576,7 @@ mlf_status validate_batch(const mlf_params* films, int n, std::string* why) {
 }
 
 size_t film_bytes(const mlf_params* p) {
-  return align256(buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny));
+  return align256(buffer_bytes(p->precision, p->n_layers, (size_t)pitch_of(p) * p->ny, nq_of(p)));
 }
 
 bool batch_double(const mlf_batch* b) { return b->p0.precision == MLF_F64; }

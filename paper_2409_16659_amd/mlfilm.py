@@ -51,7 +51,7 @@ class Params(C.Structure):
         ("tau", C.c_double), ("hstar", C.c_double), ("exp_a", C.c_int32), ("exp_b", C.c_int32),
         ("gamma", C.c_double * MAX_LAYERS), ("mu", C.c_double * MAX_LAYERS),
         ("slip", C.c_double * MAX_LAYERS), ("spread", C.c_double * MAX_PAIRS),
-        ("check_every", C.c_int32), ("allow_unstable", C.c_int32),
+        ("check_every", C.c_int32), ("allow_unstable", C.c_int32), ("lattice", C.c_int32),
     ]
 
 
@@ -156,9 +156,13 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(_D)
 
 
-def make_params(film, precision="f64", check_every=0, allow_unstable=False) -> Params:
+LATTICES = {"d2q9": 0, "d1q3": 1}
+
+
+def make_params(film, precision="f64", check_every=0, allow_unstable=False, lattice="d2q9") -> Params:
     """Copy a film parameter mapping (see ``inputs``) into the ABI struct."""
     p = Params()
+    p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     n = int(film["n_layers"])
     p.n_layers, p.nx, p.ny = n, int(film["nx"]), int(film["ny"])
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -248,13 +252,14 @@ class Film:
     """
 
     def __init__(self, film, precision="f64", check_every=0, allow_unstable=False,
-                 stream=None, device=None):
+                 stream=None, device=None, lattice="d2q9"):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         self.film = dict(film)
-        self.params = make_params(film, precision, check_every, allow_unstable)
+        self.params = make_params(film, precision, check_every, allow_unstable, lattice)
+        self.nq = 3 if self.params.lattice == LATTICES["d1q3"] else 9
         self.n, self.nx, self.ny = self.params.n_layers, self.params.nx, self.params.ny
         pop_bytes, scratch_bytes = query_sizes(self.params)
         self.pop_bytes, self.scratch_bytes = pop_bytes, scratch_bytes
@@ -355,13 +360,13 @@ class Film:
         return taken.value, layer.value
 
     def populations(self):
-        f = np.empty((self.n, 9, self.ny, self.nx))
+        f = np.empty((self.n, self.nq, self.ny, self.nx))
         self._check(self.lib.mlf_read_populations(self.h, _dp(f)), "mlf_read_populations")
         return f
 
     def set_populations(self, f):
         f = _f64(f)
-        assert f.shape == (self.n, 9, self.ny, self.nx)
+        assert f.shape == (self.n, self.nq, self.ny, self.nx)
         self._check(self.lib.mlf_write_populations(self.h, _dp(f)), "mlf_write_populations")
 
     def save(self) -> bytes:

@@ -39,7 +39,8 @@ def test_params_struct_layout_matches_header():
     assert p.tau.offset == 16 and p.hstar.offset == 24
     assert p.gamma.offset == 40 and p.mu.offset == 72 and p.slip.offset == 104
     assert p.spread.offset == 136 and p.check_every.offset == 216
-    assert C.sizeof(p) == 224
+    assert p.allow_unstable.offset == 220 and p.lattice.offset == 224
+    assert C.sizeof(p) == 232
 
 
 def _tension_table(n, rng):
@@ -223,3 +224,27 @@ def test_single_layer_slip_closed_form():
         K, _ = mlfilm.friction_matrix([h], [mu], [beta])
         want = -2 * mu * h / (2 * h * h / 3 + 2 * h * beta + beta * beta) / h  # per unit flux q = h U
         assert abs(K[0, 0] - want) <= 1e-13 * abs(want)
+
+
+def test_d1q3_validation_and_sizes():
+    film = inputs.film_params(2, 100, 1, gamma=[0.01, 0.01], mu=[0.01, 0.01], hstar=0.3)
+    q9 = mlfilm.make_params(film, "f64")
+    q3 = mlfilm.make_params(film, "f64", lattice="d1q3")
+    b9, _ = mlfilm.query_sizes(q9)
+    b3, _ = mlfilm.query_sizes(q3)
+    assert b9 == 3 * b3 == 9 * mlfilm.query_pitch(q3) * 2 * 8   # three planes instead of nine
+    for prec in ("f16", "bf16", "f16mix", "bf16mix"):
+        with pytest.raises(mlfilm.MlfError) as e:
+            mlfilm.query_sizes(mlfilm.make_params(film, prec, lattice="d1q3"))
+        assert e.value.status == "EUNSUPPORTED"
+    two_rows = inputs.film_params(2, 100, 2, gamma=[0.01, 0.01], mu=[0.01, 0.01], hstar=0.3)
+    with pytest.raises(mlfilm.MlfError) as e:
+        mlfilm.query_sizes(mlfilm.make_params(two_rows, "f64", lattice="d1q3"))
+    assert e.value.status == "EINVAL"
+    q3.lattice = 7
+    with pytest.raises(mlfilm.MlfError) as e:
+        mlfilm.query_sizes(q3)
+    assert e.value.status == "EINVAL"
+    with pytest.raises(mlfilm.MlfError) as e:
+        mlfilm.batch_query_sizes([mlfilm.make_params(film, "f64", lattice="d1q3")])
+    assert e.value.status == "EUNSUPPORTED"
