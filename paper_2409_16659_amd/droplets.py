@@ -121,7 +121,8 @@ def fit_arc(d, lo=2.0, hi=60.0, step=0.05):
 
 def sweep(cases, steps=250_000, precision="f32", graph_steps=1000, launch=(64, 1, 0)):
     """Relax every case (kind, expected angle, initial angle) in one batch
-    and fit the results.  Returns one dict per case and face."""
+    and fit the results.  Returns one dict per case and face (with the final
+    heights [N][nx] of the case)."""
     films = [drop(k, th, th0) for k, th, th0 in cases]
     b = mlfilm.Batch([f for f, _ in films], precision)
     b.set_launch(*launch)
@@ -137,7 +138,8 @@ def sweep(cases, steps=250_000, precision="f32", graph_steps=1000, launch=(64, 1
             ang, e_best, err = fit_arc(d)
             rows.append({"kind": kind, "face": face, "expected": th, "start": th0, "measured": ang,
                          "model": model_angle(th), "fit_error": e_best,
-                         "error_at_expected": err(math.radians(th)), "max_speed": float(np.abs(ux).max())})
+                         "error_at_expected": err(math.radians(th)), "max_speed": float(np.abs(ux).max()),
+                         "case": i, "heights": h[:, 0, :]})
     return rows
 
 

@@ -1,0 +1,94 @@
+"""Droplet relaxation sweep (Sec. IV.B, Fig. relax) on the batched GPU path.
+
+Every drop kind and expected angle starts at the angle, twice it (at most
+45 degrees) and half of it, all 32 films in one batch for 2.5e5 steps.
+Measured with the paper's arc fit.  Gates (the paper reports best-fit
+errors below 2 %, errors at the expected angle below 15 % and often below
+6 %, and some hysteresis when a drop starts away from its angle):
+
+* sessile, type-1 and type-3 drops: E(expected) < 8 % from every start;
+  started at the expected angle, measured within 5 % of it and E < 3 %;
+* lenses (strong hysteresis, as the paper also finds): at 10 degrees
+  E < 7 % from every start; at 20 degrees started there E < 10 %;
+* every drop at rest (|U| < 1e-4);
+* one sessile drop against the FP64 oracle (FP64 batch 1e-10, FP32 1e-3).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def rows(torch_cuda):
+    from paper_2409_16659_amd import droplets, mlfilm
+
+    mlfilm.load_library()
+    cases = droplets.paper_cases(thetas=(10.0, 20.0, 30.0), kinds=("sessile", "type1", "type3"))
+    cases += [("lens", 10.0, s) for s in (10.0, 20.0, 5.0)] + [("lens", 20.0, 20.0)]
+    out = droplets.sweep(cases, steps=250_000)
+    for r in out:
+        print(f"{r['kind']:8s} {r['face']:6s} theta {r['expected']:4.1f} start {r['start']:4.1f}: "
+              f"measured {r['measured']:5.2f} fit {r['fit_error']:.3f} E(theta) {r['error_at_expected']:.3f}",
+              flush=True)
+    return out
+
+
+def test_sessile_and_two_liquid_drops(rows):
+    for r in rows:
+        if r["kind"] == "lens":
+            continue
+        assert r["error_at_expected"] < 0.08, r
+        if r["start"] == r["expected"]:
+            assert abs(r["measured"] - r["expected"]) <= 0.05 * r["expected"], r
+            assert r["error_at_expected"] < 0.03, r
+
+
+def test_lenses(rows):
+    for r in rows:
+        if r["kind"] != "lens":
+            continue
+        if r["expected"] == 10.0:
+            assert r["error_at_expected"] < 0.07, r
+            assert abs(r["measured"] - 10.0) <= 0.5, r
+        else:
+            assert r["error_at_expected"] < 0.10, r
+
+
+def test_drops_at_rest(rows):
+    assert max(r["max_speed"] for r in rows) < 1e-4
+
+
+def test_sessile_drop_against_oracle(rows, oracle_mod):
+    """A sessile drop (20 degrees, started at 40) after 2.5e5 steps: the
+    same case run as an FP64 batch matches the FP64 oracle to 1e-10; the
+    FP32 film of the sweep, whose last creep falls below FP32 resolution
+    of the stored deviations, is within 1e-3 and 0.2 degrees of it."""
+    from paper_2409_16659_amd import droplets
+
+    case = ("sessile", 20.0, 40.0)
+    film, h0 = droplets.drop(*case)
+    o = oracle_mod.Oracle(film)
+    o.init(h0)
+    o.step(250_000)
+    ho = o.read()[0][:, 0, :]
+    r64 = droplets.sweep([case], steps=250_000, precision="f64")[0]
+    e64 = float(np.abs(r64["heights"] - ho).max() / np.abs(ho).max())
+    r32 = next(r for r in rows if (r["kind"], r["expected"], r["start"]) == case)
+    e32 = float(np.abs(r32["heights"] - ho).max() / np.abs(ho).max())
+    ang_o = droplets.fit_arc(ho[0] - np.median(np.concatenate([ho[0, :8], ho[0, -8:]])))[0]
+    print(f"sessile 20/40 vs FP64 oracle: FP64 batch e_h={e64:.2e}, FP32 batch e_h={e32:.2e}; "
+          f"angles oracle {ang_o:.2f} FP64 {r64['measured']:.2f} FP32 {r32['measured']:.2f}", flush=True)
+    assert e64 < 1e-10 and r64["measured"] == ang_o
+    assert e32 < 1e-3 and abs(r32["measured"] - ang_o) <= 0.2
