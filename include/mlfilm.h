@@ -192,10 +192,11 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
 /* Autotuner: times candidate launch shapes on the current state and keeps
  * the fastest (written to block_w / seg_h if not NULL).  Each candidate is
  * launched `reps` times (>= 1) from the current population buffer into the
- * other one without swapping, so the state and step counter are unchanged.
- * Candidates: block_w in {64, 128, 192, 256} and segment heights from a
- * fixed list plus those that fill whole dispatch rounds of the device.
- * Synchronises. */
+ * other one without swapping, so the state and step counter are unchanged;
+ * the four fastest are then re-timed twice with 4 x reps launches each and
+ * the smallest time wins.  Candidates: block_w in {64, 128, 192, 256} and
+ * segment heights from a fixed list plus those that fill whole dispatch
+ * rounds of the device.  Synchronises. */
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h);
 
 /* Capture `steps` (even, > 0) consecutive step launches into a HIP graph
