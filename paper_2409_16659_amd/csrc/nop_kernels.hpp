@@ -27,6 +27,21 @@ typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
 __device__ inline int pwrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// tanh-form GELU and, if dg is given, its derivative
+__device__ inline float gelu_f(float a, float* dg) {
+  const float k0 = 0.7978845608028654f, k1 = 0.044715f;
+  const float u = k0 * (a + k1 * a * a * a);
+  const float th = tanhf(u);
+  if (dg) *dg = 0.5f * (1.f + th) + 0.5f * a * (1.f - th * th) * k0 * (1.f + 3.f * k1 * a * a);
+  return 0.5f * a * (1.f + th);
+}
+
+// Epilogues of the forward convolution: v = products + bias, then
+//  kEpiPlain: out = v;
+//  kEpiGelu:  out = v (pre-activation, FP32), outb = bf16(gelu(v));
+//  kEpiResid: out = res + v, outb = bf16(out)  (residual block output).
+enum { kEpiPlain = 0, kEpiGelu = 1, kEpiResid = 2 };
+
 __device__ inline bf16x8 ld8(const __bf16* p) {
   const u32x4v w = *reinterpret_cast<const u32x4v*>(p);
   return __builtin_bit_cast(bf16x8, w);
@@ -34,23 +49,34 @@ __device__ inline bf16x8 ld8(const __bf16* p) {
 
 // ---- 3x3 periodic convolution, forward (also used for the input gradient)
 // out[b, y, x, co] = bias[co] + sum_{o, ci} W[o][co][ci] in[b, y+dy, x+dx, ci]
-// One workgroup = 4 waves = 4 rows of 64 pixels of one image; each wave
-// computes 64 pixels x C output channels (C / 16 column tiles).  Requires
-// gx == 64 * XT (XT >= 1 tiles of 64 pixels per row handled by the grid),
-// C % 32 == 0, C <= 256.
-template <int C>
-__global__ void __launch_bounds__(256) conv3x3_fwd(const __bf16* __restrict__ in, const __bf16* __restrict__ w,
-                                                    const float* __restrict__ bias, float* __restrict__ out, int gy,
-                                                    int gx) {
-  constexpr int NT = C / 16;  // column (output channel) tiles per wave
+// A workgroup of WAVES waves covers WAVES rows of 64 pixels of one image and
+// CO of the C output channels (channel group blockIdx.y); each wave computes
+// 64 pixels x CO channels (CO / 16 column tiles).  The weights of one offset
+// o for the group's channels are staged in LDS (row stride C + 8 bf16,
+// which spreads the 16 rows a wave reads over the banks) and shared by the
+// waves; the next offset's weights are fetched into registers while the
+// current offset's products run (double buffer, one barrier per offset).
+// Input fragments come straight from global memory as 16-byte loads that
+// match the MFMA lane layout.  The per-lane accumulation order (offsets,
+// then 32-channel steps) is fixed, so every launch shape gives the same
+// bits.  Requires gx % 64 == 0, gy % WAVES == 0, C % 32 == 0, CO | C.
+template <int C, int CO, int WAVES, int EPI>
+__global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restrict__ in,
+                                                           const __bf16* __restrict__ w,
+                                                           const float* __restrict__ bias, float* __restrict__ out,
+                                                           const float* __restrict__ res, __bf16* __restrict__ outb,
+                                                           int gy, int gx) {
+  constexpr int NT = CO / 16, KS = C + 8, NTH = 64 * WAVES;
+  constexpr int PER = (CO * C / 8 + NTH - 1) / NTH;  // 16-byte pieces of one offset per thread
+  __shared__ __bf16 sw[2][CO * KS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int xtiles = gx / 64;
-  const int blk = blockIdx.x;
-  const int xt = blk % xtiles;
-  const int rowblk = blk / xtiles;  // (b, 4-row group)
-  const int rows_per_img = gy / 4;
+  const int xt = blockIdx.x % xtiles;
+  const int rowblk = blockIdx.x / xtiles;  // (b, group of WAVES rows)
+  const int rows_per_img = gy / WAVES;
   const int b = rowblk / rows_per_img;
-  const int y = (rowblk % rows_per_img) * 4 + wave;
+  const int y = (rowblk % rows_per_img) * WAVES + wave;
+  const int cg = blockIdx.y;
   const int r = lane & 15, g = lane >> 4;
   f32x4 acc[4][NT];
 #pragma unroll
@@ -58,12 +84,31 @@ __global__ void __launch_bounds__(256) conv3x3_fwd(const __bf16* __restrict__ in
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* img = in + (long long)b * gy * gx * C;
+  u32x4v stage[PER];
+  auto fetch = [&](int o) {
+    const __bf16* wo = w + ((long long)o * C + cg * CO) * C;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < CO * C / 8) stage[j] = *reinterpret_cast<const u32x4v*>(wo + (long long)(t / (C / 8)) * C + (t % (C / 8)) * 8);
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < CO * C / 8) *reinterpret_cast<u32x4v*>(&sw[buf][(t / (C / 8)) * KS + (t % (C / 8)) * 8]) = stage[j];
+    }
+  };
+  fetch(0);
+  put(0);
+  __syncthreads();
   for (int o = 0; o < 9; ++o) {
+    if (o + 1 < 9) fetch(o + 1);
     const int dy = o / 3 - 1, dx = o % 3 - 1;
-    const int yy = pwrap(y + dy, gy);
-    const __bf16* rowp = img + (long long)yy * gx * C;
-    const __bf16* wo = w + (long long)o * C * C;
-#pragma unroll 1
+    const __bf16* rowp = img + (long long)pwrap(y + dy, gy) * gx * C;
+    const __bf16* swo = sw[o & 1];
+#pragma unroll
     for (int c0 = 0; c0 < C; c0 += 32) {
       bf16x8 a[4], bb[NT];
 #pragma unroll
@@ -72,22 +117,37 @@ __global__ void __launch_bounds__(256) conv3x3_fwd(const __bf16* __restrict__ in
         a[m] = ld8(rowp + (long long)xx * C + c0 + 8 * g);
       }
 #pragma unroll
-      for (int n = 0; n < NT; ++n) bb[n] = ld8(wo + (long long)(16 * n + r) * C + c0 + 8 * g);
+      for (int n = 0; n < NT; ++n) bb[n] = ld8(swo + (16 * n + r) * KS + c0 + 8 * g);
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
     }
+    if (o + 1 < 9) put((o + 1) & 1);  // the other buffer: last read before the previous barrier
+    __syncthreads();
   }
-  float* orow = out + (((long long)b * gy + y) * gx + xt * 64) * C;
+  const long long base = (((long long)b * gy + y) * gx + xt * 64) * C;
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
-      const int co = 16 * n + r;
+      const int co = cg * CO + 16 * n + r;
       const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) orow[(long long)(16 * m + 4 * g + i) * C + co] = acc[m][n][i] + bv;
+      for (int i = 0; i < 4; ++i) {
+        const long long e = base + (long long)(16 * m + 4 * g + i) * C + co;
+        const float v = acc[m][n][i] + bv;
+        if constexpr (EPI == kEpiPlain) {
+          out[e] = v;
+        } else if constexpr (EPI == kEpiGelu) {
+          out[e] = v;
+          outb[e] = (__bf16)gelu_f(v, nullptr);
+        } else {
+          const float s = res[e] + v;
+          out[e] = s;
+          outb[e] = (__bf16)s;
+        }
+      }
     }
 }
 
