@@ -410,12 +410,22 @@ __global__ void __launch_bounds__(256) field_partials(const double* __restrict__
 }
 
 // Final fixed-order sum of the partials; one thread per layer.
-__global__ void finish_partials(const double* __restrict__ part, double* __restrict__ out, int nblocks, int nl) {
-  const int i = threadIdx.x;
-  if (i < nl) {
+// out[i] = sum over nblocks partials of layer i: each of the 256 threads
+// sums a strided subset in order, then a tree in LDS (a fixed order).
+__global__ void __launch_bounds__(256) finish_partials(const double* __restrict__ part, double* __restrict__ out,
+                                                       int nblocks, int nl) {
+  __shared__ double red[256];
+  for (int i = 0; i < nl; ++i) {
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[b * kMaxLayers + i];
-    out[i] = s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += part[b * kMaxLayers + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
+    __syncthreads();
   }
 }
 
@@ -1161,7 +1171,7 @@ mlf_status mlf_init_device(mlf_handle* h, const double* hgt, const double* ux, c
   h->initialised = false;
   hipLaunchKernelGGL(field_partials, dim3(kRedBlocks), dim3(256), 0, h->stream, hgt, part_ptr(h), nn, p.n_layers);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
+  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(256), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
                      p.n_layers);
   HIPCHK(hipGetLastError());
   double sums[kMaxLayers];
@@ -1314,7 +1324,7 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
                        h->pitch, p.n_layers, L);
   });
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
+  hipLaunchKernelGGL(finish_partials, dim3(1), dim3(256), 0, h->stream, part_ptr(h), redout_ptr(h), kRedBlocks,
                      p.n_layers);
   HIPCHK(hipGetLastError());
   double dev[kMaxLayers];
@@ -1855,7 +1865,7 @@ mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
     hipLaunchKernelGGL(field_partials, dim3(kRedBlocks), dim3(256), 0, b->stream, hgts[f], part_ptr(h), nn,
                        h->p.n_layers);
     BHIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(finish_partials, dim3(1), dim3(64), 0, b->stream, part_ptr(h), sums + (size_t)f * kMaxLayers,
+    hipLaunchKernelGGL(finish_partials, dim3(1), dim3(256), 0, b->stream, part_ptr(h), sums + (size_t)f * kMaxLayers,
                        kRedBlocks, h->p.n_layers);
     BHIPCHK(hipGetLastError());
   }
