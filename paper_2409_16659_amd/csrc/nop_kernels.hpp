@@ -154,15 +154,22 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
 // ---- 3x3 periodic convolution, weight gradient ----------------------------
 // part[b][o][co][ci] = sum_{y, x} dy[b, y, x, co] in[b, y+dy_o, x+dx_o, ci]
 // One workgroup per (image b, offset o); it marches the image in chunks of
-// 32 pixels of one row, staging dY and the shifted input transposed in LDS
-// ([channel][pixel]) so that 8 consecutive pixels are one 16-byte read.
-// The C x C result is split over 4 waves by output-channel row tiles.
+// 64 pixels of one row.  Each chunk of dY and of the shifted input is staged
+// transposed in LDS ([channel][pixel], stride 72 so that 8 consecutive
+// pixels are one 16-byte read): a thread loads 4 consecutive pixels x 8
+// channels of each tensor and writes 8-byte runs (4 pixels of one channel).
+// The next chunk's loads are issued before this chunk's products.  The
+// C x C result is split over 4 waves by output-channel row tiles; pixels
+// are accumulated in order (32 per MFMA step).  Requires gx % 64 == 0.
 template <int C>
 __global__ void __launch_bounds__(256) conv3x3_wgrad(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
                                                       float* __restrict__ part, int gy, int gx) {
+  constexpr int CH = 64;              // pixels per chunk
   constexpr int NT = C / 16;          // tiles per dimension
   constexpr int RT = NT / 4;          // row tiles per wave (C / 64)
-  constexpr int KP = 32 + 8;          // padded pixel stride of an LDS row (bf16)
+  constexpr int KP = CH + 8;          // padded pixel stride of an LDS row (bf16)
+  constexpr int PER = ((CH / 4) * (C / 8) + 255) / 256;  // staging pieces per thread
+  typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
   __shared__ __bf16 sd[C * KP];       // dY chunk, [co][px]
   __shared__ __bf16 sx[C * KP];       // input chunk, [ci][px]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -176,32 +183,57 @@ __global__ void __launch_bounds__(256) conv3x3_wgrad(const __bf16* __restrict__ 
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* dimg = dout + (long long)b * gy * gx * C;
   const __bf16* ximg = in + (long long)b * gy * gx * C;
-  const int chunks_per_row = gx / 32;
-  for (int ch = 0; ch < gy * chunks_per_row; ++ch) {
-    const int y = ch / chunks_per_row, x0 = (ch % chunks_per_row) * 32;
+  const int chunks_per_row = gx / CH, nch = gy * chunks_per_row;
+  bf16x8 vd[PER][4], vx[PER][4];
+  auto fetch = [&](int ch) {
+    const int y = ch / chunks_per_row, x0 = (ch % chunks_per_row) * CH;
     const int ys = pwrap(y + dy, gy);
-    // stage: 32 pixels x C channels of each tensor, 8 channels per thread-load
-    for (int t = threadIdx.x; t < 32 * (C / 8); t += 256) {
-      const int px = t / (C / 8), c8 = (t % (C / 8)) * 8;
-      const bf16x8 vd = ld8(dimg + ((long long)y * gx + x0 + px) * C + c8);
-      const int xs = pwrap(x0 + px + dx, gx);
-      const bf16x8 vx = ld8(ximg + ((long long)ys * gx + xs) * C + c8);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        sd[(c8 + j) * KP + px] = vd[j];
-        sx[(c8 + j) * KP + px] = vx[j];
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + 256 * j;
+      if (t < (CH / 4) * (C / 8)) {
+        const int p4 = (t / (C / 8)) * 4, c8 = (t % (C / 8)) * 8;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          vd[j][q] = ld8(dimg + ((long long)y * gx + x0 + p4 + q) * C + c8);
+          vx[j][q] = ld8(ximg + ((long long)ys * gx + pwrap(x0 + p4 + q + dx, gx)) * C + c8);
+        }
       }
     }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + 256 * j;
+      if (t < (CH / 4) * (C / 8)) {
+        const int p4 = (t / (C / 8)) * 4, c8 = (t % (C / 8)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 a4[4] = {vd[j][0][e], vd[j][1][e], vd[j][2][e], vd[j][3][e]};
+          __bf16 b4[4] = {vx[j][0][e], vx[j][1][e], vx[j][2][e], vx[j][3][e]};
+          *reinterpret_cast<u32x2v*>(sd + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, a4);
+          *reinterpret_cast<u32x2v*>(sx + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, b4);
+        }
+      }
+    }
+  };
+  fetch(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    put();
     __syncthreads();
-    bf16x8 a[RT], bb[NT];
+    if (ch + 1 < nch) fetch(ch + 1);
 #pragma unroll
-    for (int m = 0; m < RT; ++m) a[m] = ld8(sd + (16 * (wave * RT + m) + r) * KP + 8 * g);
+    for (int k0 = 0; k0 < CH; k0 += 32) {
+      bf16x8 a[RT], bb[NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) bb[n] = ld8(sx + (16 * n + r) * KP + 8 * g);
+      for (int m = 0; m < RT; ++m) a[m] = ld8(sd + (16 * (wave * RT + m) + r) * KP + k0 + 8 * g);
 #pragma unroll
-    for (int m = 0; m < RT; ++m)
+      for (int n = 0; n < NT; ++n) bb[n] = ld8(sx + (16 * n + r) * KP + k0 + 8 * g);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+      for (int m = 0; m < RT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+    }
     __syncthreads();
   }
   float* pb = part + ((long long)b * 9 + o) * C * C;
