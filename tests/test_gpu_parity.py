@@ -182,11 +182,41 @@ def test_fp32_three_layer_crop(mlf, oracle_mod):
     assert np.abs(m_g - m_o).max() <= 1e-9 * m_o.max()
 
 
+def bench_launch():
+    """The launch shape the benchmark times for the 3-layer 1024^2 FP32
+    workload (the autotuner's choice recorded with the profiles)."""
+    import bench
+
+    return bench.profiled_launch("film3_2d_1024", "f32") or (192, 8)
+
+
 def test_fp32_three_layer_full_size(mlf, oracle_mod):
-    """Full 1024x1024 3-layer workload in the benchmark's launch shape."""
+    """Full 1024x1024 3-layer workload in the benchmark's launch shape,
+    against the oracle over 20 steps."""
     film, h0, _ = inputs.workload("film3_2d_1024")
-    g, o = run_pair(mlf, oracle_mod, film, h0, 20, "f32")
+    g, o = run_pair(mlf, oracle_mod, film, h0, 20, "f32", launch=bench_launch())
     check(g, o, 1e-5, 1e-4)
+
+
+def test_fp32_full_size_parity_horizon(mlf):
+    """The FP32 bar over the workload's first 10^4 steps at full size, in the
+    benchmark's launch shape: against the FP64 path (pinned to the oracle to
+    1e-12 above), e_h <= 1e-5 and e_U <= 1e-4; per-layer mass of the FP32
+    run within 1e-9 (the oracle at this size and length takes ~15 minutes
+    on 16 cores)."""
+    film, h0, _ = inputs.workload("film3_2d_1024")
+    launch = bench_launch()
+    say(f"case film3_2d_1024 f32 vs f64, 10^4 steps, launch {launch}")
+    a = mlf.Film(film, "f32")
+    a.set_launch(*launch)
+    b = mlf.Film(film, "f64")
+    for g in (a, b):
+        g.init(h0)
+    m0 = b.mass()
+    a.step(10_000)
+    b.step(10_000)
+    check(a, b, 1e-5, 1e-4)
+    assert np.abs(a.mass() - m0).max() <= 1e-9 * m0.max()
 
 
 # ------------------------------------------------------------ properties --
