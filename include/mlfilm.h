@@ -224,8 +224,12 @@ typedef struct mlf_batch mlf_batch;
 
 /* Sizes of each of the two population buffers (the films' buffers back to
  * back, 256-byte aligned) and of the scratch buffer.  EINVAL / EUNSUPPORTED
- * as mlf_query_sizes, also for films that do not share precision, tau and
- * exponents, or n outside 1..4096. */
+ * as mlf_query_sizes, also for films that do not share precision, tau,
+ * exponents and lattice, or n outside 1..4096.  A D1Q3 batch holds films
+ * that each fit one workgroup's LDS (as for the resident single-film
+ * kernel; else EUNSUPPORTED) and advances them one workgroup per film,
+ * many steps per launch; its launch shape is fixed (set_launch values are
+ * kept and ignored, autotune returns them). */
 mlf_status mlf_batch_query_sizes(const mlf_params* films, int32_t n, size_t* pop_bytes, size_t* scratch_bytes);
 
 /* Bind n films to caller-owned buffers (sizes from mlf_batch_query_sizes,
@@ -252,7 +256,8 @@ mlf_status mlf_batch_step(mlf_batch* b, int64_t nsteps);
 
 /* Capture `steps` (even, > 0) consecutive batch launches into a HIP graph
  * that mlf_batch_step replays; 0 drops the graph.  Changing the launch
- * shape drops it too.  EUNSUPPORTED on the default stream. */
+ * shape drops it too.  EUNSUPPORTED on the default stream and for D1Q3
+ * batches. */
 mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps);
 
 /* Read-back and FP64 per-layer mass of one film, as mlf_read and

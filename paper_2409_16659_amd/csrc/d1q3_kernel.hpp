@@ -23,6 +23,9 @@
 //    three barriers per step and no global traffic between the first load
 //    and the last store.  Pseudo-1D films are tiny (10^2..10^3 nodes), so a
 //    launch per step would cost far more than the step.
+//  * d1q3_resident_batch: the same for many films at once, one workgroup
+//    per film (the droplet sweeps of the paper's Sec. IV.B are batches of
+//    such strips).
 //  * d1q3_step: one step per launch for films too large for one
 //    workgroup's LDS; a workgroup of 256 lanes covers 252 nodes plus two
 //    halo nodes on each side.
@@ -217,8 +220,7 @@ __host__ __device__ constexpr size_t d1_resident_lds(int nx, int nl) {
 // `steps` steps of one film held in LDS: src -> (LDS) -> dst.  Lane t owns
 // nodes t and t + blockDim (nx <= 2 blockDim; blockDim a multiple of 64).
 template <typename C, int NL, bool TAU1, int EA, int EB>
-__global__ void __launch_bounds__(kD1Threads) d1q3_resident(const C* __restrict__ src, C* __restrict__ dst,
-                                                            StepConsts<C> kc, int steps) {
+__device__ void d1_resident_run(const C* __restrict__ src, C* __restrict__ dst, const StepConsts<C>& kc, int steps) {
   extern __shared__ unsigned char smem_raw[];
   const int nx = kc.nx;
   C* sf = reinterpret_cast<C*>(smem_raw);  // [3][nx][NL]
@@ -288,6 +290,32 @@ __global__ void __launch_bounds__(kD1Threads) d1q3_resident(const C* __restrict_
 #pragma unroll
     for (int k = 0; k < 3; ++k) dst[k * plane * NL + e] = sf[k * nx * NL + e];
   if (bad) kc.flag[0] = bad;
+}
+
+template <typename C, int NL, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(kD1Threads) d1q3_resident(const C* __restrict__ src, C* __restrict__ dst,
+                                                            StepConsts<C> kc, int steps) {
+  d1_resident_run<C, NL, TAU1, EA, EB>(src, dst, kc, steps);
+}
+
+// A batch of D1Q3 films, one workgroup per film (its constants, byte offset
+// and layer count in the batch table), each held in LDS for `steps` steps;
+// flip selects the source buffer (0: a -> b, 1: b -> a).  The workgroup is
+// sized for the longest film and the dynamic LDS for the largest one.
+template <typename C, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(kD1Threads) d1q3_resident_batch(const BatchFilm<C>* __restrict__ films,
+                                                                  unsigned char* __restrict__ buf_a,
+                                                                  unsigned char* __restrict__ buf_b, int flip,
+                                                                  int steps) {
+  const BatchFilm<C>& bf = films[blockIdx.x];
+  const C* src = reinterpret_cast<const C*>((flip ? buf_b : buf_a) + bf.offset);
+  C* dst = reinterpret_cast<C*>((flip ? buf_a : buf_b) + bf.offset);
+  switch (bf.nl) {
+    case 1: d1_resident_run<C, 1, TAU1, EA, EB>(src, dst, bf.kc, steps); break;
+    case 2: d1_resident_run<C, 2, TAU1, EA, EB>(src, dst, bf.kc, steps); break;
+    case 3: d1_resident_run<C, 3, TAU1, EA, EB>(src, dst, bf.kc, steps); break;
+    default: d1_resident_run<C, 4, TAU1, EA, EB>(src, dst, bf.kc, steps); break;
+  }
 }
 
 // One step for a film of any length: workgroup b covers nodes

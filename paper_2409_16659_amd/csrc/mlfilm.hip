@@ -476,6 +476,8 @@ struct MinFilm {
   long long offset;  // bytes into the population buffer
   long long plane;   // nodes per plane (ny * pitch)
   int nx, ny, pitch, nl;
+  int nq;            // directions (9 or 3)
+  int pad;
   Layers L;
 };
 
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(256) batch_min_partials(const MinFilm* __restr
                                                           unsigned char* __restrict__ buf,
                                                           double* __restrict__ part) {
   const MinFilm m = films[blockIdx.y];
-  const PopView<R, S> f{buf + m.offset, m.plane, m.nl, kQ};  // batches hold D2Q9 films
+  const PopView<R, S> f{buf + m.offset, m.plane, m.nl, m.nq};
   block_min(f, m.nx, m.ny, m.pitch, m.nl, m.L, blockIdx.x * (long long)blockDim.x + threadIdx.x,
             (long long)gridDim.x * blockDim.x, part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kMaxLayers);
 }
@@ -1591,8 +1593,12 @@ mlf_status validate_batch(const mlf_params* films, int n, std::string* why) {
   for (int f = 0; f < n; ++f) {
     mlf_status st = validate(&films[f], why);
     if (st != MLF_OK) return st;
-    if (films[f].lattice != MLF_D2Q9) {
-      if (why) *why = "batches hold D2Q9 films";
+    if (films[f].lattice != films[0].lattice) {
+      if (why) *why = "films of a batch share the lattice";
+      return MLF_EUNSUPPORTED;
+    }
+    if (films[f].lattice == MLF_D1Q3 && !d1_resident(films[f])) {
+      if (why) *why = "batched D1Q3 films must fit one workgroup's LDS (nx <= 1024, 5 N nx values <= 64 KiB)";
       return MLF_EUNSUPPORTED;
     }
     if (films[f].precision != films[0].precision || films[f].tau != films[0].tau ||
@@ -1702,6 +1708,35 @@ hipError_t launch_batch_sc(const mlf_batch* b, int flip, int* occ) {
 }
 
 // One step of every film from buffer `flip` into the other one.
+// D1Q3 batch: one workgroup per film, `steps` steps held in LDS.
+template <typename C, bool T1, int EA, int EB>
+hipError_t d1_batch_launch_t(const mlf_batch* b, int steps) {
+  size_t lds = 0;
+  int threads = 64;
+  for (const mlf_handle* h : b->film) {
+    lds = std::max(lds, mlf::d1_resident_lds<C>(h->p.nx, h->p.n_layers));
+    threads = std::max(threads, d1_threads(h->p.nx));
+  }
+  hipLaunchKernelGGL((mlf::d1q3_resident_batch<C, T1, EA, EB>), dim3((unsigned)b->n), dim3((unsigned)threads), lds,
+                     b->stream, reinterpret_cast<const mlf::BatchFilm<C>*>(b->scratch + kBatchTableOff), b->pop[0],
+                     b->pop[1], b->cur, steps);
+  return hipGetLastError();
+}
+
+template <typename C>
+hipError_t d1_batch_launch_c(const mlf_batch* b, int steps) {
+  const bool t1 = b->p0.tau == 1.0;
+  const bool e93 = b->p0.exp_a == 9 && b->p0.exp_b == 3;
+  if (t1 && e93) return d1_batch_launch_t<C, true, 9, 3>(b, steps);
+  if (t1) return d1_batch_launch_t<C, true, 0, 0>(b, steps);
+  if (e93) return d1_batch_launch_t<C, false, 9, 3>(b, steps);
+  return d1_batch_launch_t<C, false, 0, 0>(b, steps);
+}
+
+hipError_t d1_batch_launch(const mlf_batch* b, int steps) {
+  return b->p0.precision == MLF_F64 ? d1_batch_launch_c<double>(b, steps) : d1_batch_launch_c<float>(b, steps);
+}
+
 hipError_t launch_batch(const mlf_batch* b, int flip) {
   hipError_t e = hipSuccess;
   by_storage(b->film[0], [&](auto* rt, auto* st) {
@@ -1921,6 +1956,16 @@ mlf_status mlf_batch_step(mlf_batch* b, int64_t nsteps) {
   mlf_status st = batch_ready(b);
   if (st != MLF_OK) return st;
   b->failed = -1;
+  if (b->p0.lattice == MLF_D1Q3) {
+    for (int64_t left = nsteps; left > 0;) {
+      const int chunk = (int)std::min<int64_t>(left, kD1MaxStepsPerLaunch);
+      BHIPCHK(d1_batch_launch(b, chunk));
+      b->cur ^= 1;
+      left -= chunk;
+      b->steps += chunk;
+    }
+    return batch_guard(b);
+  }
   int64_t left = nsteps;
   while (left > 0) {
     if (b->graph && b->cur == b->graph_parity && left >= b->graph_steps) {
@@ -1942,6 +1987,8 @@ mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps) {
   drop_graph(b);
   if (steps == 0) return MLF_OK;
   if (steps < 0 || steps % 2 != 0) return bfail(b, MLF_EINVAL, "graph steps must be even and >= 0");
+  if (b->p0.lattice == MLF_D1Q3)
+    return bfail(b, MLF_EUNSUPPORTED, "D1Q3 batches run many steps per launch; no graph needed");
   if (!b->stream) return bfail(b, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
   mlf_status st = batch_ready(b);
   if (st != MLF_OK) return st;
@@ -2011,8 +2058,8 @@ mlf_status mlf_batch_layer_min_all(mlf_batch* b, double* hmin) {
   std::vector<MinFilm> tab(b->n);
   for (int f = 0; f < b->n; ++f) {
     const mlf_handle* h = b->film[f];
-    tab[f] = MinFilm{(long long)b->offset[f], (long long)h->plane, h->p.nx, h->p.ny, h->pitch, h->p.n_layers,
-                     layers_of(h)};
+    tab[f] = MinFilm{(long long)b->offset[f], (long long)h->plane, h->p.nx,    h->p.ny,
+                     h->pitch,                 h->p.n_layers,          nq_of(&h->p), 0, layers_of(h)};
   }
   MinFilm* dtab = reinterpret_cast<MinFilm*>(b->scratch + kBatchMinTabOff);
   double* part = reinterpret_cast<double*>(b->scratch + kBatchMinPartOff);
@@ -2095,6 +2142,12 @@ mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int3
   if (!b || reps < 1) return MLF_EINVAL;
   mlf_status st = batch_ready(b);
   if (st != MLF_OK) return st;
+  if (b->p0.lattice == MLF_D1Q3) {  // fixed shape: one workgroup per film
+    if (block_w) *block_w = b->block_w;
+    if (seg_h) *seg_h = b->seg_h;
+    if (persistent) *persistent = b->persistent;
+    return MLF_OK;
+  }
   drop_graph(b);
   const int keep_w = b->block_w, keep_h = b->seg_h, keep_p = b->persistent;
   struct Cand {

@@ -1,8 +1,9 @@
 """Droplet relaxation sweep (Sec. IV.B, Fig. relax) on the batched GPU path.
 
 Every (kind, expected angle, initial angle) is one pseudo-1D film of a
-single batch, so the whole sweep advances with one launch per step (and a
-captured graph of the step loop).  After relaxation the host fits a
+single batch: on D2Q9 the whole sweep advances with one launch per step (a
+captured graph of the step loop), on D1Q3 each film sits in one
+workgroup's LDS for thousands of steps per launch.  After relaxation the host fits a
 circular arc that shares the drop's peak position and height by minimising
 the volume error E(theta) = int |h - H_theta| / int h, as the paper
 measures contact angles, and reports E at the expected angle as well.
@@ -119,16 +120,18 @@ def fit_arc(d, lo=2.0, hi=60.0, step=0.05):
     return math.degrees(grid[i]), float(es[i]), err
 
 
-def sweep(cases, steps=250_000, precision="f32", graph_steps=1000, launch=(64, 1, 0)):
+def sweep(cases, steps=250_000, precision="f32", graph_steps=1000, launch=(64, 1, 0), lattice="d2q9"):
     """Relax every case (kind, expected angle, initial angle) in one batch
     and fit the results.  Returns one dict per case and face (with the final
-    heights [N][nx] of the case)."""
+    heights [N][nx] of the case).  lattice="d1q3" holds every film in one
+    workgroup's LDS for thousands of steps per launch (D2Q9: one launch per
+    step, graph-captured)."""
     films = [drop(k, th, th0) for k, th, th0 in cases]
-    b = mlfilm.Batch([f for f, _ in films], precision)
+    b = mlfilm.Batch([f for f, _ in films], precision, lattice=lattice)
     b.set_launch(*launch)
     for i, (_, h0) in enumerate(films):
         b.init(i, h0)
-    if graph_steps and steps >= graph_steps:
+    if lattice == "d2q9" and graph_steps and steps >= graph_steps:
         b.capture(graph_steps)
     b.step(steps)
     rows = []

@@ -413,13 +413,13 @@ class Batch:
     its own (default-priority) stream so that its step loop can be
     captured into a HIP graph."""
 
-    def __init__(self, films, precision="f32", allow_unstable=False, stream=None, device=None):
+    def __init__(self, films, precision="f32", allow_unstable=False, stream=None, device=None, lattice="d2q9"):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         self.films = [dict(f) for f in films]
-        self.params = [make_params(f, precision, 0, allow_unstable) for f in films]
+        self.params = [make_params(f, precision, 0, allow_unstable, lattice) for f in films]
         self.n = len(films)
         arr = (Params * self.n)(*self.params)
         pop_bytes, scratch_bytes = batch_query_sizes(self.params)

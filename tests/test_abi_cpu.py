@@ -245,6 +245,13 @@ def test_d1q3_validation_and_sizes():
     with pytest.raises(mlfilm.MlfError) as e:
         mlfilm.query_sizes(q3)
     assert e.value.status == "EINVAL"
+    # batches: one lattice per batch; D1Q3 films must fit one workgroup's LDS
+    mlfilm.batch_query_sizes([mlfilm.make_params(film, "f64", lattice="d1q3")] * 3)
     with pytest.raises(mlfilm.MlfError) as e:
-        mlfilm.batch_query_sizes([mlfilm.make_params(film, "f64", lattice="d1q3")])
+        mlfilm.batch_query_sizes([mlfilm.make_params(film, "f64", lattice="d1q3"), mlfilm.make_params(film, "f64")])
+    assert e.value.status == "EUNSUPPORTED"
+    long_strip = inputs.film_params(2, 1100, 1, gamma=[0.01, 0.01], mu=[0.01, 0.01], hstar=0.3)
+    mlfilm.query_sizes(mlfilm.make_params(long_strip, "f64", lattice="d1q3"))  # single film: one-step kernel
+    with pytest.raises(mlfilm.MlfError) as e:
+        mlfilm.batch_query_sizes([mlfilm.make_params(long_strip, "f32", lattice="d1q3")])
     assert e.value.status == "EUNSUPPORTED"

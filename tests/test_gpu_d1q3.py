@@ -180,3 +180,61 @@ def test_guard_and_unsupported(mlf):
     with pytest.raises(mlf.MlfError) as e:
         g.capture(8)
     assert e.value.status == "EUNSUPPORTED"
+
+
+BATCH_STRIPS = [(1, 64), (2, 333), (3, 500), (4, 96), (2, 5), (4, 400), (3, 1)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_matches_single_films(mlf, prec):
+    """A batch of D1Q3 strips (one workgroup per film, each held in LDS)
+    gives every film bit for bit what the single-film resident kernel gives,
+    with the steps split into launches differently."""
+    films = [strip(n, nx, seed=300 + 7 * n + nx) for n, nx in BATCH_STRIPS]
+    b = mlf.Batch([f for f, _ in films], prec, lattice="d1q3")
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    b.step(300)
+    b.step(477)
+    assert b.steps_done == 777
+    mins = b.layer_min_all()
+    for i, (film, h0) in enumerate(films):
+        g = mlf.Film(film, prec, lattice="d1q3")
+        g.init(h0)
+        g.step(777)
+        hb, ub, _ = b.read(i)
+        hs, us, _ = g.read()
+        assert np.array_equal(hb, hs) and np.array_equal(ub, us), i
+        assert np.array_equal(mins[i, :film["n_layers"]], hb.reshape(film["n_layers"], -1).min(axis=1))
+
+
+def test_batch_against_oracle(mlf, oracle_mod):
+    films = [strip(n, nx, seed=400 + n) for n, nx in [(2, 200), (4, 150), (1, 77)]]
+    b = mlf.Batch([f for f, _ in films], "f64", lattice="d1q3")
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    b.step(400)
+    for i, (film, h0) in enumerate(films):
+        o = oracle_mod.Oracle(film, oracle_mod.D1Q3)
+        o.init(h0)
+        o.step(400)
+        hb, ub, _ = b.read(i)
+        ho, uo, _ = o.read()
+        say(f"   batch film {i}: e_h={err(hb, ho):.2e} e_U={err(ub, uo):.2e}")
+        assert err(hb, ho) <= 1e-12 and err(ub, uo) <= 1e-10
+    with pytest.raises(mlf.MlfError) as e:
+        b.capture(8)
+    assert e.value.status == "EUNSUPPORTED"
+
+
+def test_batch_guard_names_the_failing_film(mlf):
+    films = [strip(2, 128, seed=500 + j) for j in range(3)]
+    film, h0 = films[1]
+    films[1] = (dict(film, mu=[3.0, 3.0]), h0)
+    b = mlf.Batch([f for f, _ in films], "f64", lattice="d1q3", allow_unstable=True)
+    for i, (_, h) in enumerate(films):
+        b.init(i, h)
+    with pytest.raises(mlf.MlfError) as e:
+        b.step(2000)
+    assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
+    assert b.failed_film == 1
