@@ -190,7 +190,7 @@ def bench_surrogate(args):
     m.predict(T0[:8].repeat(8, 1, 1, 1).contiguous())
     ms_f, ms_w = m.time_conv(64, reps=20)
     flops = m.conv_flops(64)
-    runs = [S.judged_run(m, test_films, 60000, 40, k, 1e-3) for k in (4, 8, 16)]
+    runs = [S.judged_run(m, test_films, 60000, 40, k, 1e-3, overlap=ov) for ov in (False, True) for k in (4, 8, 16)]
     for r in runs:
         r["judge_errors_max"] = max(r.pop("judge_errors"))
     ok = [r for r in runs if max(r["final_rel_l2"]) <= 1e-3] or runs
@@ -204,7 +204,8 @@ def bench_surrogate(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "surrogate_film3_256", "films": len(test_films), "window": 100,
                    "params": m.param_count, "width": 128, "blocks": 3, "train_pairs": int(X0.shape[0]),
-                   "train_steps": args.train_steps, "judge_every": best["k"], "tol": 1e-3},
+                   "train_steps": args.train_steps, "judge_every": best["k"], "judge_overlap": best["overlap"],
+                   "tol": 1e-3},
         "judged_runs": runs, "held_out": held_out,
         "training_s": t_train, "data_s": t_data,
         "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,

@@ -138,9 +138,16 @@ def test_pipeline_end_to_end(mlf, torch_cuda):
     m.set_params(S.init_params(m, seed=0))
     losses = S.train(m, X0, X1, 20, batch=8, lr=1e-3)
     assert np.all(np.isfinite(losses)) and m_steps(m) == 20
-    r = S.judged_run(m, films[:2], 2000, 6, 3, 1e-3)
-    assert r["accepted_windows"] + r["rejected_windows"] == 6
-    assert len(r["judge_errors"]) == 2 and r["solver_s"] > 0 and r["total_s"] > 0
+    for overlap in (False, True):
+        r = S.judged_run(m, films[:2], 2000, 7, 3, 1e-3, overlap=overlap)
+        assert r["accepted_windows"] + r["rejected_windows"] == 7
+        assert len(r["judge_errors"]) == 3 and r["solver_s"] > 0 and r["total_s"] > 0
+    # a tolerance nothing meets: every block falls back to the solver, and the
+    # result is then the solver's own trajectory
+    for overlap in (False, True):
+        r = S.judged_run(m, films[:2], 2000, 5, 2, 0.0, overlap=overlap)
+        assert r["rejected_windows"] == 5 and r["accepted_windows"] == 0
+        assert max(r["final_rel_l2"]) < 1e-6
 
 
 def m_steps(m):
