@@ -238,3 +238,34 @@ def test_batch_guard_names_the_failing_film(mlf):
         b.step(2000)
     assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
     assert b.failed_film == 1
+
+
+def test_rupture_detection_on_d1q3(mlf, oracle_mod):
+    """Rupture of the four-layer strip on D1Q3: the single film (resident
+    kernel) stops at the oracle's D1Q3 check, and a batch of strips reports
+    for each film the step it gives alone."""
+    films = []
+    for j, amp in enumerate((1e-2, 2e-2, 5e-3)):
+        film = inputs._film4(192, 1)
+        films.append((film, inputs.initial_heights(film, (1.0, 0.8, 0.6, 0.4), "uniform", 11 + j, amp)))
+    film, h0 = films[0]
+    g = mlf.Film(film, "f64", lattice="d1q3")
+    g.init(h0)
+    steps, layer = g.step_until(60_000, 100)
+    o = oracle_mod.Oracle(film, oracle_mod.D1Q3)
+    o.init(h0)
+    thr = mlf.rupture_threshold(film)
+    while o.steps_done < 60_000:
+        o.step(100)
+        if (o.read()[0].reshape(4, -1).min(axis=1) <= thr).any():
+            break
+    say(f"   D1Q3 rupture: GPU {steps} (layer {layer}), oracle {o.steps_done}")
+    assert steps == o.steps_done and layer == 3
+    b = mlf.Batch([f for f, _ in films], "f64", lattice="d1q3")
+    for i, (_, h) in enumerate(films):
+        b.init(i, h)
+    t_hit, lay, _ = b.step_until(60_000, 100)
+    for i, (f, h) in enumerate(films):
+        s = mlf.Film(f, "f64", lattice="d1q3")
+        s.init(h)
+        assert s.step_until(60_000, 100) == (t_hit[i], lay[i]), i
