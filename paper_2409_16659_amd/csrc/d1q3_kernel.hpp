@@ -83,8 +83,9 @@ __device__ inline void d1_pressure(const StepConsts<C>& kc, const C (&zm)[NL], c
       const C rr = kc.khs[kk - 1] * rd;
       C ra, rb;
       pow_ab<EA, EB>(rr, kc, ra, rb);
-      sphi[l] += kc.sa[l][kk - 1] * rb - kc.sb[l][kk - 1] * ra;
-      const C dphi = kc.sab[l][kk - 1] * (ra - rb) * rd;
+      C phi, dphi;
+      wetting<EA, EB>(kc, l, kk, ra, rb, rd, phi, dphi);
+      sphi[l] += phi;
       dup[l] += dphi;
       ddn[l + kk] += dphi * (C(1) + C(0.5) * qq[l]);
     }

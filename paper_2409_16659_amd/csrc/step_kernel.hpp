@@ -283,6 +283,22 @@ __device__ inline void pow_ab(C r, const StepConsts<C>& k, C& ra, C& rb) {
   }
 }
 
+// phi = S_lk phi_k(d) = S (a r^b - b r^a)/(a - b) and
+// phi' = S a b (r^a - r^b)/((a - b) d) of pair (l, k) from r^a, r^b, 1/d.
+// With compile-time exponents only S a/(a - b) is read from the constants
+// (b/a and b are literals): fewer live scalar registers in the row loop.
+template <int EA, int EB, typename C>
+__device__ inline void wetting(const StepConsts<C>& k, int l, int kk, C ra, C rb, C rd, C& phi, C& dphi) {
+  const C s = k.sa[l][kk - 1];
+  if constexpr (EA > 0) {
+    phi = s * (rb - C(double(EB) / double(EA)) * ra);
+    dphi = (s * C(EB)) * (ra - rb) * rd;
+  } else {
+    phi = s * rb - k.sb[l][kk - 1] * ra;
+    dphi = k.sab[l][kk - 1] * (ra - rb) * rd;
+  }
+}
+
 __host__ __device__ inline int wrap(int v, int n) {
   v = v < 0 ? v + n : v;
   v = v >= n ? v - n : v;
@@ -498,9 +514,8 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
           const C rr = kc.khs[kk - 1] * rd;
           C ra, rb;
           pow_ab<EA, EB>(rr, kc, ra, rb);
-          // phi = S (a r^b - b r^a)/(a-b), phi' = S a b (r^a - r^b)/((a-b) d)
-          const C phi = kc.sa[l][kk - 1] * rb - kc.sb[l][kk - 1] * ra;
-          const C dphi = kc.sab[l][kk - 1] * (ra - rb) * rd;
+          C phi, dphi;
+          wetting<EA, EB>(kc, l, kk, ra, rb, rd, phi, dphi);
           sphi[l] += phi;
           dup[l] += dphi;
           ddn[l + kk] += dphi * (C(1) + C(0.5) * qq[l]);
