@@ -79,7 +79,13 @@ def cpu_baseline(film, h0, budget_s: float, lattice="d2q9"):
         if el >= budget_s:
             break
     lu = film["n_layers"] * film["nx"] * film["ny"] * n
-    return {"value": lu / el, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle",
+    host = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": lu / el, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle", "host": host,
             "sample": f"{n} FP64 {lattice.upper()} steps of the same {film['nx']}x{film['ny']} "
                       f"{film['n_layers']}-layer film ({el:.1f} s)"}
 
