@@ -118,6 +118,17 @@ def test_fp64_ragged_2d(mlf, oracle_mod, n):
     assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max()
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_fp64_128_square_1000_steps(mlf, oracle_mod, n):
+    """The FP64 bar on N = 1..4 128^2 films over 10^3 steps, mass included."""
+    film = small_film(n, 128, 128, seed=200 + n)
+    h0 = noisy(n, 128, 128, seed=210 + n)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 1000, "f64")
+    check(g, o, 1e-12, 1e-10)
+    m_g, m_o = g.mass(), o.mass()
+    assert np.abs(m_g - m_o).max() <= 1e-12 * m_o.max()
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (3, 2), (5, 3), (7, 1), (1, 6), (64, 2), (61, 5), (65, 9)])
 def test_fp64_tiny_and_degenerate_grids(mlf, oracle_mod, nx, ny):
     film = small_film(2, nx, ny, seed=7)
