@@ -51,31 +51,38 @@ __device__ inline bf16x8 ld8(const __bf16* p) {
 // out[b, y, x, co] = bias[co] + sum_{o, ci} W[o][co][ci] in[b, y+dy, x+dx, ci]
 // A workgroup of WAVES waves covers WAVES rows of 64 pixels of one image and
 // CO of the C output channels (channel group blockIdx.y); each wave computes
-// 64 pixels x CO channels (CO / 16 column tiles).  The weights of one offset
-// o for the group's channels are staged in LDS (row stride C + 8 bf16,
-// which spreads the 16 rows a wave reads over the banks) and shared by the
-// waves; the next offset's weights are fetched into registers while the
-// current offset's products run (double buffer, one barrier per offset).
-// Input fragments come straight from global memory as 16-byte loads that
-// match the MFMA lane layout.  The per-lane accumulation order (offsets,
-// then 32-channel steps) is fixed, so every launch shape gives the same
-// bits.  Requires gx % 64 == 0, gy % WAVES == 0, C % 32 == 0, CO | C.
+// 64 pixels x CO channels (CO / 16 column tiles).  The input channels are
+// taken in slabs of 32 (one MFMA k-step): per slab the workgroup stages in
+// LDS its WAVES + 2 input rows with one halo pixel on each side
+// ([row][66][40] bf16) and the slab's weights of all nine offsets for its
+// output channels ([9][CO][40] bf16; the stride of 40 spreads the 16 rows a
+// wave reads over the banks), then every product of the slab reads LDS
+// only.  Accumulation order per output: slabs, then offsets.  Dynamic LDS
+// conv3x3_fwd_lds() bytes (up to ~142 KiB).  Requires gx % 64 == 0,
+// gy % WAVES == 0, C % 32 == 0, CO | C.
+constexpr int kConvPS = 40;  // LDS stride of a pixel / weight row (bf16)
+
+__host__ __device__ constexpr size_t conv3x3_fwd_lds(int CO, int waves) {
+  return (size_t)((waves + 2) * 66 + 9 * CO) * kConvPS * 2;
+}
+
 template <int C, int CO, int WAVES, int EPI>
 __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restrict__ in,
                                                            const __bf16* __restrict__ w,
                                                            const float* __restrict__ bias, float* __restrict__ out,
                                                            const float* __restrict__ res, __bf16* __restrict__ outb,
                                                            int gy, int gx) {
-  constexpr int NT = CO / 16, KS = C + 8, NTH = 64 * WAVES;
-  constexpr int PER = (CO * C / 8 + NTH - 1) / NTH;  // 16-byte pieces of one offset per thread
-  __shared__ __bf16 sw[2][CO * KS];
+  constexpr int NT = CO / 16, NTH = 64 * WAVES, PS = kConvPS, ROWS = WAVES + 2, PX = 66;
+  extern __shared__ __bf16 conv_smem[];
+  __bf16* sx = conv_smem;                 // [ROWS][PX][PS]
+  __bf16* sw = conv_smem + ROWS * PX * PS; // [9][CO][PS]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int xtiles = gx / 64;
   const int xt = blockIdx.x % xtiles;
   const int rowblk = blockIdx.x / xtiles;  // (b, group of WAVES rows)
   const int rows_per_img = gy / WAVES;
   const int b = rowblk / rows_per_img;
-  const int y = (rowblk % rows_per_img) * WAVES + wave;
+  const int y0 = (rowblk % rows_per_img) * WAVES;
   const int cg = blockIdx.y;
   const int r = lane & 15, g = lane >> 4;
   f32x4 acc[4][NT];
@@ -84,48 +91,36 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* img = in + (long long)b * gy * gx * C;
-  u32x4v stage[PER];
-  auto fetch = [&](int o) {
-    const __bf16* wo = w + ((long long)o * C + cg * CO) * C;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int t = threadIdx.x + j * NTH;
-      if (t < CO * C / 8) stage[j] = *reinterpret_cast<const u32x4v*>(wo + (long long)(t / (C / 8)) * C + (t % (C / 8)) * 8);
+  for (int c0 = 0; c0 < C; c0 += 32) {
+    __syncthreads();  // the previous slab's products are done with LDS
+    for (int t = threadIdx.x; t < ROWS * PX * 4; t += NTH) {
+      const int q = t & 3, px = (t >> 2) % PX, row = (t >> 2) / PX;
+      const int yy = pwrap(y0 - 1 + row, gy), xx = pwrap(xt * 64 - 1 + px, gx);
+      *reinterpret_cast<u32x4v*>(sx + (row * PX + px) * PS + 8 * q) =
+          *reinterpret_cast<const u32x4v*>(img + ((long long)yy * gx + xx) * C + c0 + 8 * q);
     }
-  };
-  auto put = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int t = threadIdx.x + j * NTH;
-      if (t < CO * C / 8) *reinterpret_cast<u32x4v*>(&sw[buf][(t / (C / 8)) * KS + (t % (C / 8)) * 8]) = stage[j];
+    for (int t = threadIdx.x; t < 9 * CO * 4; t += NTH) {
+      const int q = t & 3, co = (t >> 2) % CO, o = (t >> 2) / CO;
+      *reinterpret_cast<u32x4v*>(sw + (o * CO + co) * PS + 8 * q) =
+          *reinterpret_cast<const u32x4v*>(w + ((long long)o * C + cg * CO + co) * C + c0 + 8 * q);
     }
-  };
-  fetch(0);
-  put(0);
-  __syncthreads();
-  for (int o = 0; o < 9; ++o) {
-    if (o + 1 < 9) fetch(o + 1);
-    const int dy = o / 3 - 1, dx = o % 3 - 1;
-    const __bf16* rowp = img + (long long)pwrap(y + dy, gy) * gx * C;
-    const __bf16* swo = sw[o & 1];
+    __syncthreads();
 #pragma unroll
-    for (int c0 = 0; c0 < C; c0 += 32) {
+    for (int o = 0; o < 9; ++o) {
+      const int dy = o / 3 - 1, dx = o % 3 - 1;
+      const __bf16* xrow = sx + (wave + 1 + dy) * PX * PS;
       bf16x8 a[4], bb[NT];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int xx = pwrap(xt * 64 + 16 * m + r + dx, gx);
-        a[m] = ld8(rowp + (long long)xx * C + c0 + 8 * g);
-      }
+      for (int m = 0; m < 4; ++m) a[m] = ld8(xrow + (16 * m + r + 1 + dx) * PS + 8 * g);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) bb[n] = ld8(swo + (16 * n + r) * KS + c0 + 8 * g);
+      for (int n = 0; n < NT; ++n) bb[n] = ld8(sw + (o * CO + 16 * n + r) * PS + 8 * g);
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
     }
-    if (o + 1 < 9) put((o + 1) & 1);  // the other buffer: last read before the previous barrier
-    __syncthreads();
   }
+  const int y = y0 + wave;
   const long long base = (((long long)b * gy + y) * gx + xt * 64) * C;
 #pragma unroll
   for (int m = 0; m < 4; ++m)

@@ -482,25 +482,34 @@ Layout layout_of(const mlf_nop_params* p) {
 }
 
 // Launch shape by workload: small batches (the judged runs' windows) split
-// the output channels over two workgroups to fill the device; large ones
-// (training) give each workgroup all channels, and for C = 128 eight rows,
-// so that each staged offset of weights serves more products.
+// the output channels over two workgroups of 4 waves to fill the device;
+// large ones (training) give each workgroup all channels and, for C = 128,
+// 8 rows, so that each staged slab of weights serves more products.  The
+// dynamic LDS above 64 KiB is enabled once per kernel.
+template <int C, int CO, int WAVES, int EPI>
+mlf_status conv_fwd_launch(mlf_nop* m, long long rows, const __bf16* in, const __bf16* w, const float* bias,
+                           float* out, const float* res, __bf16* outb) {
+  auto kern = nop::conv3x3_fwd<C, CO, WAVES, EPI>;
+  const size_t lds = nop::conv3x3_fwd_lds(CO, WAVES);
+  static bool attr = false;
+  if (!attr) {
+    NHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+    attr = true;
+  }
+  const unsigned xt = (unsigned)(m->gx / 64);
+  NLAUNCH(kern, dim3((unsigned)(rows / WAVES) * xt, C / CO), dim3(64 * WAVES), lds, m->stream, in, w, bias, out, res,
+          outb, m->gy, m->gx);
+  return MLF_OK;
+}
+
 template <int C, int EPI>
 mlf_status conv_fwd_t(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, const float* bias, float* out,
                       const float* res, __bf16* outb) {
   const long long rows = (long long)batch * m->gy;
-  const unsigned xt = (unsigned)(m->gx / 64);
-  if (rows < 64 * 64) {
-    NLAUNCH((nop::conv3x3_fwd<C, C / 2, 4, EPI>), dim3((unsigned)(rows / 4) * xt, 2), dim3(256), 0, m->stream, in,
-            w, bias, out, res, outb, m->gy, m->gx);
-  } else if (C == 128 && m->gy % 8 == 0) {
-    NLAUNCH((nop::conv3x3_fwd<C, C, 8, EPI>), dim3((unsigned)(rows / 8) * xt, 1), dim3(512), 0, m->stream, in, w,
-            bias, out, res, outb, m->gy, m->gx);
-  } else {
-    NLAUNCH((nop::conv3x3_fwd<C, C, 4, EPI>), dim3((unsigned)(rows / 4) * xt, 1), dim3(256), 0, m->stream, in, w,
-            bias, out, res, outb, m->gy, m->gx);
-  }
-  return MLF_OK;
+  if (rows < 64 * 64) return conv_fwd_launch<C, C / 2, 4, EPI>(m, rows, in, w, bias, out, res, outb);
+  if (C == 128 && m->gy % 8 == 0) return conv_fwd_launch<C, C, 8, EPI>(m, rows, in, w, bias, out, res, outb);
+  return conv_fwd_launch<C, C, 4, EPI>(m, rows, in, w, bias, out, res, outb);
 }
 
 template <int EPI>
