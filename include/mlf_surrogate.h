@@ -37,7 +37,8 @@ extern "C" {
 
 typedef struct mlf_nop_params {
   int32_t n_layers;  /* N, 1..4                                             */
-  int32_t nx, ny;    /* grid: nx a multiple of 256, ny a multiple of 16      */
+  int32_t nx, ny;    /* grid: nx a multiple of 256, ny a multiple of 16;
+                        (ny/4)(nx/4)*width < 2^31 (one latent image)      */
   int32_t width;     /* C, 64 or 128 (EUNSUPPORTED otherwise)                */
   int32_t blocks;    /* L residual blocks, 0..32                              */
   int32_t batch;     /* largest batch passed to the calls below, 1..4096      */

@@ -73,6 +73,13 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
                                                            const float* __restrict__ res, __bf16* __restrict__ outb,
                                                            int gy, int gx) {
   constexpr int NT = CO / 16, NTH = 64 * WAVES, PS = kConvPS, ROWS = WAVES + 2, PX = 66;
+  constexpr int NXP = ROWS * PX * 4, NWP = 9 * CO * 4;  // 16-byte pieces of a slab
+  constexpr int XPER = (NXP + NTH - 1) / NTH, WPER = (NWP + NTH - 1) / NTH, NP = XPER + WPER;
+  // Prefetch the next slab into registers during this slab's products when
+  // the staging registers fit beside the accumulators; otherwise stage each
+  // slab after the barrier that frees LDS, in groups of loads issued together.
+  constexpr bool kPrefetch = 16 * NT + 4 * NP <= 160;
+  constexpr int G = kPrefetch ? NP : 4;
   extern __shared__ __bf16 conv_smem[];
   __bf16* sx = conv_smem;                 // [ROWS][PX][PS]
   __bf16* sw = conv_smem + ROWS * PX * PS; // [9][CO][PS]
@@ -91,20 +98,43 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* img = in + (long long)b * gy * gx * C;
-  for (int c0 = 0; c0 < C; c0 += 32) {
-    __syncthreads();  // the previous slab's products are done with LDS
-    for (int t = threadIdx.x; t < ROWS * PX * 4; t += NTH) {
-      const int q = t & 3, px = (t >> 2) % PX, row = (t >> 2) / PX;
+  // 16-byte piece j of this thread (input pieces first, then weights):
+  // its source at slab c0 and its place in LDS; false past the slab's end
+  auto piece = [&](int j, int c0, const u32x4v*& src, u32x4v*& dst) -> bool {
+    const int t = threadIdx.x + (j < XPER ? j : j - XPER) * NTH;
+    const int q = t & 3;
+    if (j < XPER) {
+      if (t >= NXP) return false;
+      const int px = (t >> 2) % PX, row = (t >> 2) / PX;
       const int yy = pwrap(y0 - 1 + row, gy), xx = pwrap(xt * 64 - 1 + px, gx);
-      *reinterpret_cast<u32x4v*>(sx + (row * PX + px) * PS + 8 * q) =
-          *reinterpret_cast<const u32x4v*>(img + ((long long)yy * gx + xx) * C + c0 + 8 * q);
+      src = reinterpret_cast<const u32x4v*>(img + (yy * gx + xx) * C + c0 + 8 * q);
+      dst = reinterpret_cast<u32x4v*>(sx + (row * PX + px) * PS + 8 * q);
+    } else {
+      if (t >= NWP) return false;
+      const int co = (t >> 2) % CO, o = (t >> 2) / CO;
+      src = reinterpret_cast<const u32x4v*>(w + (o * C + cg * CO + co) * C + c0 + 8 * q);
+      dst = reinterpret_cast<u32x4v*>(sw + (o * CO + co) * PS + 8 * q);
     }
-    for (int t = threadIdx.x; t < 9 * CO * 4; t += NTH) {
-      const int q = t & 3, co = (t >> 2) % CO, o = (t >> 2) / CO;
-      *reinterpret_cast<u32x4v*>(sw + (o * CO + co) * PS + 8 * q) =
-          *reinterpret_cast<const u32x4v*>(w + ((long long)o * C + cg * CO + co) * C + c0 + 8 * q);
+    return true;
+  };
+  u32x4v st[G];
+  auto fetch = [&](int j0, int c0) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const u32x4v* src;
+      u32x4v* dst;
+      if (j0 + j < NP && piece(j0 + j, c0, src, dst)) st[j] = *src;
     }
-    __syncthreads();
+  };
+  auto put = [&](int j0) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const u32x4v* src;
+      u32x4v* dst;
+      if (j0 + j < NP && piece(j0 + j, 0, src, dst)) *dst = st[j];
+    }
+  };
+  auto products = [&]() {
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
@@ -118,6 +148,29 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+    }
+  };
+  if constexpr (kPrefetch) {
+    fetch(0, 0);
+#pragma unroll
+    for (int c0 = 0; c0 < C; c0 += 32) {
+      if (c0) __syncthreads();  // the previous slab's products are done with LDS
+      put(0);
+      __syncthreads();
+      if (c0 + 32 < C) fetch(0, c0 + 32);
+      products();
+    }
+  } else {
+#pragma unroll 1
+    for (int c0 = 0; c0 < C; c0 += 32) {
+      if (c0) __syncthreads();
+#pragma unroll
+      for (int j0 = 0; j0 < NP; j0 += G) {
+        fetch(j0, c0);
+        put(j0);
+      }
+      __syncthreads();
+      products();
     }
   }
   const int y = y0 + wave;

@@ -83,115 +83,122 @@ __global__ void target_inc(const float* __restrict__ h0, const float* __restrict
     o[t] = (h1[t] - h0[t]) * inv_s;
 }
 
-// patch encoder: r[b][py][px][c] = be[c] + sum_j We[j][c] x[b][i][4py+u][4px+v], j = (i*4+u)*4+v
-// A wave takes 64 latent pixels (one per lane) and 32 channels, so the
-// weights are the same for all its lanes (scalar loads).
-__global__ void __launch_bounds__(256) enc_fwd(const float* __restrict__ x, const float* __restrict__ We,
-                                               const float* __restrict__ be, float* __restrict__ r,
-                                               __bf16* __restrict__ rb, int nl, int ny, int nx, int C, int batch) {
+// Wave-local LDS hand-off: the lanes of one wave write, then read what
+// other lanes of the same wave wrote (no workgroup barrier is needed).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// patch layer into the latent grid:
+//   out[b][py][px][c] = bias[c] + sum_j W[j][c] P[b][i][4py+u][4px+v],  j = (i*4+u)*4+v
+// the patch encoder (P = x, bias = b_E, BF16 copy of the output) and the
+// decoder's input gradient (P = dD, W = W_D, no bias, FP32 only).  A wave
+// takes 64 latent pixels of one row (one per lane; coalesced patch loads)
+// and 32 channels, so the weights are the same for all its lanes (scalar
+// loads); the 64 x 32 outputs are transposed through LDS so that each store
+// writes whole 128-byte channel runs.  Needs (batch gy gx) % 64 == 0.
+template <bool BF16>
+__global__ void __launch_bounds__(256) patch_to_latent(const float* __restrict__ P, const float* __restrict__ W,
+                                                       const float* __restrict__ bias, float* __restrict__ out,
+                                                       __bf16* __restrict__ outb, int nl, int ny, int nx, int C,
+                                                       int batch) {
+  constexpr int RS = 33;  // LDS row stride of a pixel's 32 outputs (odd: no bank conflicts)
+  __shared__ float so[4][64 * RS];
   const int gy = ny / kPatch, gx = nx / kPatch;
   const long long npix = (long long)batch * gy * gx;
   const int groups = C / 32;
-  const long long waves = (npix + 63) / 64 * groups;
+  const long long waves = npix / 64 * groups;
   const int lane = threadIdx.x & 63;
-  for (long long wv = blockIdx.x * 4LL + (threadIdx.x >> 6); wv < waves; wv += gridDim.x * 4LL) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float* s = so[wave];
+  for (long long wv = blockIdx.x * 4LL + wave; wv < waves; wv += gridDim.x * 4LL) {
     const int c0 = (int)(wv % groups) * 32;
-    const long long pix = (wv / groups) * 64 + lane;
-    if (pix >= npix) continue;
+    const long long pbase = (wv / groups) * 64;
+    const long long pix = pbase + lane;
     const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
     float acc[32];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = be[c0 + c];
+    for (int c = 0; c < 32; ++c) acc[c] = bias ? bias[c0 + c] : 0.f;
     for (int i = 0; i < nl; ++i)
       for (int u = 0; u < kPatch; ++u) {
-        const float4 xv = *reinterpret_cast<const float4*>(
-            x + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
-        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+        const float4 pv = *reinterpret_cast<const float4*>(
+            P + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
+        const float ps[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float* wr = We + (long long)((i * kPatch + u) * kPatch + v) * C + c0;
+          const float* wr = W + (long long)((i * kPatch + u) * kPatch + v) * C + c0;
 #pragma unroll
-          for (int c = 0; c < 32; ++c) acc[c] += wr[c] * xs[v];
+          for (int c = 0; c < 32; ++c) acc[c] += wr[c] * ps[v];
         }
       }
-    float* ro = r + pix * C + c0;
-    __bf16* rbo = rb + pix * C + c0;
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
-      ro[c] = acc[c];
-      rbo[c] = (__bf16)acc[c];
+    for (int c = 0; c < 32; ++c) s[lane * RS + c] = acc[c];
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int p = 2 * k + (lane >> 5), ch = lane & 31;
+      const float v = s[p * RS + ch];
+      out[(pbase + p) * C + c0 + ch] = v;
+      if constexpr (BF16) outb[(pbase + p) * C + c0 + ch] = (__bf16)v;
     }
+    wave_sync();  // reads done before the next pass overwrites the rows
   }
 }
 
 // decoder + pixel shuffle: D[b][i][4py+u][4px+v] = bd[j] + sum_c Wd[j][c] r[b][py][px][c], j = (i*4+u)*4+v
-// A wave takes 64 latent pixels (one per lane) and the 16 outputs j of one
-// layer i, so the weights are the same for all its lanes (scalar loads) and
-// a batch of B films gives B * (gy * gx / 64) * N waves.
+// A wave takes 64 latent pixels of one row (one per lane) and the 16
+// outputs j of one layer i, so the weights are the same for all its lanes
+// (scalar loads) and a batch of B films gives B * (gy * gx / 64) * N waves.
+// The pixels' channels are staged through LDS 32 at a time with coalesced
+// loads (8 lanes per 128-byte run); the channel order of the sums is
+// ascending, 4 per step.  Needs (batch gy gx) % 64 == 0.
 __global__ void __launch_bounds__(256) dec_fwd(const float* __restrict__ r, const float* __restrict__ Wd,
                                                const float* __restrict__ bd, float* __restrict__ D, int nl, int ny,
                                                int nx, int C, int batch) {
+  constexpr int CH = 32, RS = CH + 4;
+  __shared__ float sr[4][64 * RS];
   const int gy = ny / kPatch, gx = nx / kPatch;
   const long long npix = (long long)batch * gy * gx;
-  const long long waves = (npix + 63) / 64 * nl;
   const int lane = threadIdx.x & 63;
-  for (long long wv = blockIdx.x * 4LL + (threadIdx.x >> 6); wv < waves; wv += gridDim.x * 4LL) {
-    const int i = (int)(wv % nl);
-    const long long pix = (wv / nl) * 64 + lane;
-    if (pix >= npix) continue;
-    const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
-    const float* W = Wd + (long long)16 * i * C;
-    float acc[16];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long wv = (long long)blockIdx.x * 4 + wave;
+  if (wv >= npix / 64 * nl) return;
+  const int i = (int)(wv % nl);
+  const long long pbase = (wv / nl) * 64;
+  const long long pix = pbase + lane;
+  const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
+  const float* W = Wd + (long long)16 * i * C;
+  float* s = sr[wave];
+  float acc[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = bd[16 * i + j];
-    const float* rp = r + pix * C;
-    for (int c = 0; c < C; c += 4) {
-      const float4 rv = *reinterpret_cast<const float4*>(rp + c);
+  for (int j = 0; j < 16; ++j) acc[j] = bd[16 * i + j];
+  for (int c0 = 0; c0 < C; c0 += CH) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = q * 8 + (lane >> 3), cq = lane & 7;
+      *reinterpret_cast<float4*>(s + p * RS + 4 * cq) =
+          *reinterpret_cast<const float4*>(r + (pbase + p) * C + c0 + 4 * cq);
+    }
+    wave_sync();
+    float4 rv[CH / 4];
+#pragma unroll
+    for (int t = 0; t < CH / 4; ++t) rv[t] = *reinterpret_cast<const float4*>(s + lane * RS + 4 * t);
+#pragma unroll
+    for (int t = 0; t < CH / 4; ++t) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const float* wp = W + (long long)j * C + c;
-        acc[j] += wp[0] * rv.x + wp[1] * rv.y + wp[2] * rv.z + wp[3] * rv.w;
+        const float* wp = W + (long long)j * C + c0 + 4 * t;
+        acc[j] += wp[0] * rv[t].x + wp[1] * rv[t].y + wp[2] * rv[t].z + wp[3] * rv[t].w;
       }
     }
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      D[(((long long)b * nl + i) * ny + kPatch * py + j / kPatch) * nx + kPatch * px + j % kPatch] = acc[j];
+    wave_sync();  // reads done before the next chunk overwrites the rows
   }
-}
-
-// decoder input gradient: dr[b][py][px][c] = sum_j Wd[j][c] dD[b][i][4py+u][4px+v]
-// A wave takes 64 latent pixels and 32 channels (scalar weight loads).
-__global__ void __launch_bounds__(256) dec_bwd_in(const float* __restrict__ dD, const float* __restrict__ Wd,
-                                                  float* __restrict__ dr, int nl, int ny, int nx, int C, int batch) {
-  const int gy = ny / kPatch, gx = nx / kPatch;
-  const long long npix = (long long)batch * gy * gx;
-  const int groups = C / 32;
-  const long long waves = (npix + 63) / 64 * groups;
-  const int lane = threadIdx.x & 63;
-  for (long long wv = blockIdx.x * 4LL + (threadIdx.x >> 6); wv < waves; wv += gridDim.x * 4LL) {
-    const int c0 = (int)(wv % groups) * 32;
-    const long long pix = (wv / groups) * 64 + lane;
-    if (pix >= npix) continue;
-    const int px = (int)(pix % gx), py = (int)((pix / gx) % gy), b = (int)(pix / ((long long)gx * gy));
-    float acc[32];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
-    for (int i = 0; i < nl; ++i)
-      for (int u = 0; u < kPatch; ++u) {
-        const float4 dv = *reinterpret_cast<const float4*>(
-            dD + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
-        const float ds[4] = {dv.x, dv.y, dv.z, dv.w};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float* wr = Wd + (long long)((i * kPatch + u) * kPatch + v) * C + c0;
-#pragma unroll
-          for (int c = 0; c < 32; ++c) acc[c] += wr[c] * ds[v];
-        }
-      }
-    float* o = dr + pix * C + c0;
-#pragma unroll
-    for (int c = 0; c < 32; ++c) o[c] = acc[c];
-  }
+  for (int u = 0; u < kPatch; ++u)
+    *reinterpret_cast<float4*>(D + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px) =
+        make_float4(acc[4 * u], acc[4 * u + 1], acc[4 * u + 2], acc[4 * u + 3]);
 }
 
 // partial outer-product sums over pixels for the patch layers:
@@ -275,23 +282,41 @@ __global__ void __launch_bounds__(256) patch_sum(const float* __restrict__ img, 
   }
 }
 
-// partial column sums: part[blk][c] = sum_{pix in slice} a[pix][c]
+// partial column sums: part[blk][c] = sum_{pix in slice} a[pix][c], in pixel
+// order; 8 rows' loads are issued together before they are added.
 __global__ void __launch_bounds__(256) col_partial(const float* __restrict__ a, float* __restrict__ part, int C,
                                                    long long npix) {
   const long long per = (npix + gridDim.x - 1) / gridDim.x;
   const long long p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
   for (int c = threadIdx.x; c < C; c += 256) {
     float s = 0.f;
-    for (long long pix = p0; pix < p1; ++pix) s += a[pix * C + c];
+    long long pix = p0;
+    for (; pix + 8 <= p1; pix += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = a[(pix + q) * C + c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; pix < p1; ++pix) s += a[pix * C + c];
     part[(long long)blockIdx.x * C + c] = s;
   }
 }
 
-// out[k] (+)= sum_r part[r][k]  (fixed order)
+// out[k] (+)= sum_r part[r][k]  (fixed order: r ascending; 8 rows' loads
+// are issued together before they are added)
 __global__ void sum_rows(const float* __restrict__ part, float* __restrict__ out, int rows, long long K, int add) {
   for (long long k = blockIdx.x * 256LL + threadIdx.x; k < K; k += (long long)gridDim.x * 256) {
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[(long long)r * K + k];
+    int r = 0;
+    for (; r + 8 <= rows; r += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(long long)(r + q) * K + k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; r < rows; ++r) s += part[(long long)r * K + k];
     out[k] = add ? out[k] + s : s;
   }
 }
@@ -429,6 +454,8 @@ mlf_status check_params(const mlf_nop_params* p) {
   if (p->n_layers < 1 || p->n_layers > 4) return MLF_EINVAL;
   if (p->nx < 64 * kPatch || p->nx % (64 * kPatch) || p->ny < 4 * kPatch || p->ny % (4 * kPatch)) return MLF_EINVAL;
   if (p->width != 64 && p->width != 128) return MLF_EUNSUPPORTED;
+  // the convolutions index within one latent image in 32-bit arithmetic
+  if ((long long)(p->ny / kPatch) * (p->nx / kPatch) * p->width >= (1LL << 31)) return MLF_EINVAL;
   if (p->blocks < 0 || p->blocks > 32 || p->batch < 1 || p->batch > 4096) return MLF_EINVAL;
   if (!(p->scale > 0.0) || !std::isfinite(p->scale)) return MLF_EINVAL;
   return MLF_OK;
@@ -481,11 +508,14 @@ Layout layout_of(const mlf_nop_params* p) {
   return s;
 }
 
-// Launch shape by workload: small batches (the judged runs' windows) split
-// the output channels over two workgroups of 4 waves to fill the device;
-// large ones (training) give each workgroup all channels and, for C = 128,
-// 8 rows, so that each staged slab of weights serves more products.  The
-// dynamic LDS above 64 KiB is enabled once per kernel.
+// Launch shape by workload (measured on 64 x 64 latent grids): small
+// batches (the judged runs' windows) split the output channels into groups
+// of 32, one workgroup of 4 waves each, to fill the device; large ones
+// (training) give each workgroup of 8 rows all channels, so that each staged
+// slab of weights serves more products -- except the residual epilogue at
+// C = 128 (it reads a third tensor), which runs faster with half the
+// channels on 4 waves, as does any grid whose rows are not a multiple of 8.
+// The dynamic LDS above 64 KiB is enabled once per kernel.
 template <int C, int CO, int WAVES, int EPI>
 mlf_status conv_fwd_launch(mlf_nop* m, long long rows, const __bf16* in, const __bf16* w, const float* bias,
                            float* out, const float* res, __bf16* outb) {
@@ -507,9 +537,10 @@ template <int C, int EPI>
 mlf_status conv_fwd_t(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, const float* bias, float* out,
                       const float* res, __bf16* outb) {
   const long long rows = (long long)batch * m->gy;
-  if (rows < 64 * 64) return conv_fwd_launch<C, C / 2, 4, EPI>(m, rows, in, w, bias, out, res, outb);
-  if (C == 128 && m->gy % 8 == 0) return conv_fwd_launch<C, C, 8, EPI>(m, rows, in, w, bias, out, res, outb);
-  return conv_fwd_launch<C, C, 4, EPI>(m, rows, in, w, bias, out, res, outb);
+  if (rows < 64 * 64) return conv_fwd_launch<C, 32, 4, EPI>(m, rows, in, w, bias, out, res, outb);
+  if (m->gy % 8 == 0 && !(C == 128 && EPI == nop::kEpiResid))
+    return conv_fwd_launch<C, C, 8, EPI>(m, rows, in, w, bias, out, res, outb);
+  return conv_fwd_launch<C, C / 2, 4, EPI>(m, rows, in, w, bias, out, res, outb);
 }
 
 template <int EPI>
@@ -560,8 +591,8 @@ mlf_status forward(mlf_nop* m, int batch, const float* h) {
   NLAUNCH(plane_mean, dim3(batch * N), dim3(1024), 0, m->stream, h, m->mean, plane);
   NLAUNCH(center_scale, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->mean, m->x, plane, img,
           (float)(1.0 / m->p.scale));
-  NLAUNCH(enc_fwd, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->x, m->par + m->oWe, m->par + m->obe, m->r,
-          m->rb, N, m->p.ny, m->p.nx, m->C, batch);
+  NLAUNCH(patch_to_latent<true>, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->x, m->par + m->oWe,
+          m->par + m->obe, m->r, m->rb, N, m->p.ny, m->p.nx, m->C, batch);
   const long long cc = 9LL * m->C * m->C;
   for (int l = 0; l < m->L; ++l) {
     float* rl = m->r + l * m->lat;
@@ -577,8 +608,8 @@ mlf_status forward(mlf_nop* m, int batch, const float* h) {
                                     m->r + (l + 1) * m->lat, rl, m->rb + (l + 1) * m->lat);
     if (st != MLF_OK) return st;
   }
-  NLAUNCH(dec_fwd, dim3(grid1((npix + 63) / 64 * N * 64)), dim3(256), 0, m->stream, m->r + m->L * m->lat, m->par + m->oWd,
-          m->par + m->obd, m->D, N, m->p.ny, m->p.nx, m->C, batch);
+  NLAUNCH(dec_fwd, dim3((unsigned)((npix / 64 * N + 3) / 4)), dim3(256), 0, m->stream, m->r + m->L * m->lat,
+          m->par + m->oWd, m->par + m->obd, m->D, N, m->p.ny, m->p.nx, m->C, batch);
   NLAUNCH(plane_mean, dim3(batch * N), dim3(1024), 0, m->stream, m->D, m->mean, plane);
   NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->D, m->mean, plane, img);
   return MLF_OK;
@@ -616,8 +647,8 @@ mlf_status backward(mlf_nop* m, int batch) {
   NLAUNCH(sum_rows, dim3(grid1(J * C)), dim3(256), 0, m->stream, m->part, m->grad + m->oWd, kRedBlocks, J * C, 0);
   NLAUNCH(patch_sum, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->part, N, m->p.ny, m->p.nx, npix);
   NLAUNCH(sum_rows, dim3(grid1(J)), dim3(256), 0, m->stream, m->part, m->grad + m->obd, kRedBlocks, J, 0);
-  NLAUNCH(dec_bwd_in, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, m->dr, N, m->p.ny,
-          m->p.nx, m->C, batch);
+  NLAUNCH(patch_to_latent<false>, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, nullptr,
+          m->dr, nullptr, N, m->p.ny, m->p.nx, m->C, batch);
   // residual blocks, last to first; m->dr holds dL/dr_{l+1}
   for (int l = m->L - 1; l >= 0; --l) {
     const long long ob = l * m->blk_stride;

@@ -196,6 +196,13 @@ def test_surrogate_sizes_and_validation():
         assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -1, field
     q = mlfilm.NopParams(3, 256, 256, 96, 3, 64, 1e-2)
     assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -2
+    # one latent image must index in 32 bits: (ny/4)(nx/4) C < 2^31
+    q = mlfilm.NopParams(1, 16384, 16384, 128, 1, 1, 1e-2)
+    assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -1
+    q = mlfilm.NopParams(1, 16384, 16380, 128, 1, 1, 1e-2)
+    assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == -1   # ny % 16
+    q = mlfilm.NopParams(1, 16384, 16368, 128, 1, 1, 1e-2)
+    assert lib.mlf_nop_query_sizes(C.byref(q), C.byref(n), C.byref(w)) == 0
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4])
