@@ -201,68 +201,85 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
 
 // ---- 3x3 periodic convolution, weight gradient ----------------------------
 // part[b][o][co][ci] = sum_{y, x} dy[b, y, x, co] in[b, y+dy_o, x+dx_o, ci]
-// One workgroup per (image b, offset o); it marches the image in chunks of
-// 64 pixels of one row.  Each chunk of dY and of the shifted input is staged
+// One workgroup per (image b, row offset dy, block of COB output channels):
+// it marches the image in chunks of 64 pixels of one row and accumulates
+// the three offsets (dy, -1), (dy, 0), (dy, +1) together.  Per chunk the
+// workgroup stages dY (its COB channels) and the input row y + dy
 // transposed in LDS ([channel][pixel], stride 72 so that 8 consecutive
-// pixels are one 16-byte read): a thread loads 4 consecutive pixels x 8
-// channels of each tensor and writes 8-byte runs (4 pixels of one channel).
-// The next chunk's loads are issued before this chunk's products.  The
-// C x C result is split over 4 waves by output-channel row tiles; pixels
-// are accumulated in order (32 per MFMA step).  Requires gx % 64 == 0.
-template <int C>
+// pixels are one 16-byte read), the input three times, shifted by
+// dx = -1, 0, 1: a thread loads 8 channels of 4 consecutive pixels of dY
+// and of 6 consecutive pixels of the input (one halo pixel each side) and
+// writes 8-byte runs of 4 pixels of one channel.  Consecutive lanes take
+// consecutive pixel groups, so the 16 lanes that write one channel row
+// write 128 contiguous bytes (no bank conflicts; channel-fast lanes wrote
+// 16 rows 8 apart into two bank groups, half the kernel's time).  The next
+// chunk's loads are issued before the current products.  The 2 x 2 waves
+// split the COB x C block; pixels are accumulated in order (32 per MFMA
+// step), so every launch shape gives the same bits.  Dynamic LDS
+// conv3x3_wgrad_lds() bytes.  Requires gx % 64 == 0, COB % 32 == 0, COB | C.
+__host__ __device__ constexpr size_t conv3x3_wgrad_lds(int C, int COB) {
+  return (size_t)(COB + 3 * C) * (64 + 8) * 2;
+}
+
+template <int C, int COB>
 __global__ void __launch_bounds__(256) conv3x3_wgrad(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
                                                       float* __restrict__ part, int gy, int gx) {
-  constexpr int CH = 64;              // pixels per chunk
-  constexpr int NT = C / 16;          // tiles per dimension
-  constexpr int RT = NT / 4;          // row tiles per wave (C / 64)
-  constexpr int KP = CH + 8;          // padded pixel stride of an LDS row (bf16)
-  constexpr int PER = ((CH / 4) * (C / 8) + 255) / 256;  // staging pieces per thread
+  constexpr int CH = 64;                      // pixels per chunk
+  constexpr int KP = CH + 8;                  // padded pixel stride of an LDS row (bf16)
+  constexpr int RT = COB / 32, NT = C / 32;   // tiles per wave (2 x 2 waves over COB x C)
+  constexpr int HB = C / COB;                 // output-channel blocks
+  constexpr int DP = (CH / 4) * (COB / 8);    // dY pieces (4 pixels x 8 channels)
+  constexpr int XP = (CH / 4) * (C / 8);      // input pieces (6 pixels x 8 channels)
+  static_assert(DP <= 256 && XP <= 256, "one piece of each tensor per thread");
   typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
-  __shared__ __bf16 sd[C * KP];       // dY chunk, [co][px]
-  __shared__ __bf16 sx[C * KP];       // input chunk, [ci][px]
+  extern __shared__ __bf16 wg_smem[];
+  __bf16* sd = wg_smem;             // [COB][KP]  dY chunk
+  __bf16* sx = wg_smem + COB * KP;  // [3][C][KP] input chunk shifted by dx = -1, 0, 1
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int b = blockIdx.x / 9, o = blockIdx.x % 9;
-  const int dy = o / 3 - 1, dx = o % 3 - 1;
+  const int h = blockIdx.x % HB, dyi = (blockIdx.x / HB) % 3, b = blockIdx.x / (3 * HB);
   const int r = lane & 15, g = lane >> 4;
-  f32x4 acc[RT][NT];
+  const int co0 = (wave >> 1) * (COB / 2), ci0 = (wave & 1) * (C / 2);
+  f32x4 acc[3][RT][NT];
 #pragma unroll
-  for (int m = 0; m < RT; ++m)
+  for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16* dimg = dout + (long long)b * gy * gx * C;
+    for (int m = 0; m < RT; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[s][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16* dimg = dout + (long long)b * gy * gx * C + h * COB;
   const __bf16* ximg = in + (long long)b * gy * gx * C;
   const int chunks_per_row = gx / CH, nch = gy * chunks_per_row;
-  bf16x8 vd[PER][4], vx[PER][4];
+  const int t = threadIdx.x;
+  const int p4 = (t % (CH / 4)) * 4, c8 = (t / (CH / 4)) * 8;  // this thread's pieces
+  bf16x8 vd[4], vx[6];
   auto fetch = [&](int ch) {
     const int y = ch / chunks_per_row, x0 = (ch % chunks_per_row) * CH;
-    const int ys = pwrap(y + dy, gy);
+    const int ys = pwrap(y + dyi - 1, gy);
+    if (t < DP) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int t = threadIdx.x + 256 * j;
-      if (t < (CH / 4) * (C / 8)) {
-        const int p4 = (t / (C / 8)) * 4, c8 = (t % (C / 8)) * 8;
+      for (int q = 0; q < 4; ++q) vd[q] = ld8(dimg + (y * gx + x0 + p4 + q) * C + c8);
+    }
+    if (t < XP) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          vd[j][q] = ld8(dimg + ((long long)y * gx + x0 + p4 + q) * C + c8);
-          vx[j][q] = ld8(ximg + ((long long)ys * gx + pwrap(x0 + p4 + q + dx, gx)) * C + c8);
-        }
-      }
+      for (int q = 0; q < 6; ++q) vx[q] = ld8(ximg + (ys * gx + pwrap(x0 + p4 + q - 1, gx)) * C + c8);
     }
   };
   auto put = [&]() {
+    if (t < DP) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int t = threadIdx.x + 256 * j;
-      if (t < (CH / 4) * (C / 8)) {
-        const int p4 = (t / (C / 8)) * 4, c8 = (t % (C / 8)) * 8;
+      for (int e = 0; e < 8; ++e) {
+        __bf16 a4[4] = {vd[0][e], vd[1][e], vd[2][e], vd[3][e]};
+        *reinterpret_cast<u32x2v*>(sd + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, a4);
+      }
+    }
+    if (t < XP) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          __bf16 a4[4] = {vd[j][0][e], vd[j][1][e], vd[j][2][e], vd[j][3][e]};
-          __bf16 b4[4] = {vx[j][0][e], vx[j][1][e], vx[j][2][e], vx[j][3][e]};
-          *reinterpret_cast<u32x2v*>(sd + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, a4);
-          *reinterpret_cast<u32x2v*>(sx + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, b4);
+          __bf16 b4[4] = {vx[s][e], vx[s + 1][e], vx[s + 2][e], vx[s + 3][e]};
+          *reinterpret_cast<u32x2v*>(sx + (s * C + c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, b4);
         }
-      }
     }
   };
   fetch(0);
@@ -272,27 +289,35 @@ __global__ void __launch_bounds__(256) conv3x3_wgrad(const __bf16* __restrict__ 
     if (ch + 1 < nch) fetch(ch + 1);
 #pragma unroll
     for (int k0 = 0; k0 < CH; k0 += 32) {
-      bf16x8 a[RT], bb[NT];
+      bf16x8 a[RT];
 #pragma unroll
-      for (int m = 0; m < RT; ++m) a[m] = ld8(sd + (16 * (wave * RT + m) + r) * KP + k0 + 8 * g);
+      for (int m = 0; m < RT; ++m) a[m] = ld8(sd + (co0 + 16 * m + r) * KP + k0 + 8 * g);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) bb[n] = ld8(sx + (16 * n + r) * KP + k0 + 8 * g);
+      for (int s = 0; s < 3; ++s) {
+        bf16x8 bb[NT];
 #pragma unroll
-      for (int m = 0; m < RT; ++m)
+        for (int n = 0; n < NT; ++n) bb[n] = ld8(sx + (s * C + ci0 + 16 * n + r) * KP + k0 + 8 * g);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+        for (int m = 0; m < RT; ++m)
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[s][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[s][m][n], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  float* pb = part + ((long long)b * 9 + o) * C * C;
 #pragma unroll
-  for (int m = 0; m < RT; ++m)
+  for (int s = 0; s < 3; ++s) {
+    float* pb = part + ((long long)b * 9 + dyi * 3 + s) * C * C;
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-      const int ci = 16 * n + r;
+    for (int m = 0; m < RT; ++m)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) pb[(long long)(16 * (wave * RT + m) + 4 * g + i) * C + ci] = acc[m][n][i];
-    }
+      for (int n = 0; n < NT; ++n) {
+        const int ci = ci0 + 16 * n + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pb[(long long)(h * COB + co0 + 16 * m + 4 * g + i) * C + ci] = acc[s][m][n][i];
+      }
+  }
 }
 
 }  // namespace nop

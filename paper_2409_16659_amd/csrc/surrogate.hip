@@ -554,12 +554,27 @@ mlf_status conv_fwd(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, co
   return conv_fwd_e<nop::kEpiPlain>(m, batch, in, w, bias, out, nullptr, nullptr);
 }
 
+// per-image weight gradients into m->part ([batch][9][C][C]); a workgroup
+// per (image, row offset, 64 output channels)
+template <int C>
+mlf_status wgrad_launch(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout) {
+  constexpr int COB = 64;
+  auto kern = nop::conv3x3_wgrad<C, COB>;
+  const size_t lds = nop::conv3x3_wgrad_lds(C, COB);
+  static bool attr = false;
+  if (!attr) {
+    NHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+    attr = true;
+  }
+  NLAUNCH(kern, dim3((unsigned)batch * 3 * (C / COB)), dim3(256), lds, m->stream, in, dout, m->part, m->gy, m->gx);
+  return MLF_OK;
+}
+
 // dW (FP32, [9][C][C]) = sum over the batch of the weight gradient
 mlf_status conv_wgrad(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout, float* dw) {
-  if (m->C == 64)
-    NLAUNCH(nop::conv3x3_wgrad<64>, dim3(batch * 9), dim3(256), 0, m->stream, in, dout, m->part, m->gy, m->gx);
-  else
-    NLAUNCH(nop::conv3x3_wgrad<128>, dim3(batch * 9), dim3(256), 0, m->stream, in, dout, m->part, m->gy, m->gx);
+  const mlf_status st = m->C == 64 ? wgrad_launch<64>(m, batch, in, dout) : wgrad_launch<128>(m, batch, in, dout);
+  if (st != MLF_OK) return st;
   const long long K = 9LL * m->C * m->C;
   NLAUNCH(sum_rows, dim3(grid1(K)), dim3(256), 0, m->stream, m->part, dw, batch, K, 0);
   return MLF_OK;
@@ -819,15 +834,8 @@ mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_
   if (st == MLF_OK) st = nhip(m, hipEventRecord(e0, m->stream), "hipEventRecord");
   for (int r = 0; r < reps && st == MLF_OK; ++r) st = conv_fwd(m, batch, m->rb, m->w1b, m->par + m->ob1, m->a);
   if (st == MLF_OK) st = nhip(m, hipEventRecord(e1, m->stream), "hipEventRecord");
-  for (int r = 0; r < reps && st == MLF_OK; ++r) {
-    if (m->C == 64)
-      hipLaunchKernelGGL(nop::conv3x3_wgrad<64>, dim3(batch * 9), dim3(256), 0, m->stream, m->rb, m->gb, m->part,
-                         m->gy, m->gx);
-    else
-      hipLaunchKernelGGL(nop::conv3x3_wgrad<128>, dim3(batch * 9), dim3(256), 0, m->stream, m->rb, m->gb, m->part,
-                         m->gy, m->gx);
-    st = nhip(m, hipGetLastError(), "conv3x3_wgrad");
-  }
+  for (int r = 0; r < reps && st == MLF_OK; ++r)
+    st = m->C == 64 ? wgrad_launch<64>(m, batch, m->rb, m->gb) : wgrad_launch<128>(m, batch, m->rb, m->gb);
   if (st == MLF_OK) st = nhip(m, hipEventRecord(e2, m->stream), "hipEventRecord");
   if (st == MLF_OK) st = nhip(m, hipEventSynchronize(e2), "hipEventSynchronize");
   float a = 0.f, b = 0.f;
