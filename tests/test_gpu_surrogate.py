@@ -11,7 +11,9 @@ over whole tensors on these random networks: increments 4e-4 (C = 64) and
 6e-4 (C = 128), three times closer than to the unrounded FP64 network;
 gradients at most 2.1e-3 (first convolution of a block).  The tests allow
 2e-3 for increments and 1e-2 for gradients, and compare the Adam update on
-the GPU's own gradient to 1e-6.
+the GPU's own gradient to 1e-6.  The oracle runs small batches; the launch
+shapes of training batches are tied to them bit for bit (predictions) and to
+1e-4 (gradients, summation order; measured 3.5e-7).
 """
 import numpy as np
 import pytest
@@ -86,6 +88,40 @@ def test_gradient_matches_reference(mlf, torch_cuda, C, N):
         print(f"   C={C} {name}: rel L2 {e:.2e}", flush=True)
         assert e <= 1e-2, name
     print(f"C={C} worst gradient rel L2 {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("C", [64, 128])
+def test_training_launch_shapes_match_small_batches(mlf, torch_cuda, C):
+    """A batch of 64 films of 256^2 (4096 latent rows) runs the convolutions
+    in the training launch shapes (all channels on 8 rows per workgroup, the
+    C = 128 residual epilogue on 64 channels and 4 waves), a batch of 8 in
+    the judged runs' shapes (32-channel groups): every shape accumulates in
+    the same order, so the predictions agree bit for bit.  The gradient of
+    the mean loss over the 64 equals the mean of the gradients of eight
+    batches of 8 up to FP32 summation order (the oracle is too slow at this
+    size; the small-batch gradients are pinned to it above)."""
+    torch = torch_cuda
+    N, L, B = 3, 1, 64
+    rng = np.random.default_rng(7)
+    vec = nop.init_params(rng, N, C, L)
+    vec += rng.normal(0, 0.01, vec.size)
+    vec = vec.astype(np.float32).astype(np.float64)
+    h0 = (1.0 + 1e-2 * rng.normal(size=(B, N, 256, 256))).astype(np.float32)
+    h1 = (h0 + 1e-3 * rng.normal(size=h0.shape)).astype(np.float32)
+    s = mlf.Surrogate(N, 256, 256, width=C, blocks=L, batch=B, scale=1e-2)
+    s.set_params(vec)
+    t0, t1 = torch.from_numpy(h0).cuda(), torch.from_numpy(h1).cuda()
+    big = s.predict(t0).cpu().numpy()
+    small = np.concatenate([s.predict(t0[i:i + 8]).cpu().numpy() for i in range(0, B, 8)])
+    assert np.array_equal(big, small)
+    loss_b, g_b = s.gradient(t0, t1)
+    parts = [s.gradient(t0[i:i + 8], t1[i:i + 8]) for i in range(0, B, 8)]
+    loss_s = float(np.mean([lv for lv, _ in parts]))
+    g_s = np.mean([g.astype(np.float64) for _, g in parts], axis=0)
+    e = rel(g_b, g_s)
+    print(f"C={C} batch 64 vs 8 x 8: loss {loss_b:.6e} / {loss_s:.6e}, gradient rel L2 {e:.2e}", flush=True)
+    assert abs(loss_b - loss_s) <= 1e-5 * loss_s
+    assert e <= 1e-4
 
 
 def test_adam_step_matches_reference_update(mlf, torch_cuda):
