@@ -515,21 +515,15 @@ Layout layout_of(const mlf_nop_params* p) {
 // slab of weights serves more products -- except the residual epilogue at
 // C = 128 (it reads a third tensor), which runs faster with half the
 // channels on 4 waves, as does any grid whose rows are not a multiple of 8.
-// The dynamic LDS above 64 KiB is enabled once per kernel.
+// The dynamic LDS above 64 KiB of every shape is enabled when the handle is
+// created (set_lds_limits, on the handle's device).
 template <int C, int CO, int WAVES, int EPI>
 mlf_status conv_fwd_launch(mlf_nop* m, long long rows, const __bf16* in, const __bf16* w, const float* bias,
                            float* out, const float* res, __bf16* outb) {
-  auto kern = nop::conv3x3_fwd<C, CO, WAVES, EPI>;
   const size_t lds = nop::conv3x3_fwd_lds(CO, WAVES);
-  static bool attr = false;
-  if (!attr) {
-    NHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-    attr = true;
-  }
   const unsigned xt = (unsigned)(m->gx / 64);
-  NLAUNCH(kern, dim3((unsigned)(rows / WAVES) * xt, C / CO), dim3(64 * WAVES), lds, m->stream, in, w, bias, out, res,
-          outb, m->gy, m->gx);
+  NLAUNCH((nop::conv3x3_fwd<C, CO, WAVES, EPI>), dim3((unsigned)(rows / WAVES) * xt, C / CO), dim3(64 * WAVES), lds,
+          m->stream, in, w, bias, out, res, outb, m->gy, m->gx);
   return MLF_OK;
 }
 
@@ -559,17 +553,38 @@ mlf_status conv_fwd(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, co
 template <int C>
 mlf_status wgrad_launch(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout) {
   constexpr int COB = 64;
-  auto kern = nop::conv3x3_wgrad<C, COB>;
-  const size_t lds = nop::conv3x3_wgrad_lds(C, COB);
-  static bool attr = false;
-  if (!attr) {
-    NHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-    attr = true;
-  }
-  NLAUNCH(kern, dim3((unsigned)batch * 3 * (C / COB)), dim3(256), lds, m->stream, in, dout, m->part, m->gy, m->gx);
+  NLAUNCH((nop::conv3x3_wgrad<C, COB>), dim3((unsigned)batch * 3 * (C / COB)), dim3(256),
+          nop::conv3x3_wgrad_lds(C, COB), m->stream, in, dout, m->part, m->gy, m->gx);
   return MLF_OK;
 }
+
+// Dynamic LDS limits of every convolution shape the launchers above can
+// pick for width C (hipFuncSetAttribute applies on the current device).
+template <typename K>
+mlf_status set_lds(mlf_nop* m, K kern, size_t bytes) {
+  NHIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)bytes));
+  return MLF_OK;
+}
+
+template <int C, int EPI>
+mlf_status set_fwd_lds(mlf_nop* m) {
+  mlf_status st = set_lds(m, nop::conv3x3_fwd<C, 32, 4, EPI>, nop::conv3x3_fwd_lds(32, 4));
+  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_fwd<C, C, 8, EPI>, nop::conv3x3_fwd_lds(C, 8));
+  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_fwd<C, C / 2, 4, EPI>, nop::conv3x3_fwd_lds(C / 2, 4));
+  return st;
+}
+
+template <int C>
+mlf_status set_lds_limits_c(mlf_nop* m) {
+  mlf_status st = set_fwd_lds<C, nop::kEpiPlain>(m);
+  if (st == MLF_OK) st = set_fwd_lds<C, nop::kEpiGelu>(m);
+  if (st == MLF_OK) st = set_fwd_lds<C, nop::kEpiResid>(m);
+  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_wgrad<C, 64>, nop::conv3x3_wgrad_lds(C, 64));
+  return st;
+}
+
+mlf_status set_lds_limits(mlf_nop* m) { return m->C == 64 ? set_lds_limits_c<64>(m) : set_lds_limits_c<128>(m); }
 
 // dW (FP32, [9][C][C]) = sum over the batch of the weight gradient
 mlf_status conv_wgrad(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout, float* dw) {
@@ -751,6 +766,10 @@ mlf_status mlf_nop_create(const mlf_nop_params* p, void* workspace, void* stream
   m->cb = reinterpret_cast<__bf16*>(w + s.off[18]);
   m->part = reinterpret_cast<float*>(w + s.off[19]);
   m->adam_t = 0;
+  if ((st = set_lds_limits(m)) != MLF_OK) {
+    delete m;
+    return st;
+  }
   *out = m;
   return MLF_OK;
 }
