@@ -62,18 +62,25 @@ __global__ void __launch_bounds__(1024) plane_mean(const float* __restrict__ a, 
   if (threadIdx.x == 0) out[blockIdx.x] = red[0] / (float)n;
 }
 
-// y = (a - mean[plane]) * scale
+// y = (a - mean[plane]) * scale; grid row blockIdx.y = plane (no index division)
 __global__ void center_scale(const float* __restrict__ a, const float* __restrict__ mean, float* __restrict__ y,
-                             long long n_plane, long long total, float scale) {
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
-    y[t] = (a[t] - mean[t / n_plane]) * scale;
+                             long long n_plane, float scale) {
+  const long long base = (long long)blockIdx.y * n_plane;
+  const float mu = mean[blockIdx.y];
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n_plane; t += (long long)gridDim.x * 256)
+    y[base + t] = (a[base + t] - mu) * scale;
 }
 
-// h_out = h + s * delta
-__global__ void axpy_out(const float* __restrict__ h, const float* __restrict__ d, float* __restrict__ o, float s,
-                         long long total) {
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
-    o[t] = h[t] + s * d[t];
+// prediction tail: o = h + s * (d - mean[plane]), the decoder output made
+// mass-free and added to the input in one pass
+__global__ void sub_mean_axpy(const float* __restrict__ h, const float* __restrict__ d,
+                              const float* __restrict__ mean, float* __restrict__ o, float s, long long n_plane) {
+  const long long base = (long long)blockIdx.y * n_plane;
+  const float mu = mean[blockIdx.y];
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n_plane; t += (long long)gridDim.x * 256) {
+    const float dv = d[base + t] - mu;
+    o[base + t] = h[base + t] + s * dv;
+  }
 }
 
 // target increment (h1 - h0) / s
@@ -98,12 +105,14 @@ __device__ inline void wave_sync() {
 // takes 64 latent pixels of one row (one per lane; coalesced patch loads)
 // and 32 channels, so the weights are the same for all its lanes (scalar
 // loads); the 64 x 32 outputs are transposed through LDS so that each store
-// writes whole 128-byte channel runs.  Needs (batch gy gx) % 64 == 0.
-template <bool BF16>
+// writes whole 128-byte channel runs.  CENTER forms the encoder's input
+// (P - pmean[plane]) * pscale on the fly (the prediction path, which keeps
+// no copy of it).  Needs (batch gy gx) % 64 == 0.
+template <bool BF16, bool CENTER>
 __global__ void __launch_bounds__(256) patch_to_latent(const float* __restrict__ P, const float* __restrict__ W,
                                                        const float* __restrict__ bias, float* __restrict__ out,
                                                        __bf16* __restrict__ outb, int nl, int ny, int nx, int C,
-                                                       int batch) {
+                                                       int batch, const float* __restrict__ pmean, float pscale) {
   constexpr int RS = 33;  // LDS row stride of a pixel's 32 outputs (odd: no bank conflicts)
   __shared__ float so[4][64 * RS];
   const int gy = ny / kPatch, gx = nx / kPatch;
@@ -123,8 +132,12 @@ __global__ void __launch_bounds__(256) patch_to_latent(const float* __restrict__
     for (int c = 0; c < 32; ++c) acc[c] = bias ? bias[c0 + c] : 0.f;
     for (int i = 0; i < nl; ++i)
       for (int u = 0; u < kPatch; ++u) {
-        const float4 pv = *reinterpret_cast<const float4*>(
+        float4 pv = *reinterpret_cast<const float4*>(
             P + (((long long)b * nl + i) * ny + kPatch * py + u) * nx + kPatch * px);
+        if constexpr (CENTER) {  // the encoder's input (P - mean of the plane) * scale, formed here
+          const float mu = pmean[b * nl + i];
+          pv = make_float4((pv.x - mu) * pscale, (pv.y - mu) * pscale, (pv.z - mu) * pscale, (pv.w - mu) * pscale);
+        }
         const float ps[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -360,10 +373,11 @@ __global__ void conv_weights(const float* __restrict__ w, __bf16* __restrict__ w
 }
 
 // d = d - mean[plane]
-__global__ void sub_plane_mean(float* __restrict__ d, const float* __restrict__ mean, long long n_plane,
-                               long long total) {
-  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256)
-    d[t] -= mean[t / n_plane];
+__global__ void sub_plane_mean(float* __restrict__ d, const float* __restrict__ mean, long long n_plane) {
+  const long long base = (long long)blockIdx.y * n_plane;
+  const float mu = mean[blockIdx.y];
+  for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n_plane; t += (long long)gridDim.x * 256)
+    d[base + t] -= mu;
 }
 
 // loss partials: part[blk] = sum (delta - target)^2 over a slice; grad = 2 (delta - target) / n
@@ -399,6 +413,10 @@ __global__ void adam(float* __restrict__ p, const float* __restrict__ g, float* 
 }
 
 unsigned grid1(long long n) { return (unsigned)std::max(1LL, std::min((n + 255) / 256, 16384LL)); }
+// per-plane elementwise kernels: blockIdx.y = plane
+dim3 plane_grid(long long n_plane, long long planes) {
+  return dim3((unsigned)std::max(1LL, std::min((n_plane + 255) / 256, 1024LL)), (unsigned)planes);
+}
 
 }  // namespace
 
@@ -613,16 +631,26 @@ mlf_status refresh_weights(mlf_nop* m) {
   return MLF_OK;
 }
 
-// forward to the projected increment m->D; keeps the activations
-mlf_status forward(mlf_nop* m, int batch, const float* h) {
+// Forward pass to the increment m->D, keeping the activations for the
+// backward pass.  predict: the encoder forms its input on the fly and the
+// decoder output keeps its plane means (mlf_nop_predict's tail removes them
+// while adding the increment to h); otherwise the encoder input x and the
+// mass-free increment D are kept for the loss and the backward pass.
+mlf_status forward(mlf_nop* m, int batch, const float* h, bool predict) {
   const int N = m->p.n_layers;
-  const long long plane = (long long)m->p.ny * m->p.nx, img = (long long)batch * N * plane;
+  const long long plane = (long long)m->p.ny * m->p.nx;
   const long long npix = (long long)batch * m->gy * m->gx, lat = npix * m->C;
+  const dim3 pg = plane_grid(plane, (long long)batch * N);
+  const float inv_s = (float)(1.0 / m->p.scale);
   NLAUNCH(plane_mean, dim3(batch * N), dim3(1024), 0, m->stream, h, m->mean, plane);
-  NLAUNCH(center_scale, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->mean, m->x, plane, img,
-          (float)(1.0 / m->p.scale));
-  NLAUNCH(patch_to_latent<true>, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->x, m->par + m->oWe,
-          m->par + m->obe, m->r, m->rb, N, m->p.ny, m->p.nx, m->C, batch);
+  if (predict) {
+    NLAUNCH((patch_to_latent<true, true>), dim3(grid1(lat / 32)), dim3(256), 0, m->stream, h, m->par + m->oWe,
+            m->par + m->obe, m->r, m->rb, N, m->p.ny, m->p.nx, m->C, batch, m->mean, inv_s);
+  } else {
+    NLAUNCH(center_scale, pg, dim3(256), 0, m->stream, h, m->mean, m->x, plane, inv_s);
+    NLAUNCH((patch_to_latent<true, false>), dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->x, m->par + m->oWe,
+            m->par + m->obe, m->r, m->rb, N, m->p.ny, m->p.nx, m->C, batch, nullptr, 0.f);
+  }
   const long long cc = 9LL * m->C * m->C;
   for (int l = 0; l < m->L; ++l) {
     float* rl = m->r + l * m->lat;
@@ -641,7 +669,7 @@ mlf_status forward(mlf_nop* m, int batch, const float* h) {
   NLAUNCH(dec_fwd, dim3((unsigned)((npix / 64 * N + 3) / 4)), dim3(256), 0, m->stream, m->r + m->L * m->lat,
           m->par + m->oWd, m->par + m->obd, m->D, N, m->p.ny, m->p.nx, m->C, batch);
   NLAUNCH(plane_mean, dim3(batch * N), dim3(1024), 0, m->stream, m->D, m->mean, plane);
-  NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->D, m->mean, plane, img);
+  if (!predict) NLAUNCH(sub_plane_mean, pg, dim3(256), 0, m->stream, m->D, m->mean, plane);
   return MLF_OK;
 }
 
@@ -665,20 +693,20 @@ mlf_status loss_and_grad(mlf_nop* m, int batch, const float* h0, const float* h1
 // and loss_and_grad with the gradient)
 mlf_status backward(mlf_nop* m, int batch) {
   const int N = m->p.n_layers;
-  const long long plane = (long long)m->p.ny * m->p.nx, img = (long long)batch * N * plane;
+  const long long plane = (long long)m->p.ny * m->p.nx;
   const long long npix = (long long)batch * m->gy * m->gx, lat = npix * m->C, J = m->J, C = m->C;
   const long long cc = 9LL * C * C;
   // the projection (no net mass change) is symmetric: project the gradient
   NLAUNCH(plane_mean, dim3(batch * N), dim3(1024), 0, m->stream, m->dD, m->mean, plane);
-  NLAUNCH(sub_plane_mean, dim3(grid1(img)), dim3(256), 0, m->stream, m->dD, m->mean, plane, img);
+  NLAUNCH(sub_plane_mean, plane_grid(plane, (long long)batch * N), dim3(256), 0, m->stream, m->dD, m->mean, plane);
   // decoder: weights, bias, input gradient
   NLAUNCH(patch_outer, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->r + m->L * m->lat, m->part, N, m->p.ny,
           m->p.nx, m->C, npix);
   NLAUNCH(sum_rows, dim3(grid1(J * C)), dim3(256), 0, m->stream, m->part, m->grad + m->oWd, kRedBlocks, J * C, 0);
   NLAUNCH(patch_sum, dim3(kRedBlocks), dim3(256), 0, m->stream, m->dD, m->part, N, m->p.ny, m->p.nx, npix);
   NLAUNCH(sum_rows, dim3(grid1(J)), dim3(256), 0, m->stream, m->part, m->grad + m->obd, kRedBlocks, J, 0);
-  NLAUNCH(patch_to_latent<false>, dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd, nullptr,
-          m->dr, nullptr, N, m->p.ny, m->p.nx, m->C, batch);
+  NLAUNCH((patch_to_latent<false, false>), dim3(grid1(lat / 32)), dim3(256), 0, m->stream, m->dD, m->par + m->oWd,
+          nullptr, m->dr, nullptr, N, m->p.ny, m->p.nx, m->C, batch, nullptr, 0.f);
   // residual blocks, last to first; m->dr holds dL/dr_{l+1}
   for (int l = m->L - 1; l >= 0; --l) {
     const long long ob = l * m->blk_stride;
@@ -798,9 +826,10 @@ mlf_status mlf_nop_predict(mlf_nop* m, int32_t batch, const float* h, float* out
   if (!m || !h || !out) return MLF_EINVAL;
   mlf_status st = check_batch(m, batch);
   if (st != MLF_OK) return st;
-  if ((st = forward(m, batch, h)) != MLF_OK) return st;
-  const long long img = (long long)batch * m->p.n_layers * m->p.ny * m->p.nx;
-  NLAUNCH(axpy_out, dim3(grid1(img)), dim3(256), 0, m->stream, h, m->D, out, (float)m->p.scale, img);
+  if ((st = forward(m, batch, h, true)) != MLF_OK) return st;
+  const long long plane = (long long)m->p.ny * m->p.nx;
+  NLAUNCH(sub_mean_axpy, plane_grid(plane, (long long)batch * m->p.n_layers), dim3(256), 0, m->stream, h, m->D,
+          m->mean, out, (float)m->p.scale, plane);
   return MLF_OK;
 }
 
@@ -808,7 +837,7 @@ mlf_status mlf_nop_loss(mlf_nop* m, int32_t batch, const float* h0, const float*
   if (!m || !h0 || !h1 || !loss) return MLF_EINVAL;
   mlf_status st = check_batch(m, batch);
   if (st != MLF_OK) return st;
-  if ((st = forward(m, batch, h0)) != MLF_OK) return st;
+  if ((st = forward(m, batch, h0, false)) != MLF_OK) return st;
   return loss_and_grad(m, batch, h0, h1, false, loss);
 }
 
@@ -817,7 +846,7 @@ mlf_status mlf_nop_gradient(mlf_nop* m, int32_t batch, const float* h0, const fl
   if (!m || !h0 || !h1 || !loss) return MLF_EINVAL;
   mlf_status st = check_batch(m, batch);
   if (st != MLF_OK) return st;
-  if ((st = forward(m, batch, h0)) != MLF_OK) return st;
+  if ((st = forward(m, batch, h0, false)) != MLF_OK) return st;
   if ((st = loss_and_grad(m, batch, h0, h1, true, loss)) != MLF_OK) return st;
   if ((st = backward(m, batch)) != MLF_OK) return st;
   if (host_grad) {
