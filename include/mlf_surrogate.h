@@ -50,6 +50,13 @@ typedef struct mlf_nop mlf_nop;
 /* Number of FP32 parameters and workspace bytes.  EINVAL on bad sizes. */
 mlf_status mlf_nop_query_sizes(const mlf_nop_params* p, size_t* param_count, size_t* workspace_bytes);
 
+/* Create a handle on the current device.  workspace: workspace_bytes of
+ * device memory (256-byte aligned), owned by the caller and kept alive
+ * until mlf_nop_destroy; stream: hipStream_t for all work (NULL = default).
+ * EINVAL / EUNSUPPORTED on p as mlf_nop_query_sizes, EINVAL for a null or
+ * misaligned workspace or a null out; EDEVICE if the convolution kernels'
+ * LDS limits cannot be set on this device.  Parameters are undefined until
+ * mlf_nop_set_params. */
 mlf_status mlf_nop_create(const mlf_nop_params* p, void* workspace, void* stream, mlf_nop** out);
 
 /* Set (host FP32 vector of param_count) / read the parameters.  Setting
@@ -80,8 +87,12 @@ mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const 
  * Synchronises. */
 mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad);
 
+/* Adam steps taken since the parameters were last set (-1 for NULL). */
 int32_t mlf_nop_steps_done(const mlf_nop* m);
+/* Text of the last failure on this handle ("" if none); valid until the
+ * next call on it. */
 const char* mlf_nop_last_error(const mlf_nop* m);
+/* Free the host handle (not the workspace); EINVAL for NULL. */
 mlf_status mlf_nop_destroy(mlf_nop* m);
 
 #ifdef __cplusplus
