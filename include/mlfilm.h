@@ -207,8 +207,14 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
  * films (which already run many steps per launch). */
 mlf_status mlf_capture(mlf_handle* h, int32_t steps);
 
+/* Steps taken since init; mlf_load restores the count saved with the
+ * checkpoint (-1 for NULL). */
 int64_t mlf_steps_done(const mlf_handle* h);
+/* Text of the last failure on this handle ("" if none; a guard trip names
+ * the failing step); valid until the next call on it. */
 const char* mlf_last_error(const mlf_handle* h);
+/* Free the host handle and its captured graph (not the device buffers,
+ * which stay the caller's); EINVAL for NULL. */
 mlf_status mlf_destroy(mlf_handle* h);
 
 /* ---- batches of independent films ------------------------------------
@@ -297,9 +303,16 @@ mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* s
  * fastest.  Drops a captured graph.  Synchronises. */
 mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int32_t* seg_h, int32_t* persistent);
 
+/* Steps the batch has taken since it was created (-1 for NULL). */
 int64_t mlf_batch_steps_done(const mlf_batch* b);
-int32_t mlf_batch_failed_film(const mlf_batch* b);  /* -1 if none */
+/* Index of the film whose guard tripped in the last failing step (-1 if
+ * none, or for NULL). */
+int32_t mlf_batch_failed_film(const mlf_batch* b);
+/* Text of the last failure on this batch ("" if none); valid until the
+ * next call on it. */
 const char* mlf_batch_last_error(const mlf_batch* b);
+/* Free the batch's host state and graph (not the device buffers); EINVAL
+ * for NULL. */
 mlf_status mlf_batch_destroy(mlf_batch* b);
 
 /* ---- host helpers (no device work) ---------------------------------- */
