@@ -1,8 +1,10 @@
-// nop_kernels.hpp -- kernels of the convolutional neural-operator surrogate
-// (gfx950): BF16 MFMA implicit-GEMM 3x3 periodic convolutions (forward,
-// input gradient through the same kernel with flipped transposed weights,
-// weight gradient), and the FP32 VALU kernels around them (patch encoder,
-// pixel-shuffle decoder, GELU, residual sums, bias sums, MSE, Adam).
+// nop_kernels.hpp -- matrix-core kernels of the convolutional
+// neural-operator surrogate (gfx950): BF16 MFMA implicit-GEMM 3x3 periodic
+// convolutions (forward with its GELU / residual epilogues, the input
+// gradient through the same kernel with flipped transposed weights, and
+// the weight gradient).  The FP32 VALU kernels around them (patch encoder,
+// pixel-shuffle decoder, GELU gradient, reductions, MSE, Adam) are in
+// surrogate.hip.
 //
 // Latent tensors are NHWC: [batch][gy][gx][C], C a multiple of 32, x
 // fastest after the channels; the grid is periodic in both directions.
