@@ -6,7 +6,7 @@ written stencils, and against the free-energy variation for flat films.
 Friction: against the closed forms for one layer, the paper's two-layer
 mobility and its symmetric Pototsky form (tests/golden/mobility_2layer.txt),
 and an exact rational solve of the boundary-condition system in the paper's
-global coordinates for N = 1..4.
+global coordinates for N = 1..4, with and without slip lengths.
 """
 from fractions import Fraction
 
@@ -137,24 +137,27 @@ def test_single_layer_capillary_symbol(oracle_mod):
 
 
 # ------------------------------------------------------------- friction ----
-def exact_friction_global(h, mu, q):
+def exact_friction_global(h, mu, q, slip=None):
     """Solve the boundary-condition system of Sec. II.A.2 exactly (rational
     arithmetic) in the paper's global vertical coordinate z, with
-    u_i = a_i z^2 + b_i z + c_i, no slip at the substrate, continuity of
-    velocity and stress at every interface, the flux constraint in every layer
-    and no stress at the gas; returns 2 mu_i h_i a_i."""
+    u_i = a_i z^2 + b_i z + c_i: Eq. (no_slip) as printed,
+    u_i(z_{i-1} - beta_i) = u_{i-1}(z_{i-1}) with u_0 = 0 (beta = 0: no slip
+    at the substrate and continuity of velocity at every interface),
+    continuity of stress at every interface, the flux constraint in every
+    layer and no stress at the gas; returns 2 mu_i h_i a_i."""
     n = len(h)
     H = [Fraction(float(v)) for v in h]
     M = [Fraction(float(v)) for v in mu]
     Q = [Fraction(float(v)) for v in q]
+    B = [Fraction(float(v)) for v in (slip if slip is not None else [0.0] * n)]
     z = [Fraction(0)]
     for v in H:
         z.append(z[-1] + v)
     m = 3 * n
     A = [[Fraction(0)] * (m + 1) for _ in range(m)]
     r = 0
-    # u_1(0) = 0
-    A[r][2] = Fraction(1); r += 1
+    # u_1(z_0 - beta_1) = u_1(-beta_1) = 0
+    A[r][0] = B[0] ** 2; A[r][1] = -B[0]; A[r][2] = Fraction(1); r += 1
     for i in range(n):
         lo, hi = z[i], z[i + 1]
         a, b, c = 3 * i, 3 * i + 1, 3 * i + 2
@@ -167,9 +170,10 @@ def exact_friction_global(h, mu, q):
             # mu_i u_i'(z_i) = mu_{i+1} u_{i+1}'(z_i)
             A[r][a] = 2 * M[i] * hi; A[r][b] = M[i]
             A[r][a + 3] = -2 * M[i + 1] * hi; A[r][b + 3] = -M[i + 1]; r += 1
-            # u_i(z_i) = u_{i+1}(z_i)
-            A[r][a] = hi ** 2; A[r][b] = hi; A[r][c] = Fraction(1)
-            A[r][a + 3] = -hi ** 2; A[r][b + 3] = -hi; A[r][c + 3] = Fraction(-1); r += 1
+            # u_{i+1}(z_i - beta_{i+1}) = u_i(z_i)
+            zs = hi - B[i + 1]
+            A[r][a] = -hi ** 2; A[r][b] = -hi; A[r][c] = Fraction(-1)
+            A[r][a + 3] = zs ** 2; A[r][b + 3] = zs; A[r][c + 3] = Fraction(1); r += 1
         else:
             # u_N'(z_N) = 0 (mu_{N+1} = 0)
             A[r][a] = 2 * hi; A[r][b] = Fraction(1); r += 1
@@ -196,6 +200,43 @@ def test_friction_exact_rational(oracle_mod, n):
         got = oracle_mod.friction(h, mu, q)
         want = exact_friction_global(h, mu, q)
         assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_friction_exact_rational_slip(oracle_mod, n):
+    """Slip lengths at the substrate and at every liquid-liquid interface
+    (Eq. no_slip with beta_i > 0), against the exact solve of the printed
+    global-coordinate conditions; slip only at the substrate, only at an
+    upper interface, and everywhere."""
+    rng = np.random.default_rng(520 + n)
+    for trial in range(24):
+        h = rng.uniform(0.1, 3.0, size=n)
+        mu = 10 ** rng.uniform(-4, -2, size=n)
+        q = rng.normal(size=n) * 1e-3
+        slip = rng.uniform(0.0, 1.5, size=n)
+        if trial % 3 == 0:
+            slip[1:] = 0.0
+        elif trial % 3 == 1 and n > 1:
+            slip[:] = 0.0
+            slip[rng.integers(1, n)] = rng.uniform(0.05, 1.5)
+        got = oracle_mod.friction(h, mu, q, slip=slip)
+        want = exact_friction_global(h, mu, q, slip)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), (slip, got, want)
+
+
+def test_friction_slip_limits(oracle_mod):
+    """Two layers: a slip length at the liquid-liquid interface lowers the
+    friction's magnitude on a lone moving top layer (the layer below resists
+    less), and beta -> 0 recovers the no-slip solve continuously."""
+    h, mu, q = np.array([0.8, 0.5]), np.array([2e-3, 3e-3]), np.array([0.0, 1e-3])
+    f0 = oracle_mod.friction(h, mu, q)
+    prev = abs(f0[1])
+    for be in (1e-3, 0.1, 0.5, 2.0):
+        f = oracle_mod.friction(h, mu, q, slip=[0.0, be])
+        assert abs(f[1]) < prev
+        prev = abs(f[1])
+    f_small = oracle_mod.friction(h, mu, q, slip=[0.0, 1e-12])
+    assert np.abs(f_small - f0).max() <= 1e-9 * np.abs(f0).max()
 
 
 def test_friction_single_layer_closed_form(oracle_mod):
