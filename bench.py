@@ -8,10 +8,16 @@ of every layer (moments, pressures, friction, force, collision, streaming).
 
 Prints one JSON line with
   value     layer-lattice updates per second (LU/s) of the whole job,
-  roofline  achieved HBM bandwidth of the step kernel from algorithmic bytes
+  roofline  achieved bandwidth of the step kernel from algorithmic bytes
             (read 9 + write 9 populations per layer-node update) over its
-            event-timed launch duration, against the 8 TB/s peak,
-  cpu_baseline  the FP64 oracle on this host's cores on a bounded sample.
+            event-timed launch duration, against the 8 TB/s HBM peak and
+            against the library's streaming copy (mlf_stream_probe) timed on
+            a buffer of the same size in the same run.  The 1024^2 film's two
+            population buffers (2 x 108 MiB) stay in the 256 MB Infinity
+            Cache, so this point is cache-resident;
+  roofline_hbm  the same for the same film on 4096^2 (2 x 1.8 GB, HBM-bound),
+  cpu_baseline  the FP64 oracle on this host's cores (and on one core) on a
+            bounded sample.
 """
 import argparse
 import hashlib
@@ -28,10 +34,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_digest() -> str:
-    """Digest of the step kernel's source (kernel body and tile geometry)."""
+    """Digest of what the step kernel's code and launch depend on: the
+    kernel source, the library source that sets up and launches it, and
+    the compiler flags."""
+    from paper_2409_16659_amd import build as _b
+
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2409_16659_amd/csrc/step_kernel.hpp"), "rb") as fh:
-        h.update(fh.read())
+    for rel in ("paper_2409_16659_amd/csrc/step_kernel.hpp", "paper_2409_16659_amd/csrc/mlfilm.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(_b.HIPCC_FLAGS[:-2]).encode())  # flags without the include path
     return h.hexdigest()[:16]
 
 
@@ -64,7 +76,7 @@ def measured_traffic(workload: str, prec: str, launch):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(film, h0, budget_s: float, lattice="d2q9"):
+def _oracle_rate(film, h0, budget_s, lattice):
     import oracle
 
     o = oracle.Oracle(film, oracle.D1Q3 if lattice == "d1q3" else oracle.D2Q9)
@@ -78,16 +90,170 @@ def cpu_baseline(film, h0, budget_s: float, lattice="d2q9"):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    lu = film["n_layers"] * film["nx"] * film["ny"] * n
+    return film["n_layers"] * film["nx"] * film["ny"] * n / el, n, el
+
+
+def cpu_baseline(film, h0, budget_s: float, lattice="d2q9", single_s: float = 0.0):
+    """The FP64 oracle as it stands, on all host threads for ~budget_s and,
+    if single_s > 0, on one thread for ~single_s (same film)."""
+    import oracle
+
+    rate, n, el = _oracle_rate(film, h0, budget_s, lattice)
     host = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
             host = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": lu / el, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle", "host": host,
-            "sample": f"{n} FP64 {lattice.upper()} steps of the same {film['nx']}x{film['ny']} "
-                      f"{film['n_layers']}-layer film ({el:.1f} s)"}
+    out = {"value": rate, "unit": "LU/s", "cores": oracle.get_threads(), "kind": "oracle", "host": host,
+           "sample": f"{n} FP64 {lattice.upper()} steps of the same {film['nx']}x{film['ny']} "
+                     f"{film['n_layers']}-layer film ({el:.1f} s)"}
+    if single_s > 0:
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        try:
+            r1, n1, el1 = _oracle_rate(film, h0, single_s, lattice)
+        finally:
+            oracle.set_threads(threads)
+        out["single_core"] = {"value": r1, "unit": "LU/s", "cores": 1,
+                              "sample": f"{n1} steps of the same film ({el1:.1f} s)"}
+    return out
+
+
+def copy_ceiling(nbytes: int, reps: int = 10):
+    """Best rate of the library's streaming copy (mlf_stream_probe, 16-byte
+    buffer accesses, chunked and grid-stride schedules) over a buffer of
+    nbytes, plus read-only and write-only rates (chunked), in GB/s (copy:
+    bytes read + bytes written)."""
+    import torch
+
+    from paper_2409_16659_amd import mlfilm
+
+    nbytes = nbytes // 16 * 16
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(mode, sched):
+        mlfilm.stream_probe(mode, a, b, nbytes, sched, stream=st)
+        e0.record(st)
+        for _ in range(reps):
+            mlfilm.stream_probe(mode, a, b, nbytes, sched, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / reps * 1e-3
+        return (2 if mode == "copy" else 1) * nbytes / sec / 1e9
+
+    copies = {sched: rate("copy", sched) for sched in ("chunked", "grid")}
+    best = max(copies, key=copies.get)
+    out = {"copy_gbs": copies[best], "copy_schedule": best, "copy_gbs_other": copies["grid" if best == "chunked"
+                                                                                       else "chunked"],
+           "read_gbs": rate("read", "chunked"), "write_gbs": rate("write", "chunked"), "bytes": nbytes}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---- rocprofv3 results -> profiles/traffic.json ------------------------------
+def _strip_count(nx, w):
+    """Strips of the step kernel's launch (same arithmetic as the library)."""
+    n = (nx + (w - 4) - 1) // (w - 4)
+    wo = (nx + n - 1) // n
+    return (nx + wo - 1) // wo
+
+
+def step_grid_threads(film, launch):
+    """Work-items of one step_kernel dispatch of this film and launch shape
+    (the grid is padded to a multiple of the 8 XCDs)."""
+    w, sh = launch
+    tiles = _strip_count(film["nx"], w) * ((film["ny"] + sh - 1) // sh)
+    return (tiles + 7) // 8 * 8 * w
+
+
+def _read_csv(path):
+    import csv
+
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirname, suffix):
+    for root, _, files in os.walk(dirname):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {dirname}")
+
+
+def _step_rows(rows, grid, warmup, steps, grid_key):
+    sel = [r for r in rows if "step_kernel" in r["Kernel_Name"] and int(r[grid_key]) == grid]
+    sel.sort(key=lambda r: int(r["Dispatch_Id"]) if "Dispatch_Id" in r else int(r["Start_Timestamp"]))
+    if len(sel) < warmup + steps:
+        raise ValueError(f"expected {warmup + steps} step_kernel dispatches of grid {grid}, found {len(sel)}")
+    return sel[len(sel) - steps:]
+
+
+def _pmc_kib(dirname, grid, warmup, steps):
+    rows = _read_csv(_find(dirname, "counter_collection.csv"))
+    sel = _step_rows(rows, grid, warmup, steps, "Grid_Size")
+    return sum(float(r["Counter_Value"]) for r in sel) / len(sel)
+
+
+def _copy_kib(dirname, mode):
+    """Mean counter value (KiB) per dispatch of the streaming probe's copy
+    (mode 2), read (0) or write (1) kernel."""
+    rows = _read_csv(_find(dirname, "counter_collection.csv"))
+    tag = f"stream_probe_kernel<{mode}, 0>"
+    sel = [float(r["Counter_Value"]) for r in rows if tag in r["Kernel_Name"]]
+    if not sel:
+        raise ValueError(f"no {tag} dispatches in {dirname}")
+    return sum(sel) / len(sel)
+
+
+def ingest_profile(a):
+    """Turn one workload's rocprofv3 runs into its profiles/traffic.json
+    entry: kernel-trace statistics of the timed step_kernel dispatches and
+    HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the same counter reads for the library's streaming copy of a known
+    size."""
+    import statistics
+
+    from paper_2409_16659_amd import inputs, mlfilm
+
+    film, _, spec = inputs.workload(a.workload)
+    prec = a.precision or spec["precision"]
+    launch = (a.block_w, a.seg_h)
+    grid = step_grid_threads(film, launch)
+    n_lu = film["n_layers"] * film["nx"] * film["ny"]
+    bpl = mlfilm.bytes_per_update(prec)
+    alg = bpl * n_lu
+    kt = _step_rows(_read_csv(_find(a.ingest_kt, "kernel_trace.csv")), grid, a.warmup, a.steps, "Grid_Size_X")
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in kt]  # us
+    fetch_kib = _pmc_kib(a.ingest_fetch, grid, a.warmup, a.steps)
+    write_kib = _pmc_kib(a.ingest_write, grid, a.warmup, a.steps)
+    copy_bytes = n_lu * bpl // 2 // 16 * 16  # one population buffer, as bench.py --copy-probe
+    fetch_scale = copy_bytes / (1024.0 * _copy_kib(a.ingest_fetch_copy, 2))
+    write_scale = copy_bytes / (1024.0 * _copy_kib(a.ingest_write_copy, 2))
+    fb, wb = fetch_kib * 1024 * fetch_scale, write_kib * 1024 * write_scale
+    ent = {"kernel_digest": kernel_digest(), "launch": list(launch), "hbm_bytes_per_launch": fb + wb,
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "fetch_scale": round(fetch_scale, 4),
+           "write_scale": round(write_scale, 4), "algorithmic_bytes_per_launch": alg,
+           "trace_us": {"dispatches": len(dur), "mean": statistics.fmean(dur), "median": statistics.median(dur),
+                        "min": min(dur), "max": max(dur)}}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        data = {}
+    data[f"{a.workload}:{prec}"] = ent
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({"workload": a.workload, "precision": prec, **ent,
+                      "trace_gbs_median": alg / (ent["trace_us"]["median"] * 1e-6) / 1e9,
+                      "traffic_over_algorithmic": (fb + wb) / alg, "fetch_over_reads": fb / (alg / 2),
+                      "write_over_writes": wb / (alg / 2)}), flush=True)
 
 
 def bench_batch(args):
@@ -221,6 +387,72 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def film_point(workload, prec, args, steps, warmup, lattice="d2q9"):
+    """Time `steps` steps of one workload after `warmup` steps: LU/s over
+    the wall clock, and the step kernel's average launch duration from HIP
+    events recorded on the film's stream around the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_2409_16659_amd import inputs, mlfilm
+
+    film, h0, spec = inputs.workload(workload)
+    n_lu = film["n_layers"] * film["nx"] * film["ny"]
+    d1 = lattice == "d1q3"
+    g = mlfilm.Film(film, prec, check_every=-1, lattice=lattice)
+    g.init(h0)
+    pl = None if (args.autotune or d1) else profiled_launch(workload, prec)
+    if d1:
+        source = "fixed (D1Q3 kernels)"
+    elif (args.block_w or args.seg_h) and workload == args.workload:
+        g.set_launch(args.block_w, args.seg_h)
+        source = "given"
+    elif pl:
+        g.set_launch(*pl)
+        source = "autotuned (profiled run)"
+    else:
+        g.autotune(reps=3)  # library autotuner: times shapes, state unchanged
+        source = "autotuned"
+    launch = g.get_launch()
+    print(f"[bench] {workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
+          f"launch={launch} warmup={warmup} steps={steps}", file=sys.stderr, flush=True)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(g.stream)
+    g.step(steps)
+    ev1.record(g.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    m = g.mass()  # the state must still be valid after the timed steps
+    assert np.all(np.isfinite(m))
+    pop_bytes = g.pop_bytes
+    del g
+    torch.cuda.empty_cache()
+    return {"film": film, "h0": h0, "n_lu": n_lu, "launch": launch, "source": source, "wall": wall,
+            "kern_ms": kern_ms, "pop_bytes": pop_bytes}
+
+
+def roofline_block(pt, workload, prec, working_set, copy):
+    from paper_2409_16659_amd import mlfilm
+
+    bpl = mlfilm.bytes_per_update(prec)
+    achieved = bpl * pt["n_lu"] / (pt["kern_ms"] * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS,
+           "traffic": measured_traffic(workload, prec, pt["launch"]),
+           "bytes_per_lu": bpl, "lu_per_launch": pt["n_lu"], "kernel_ms": pt["kern_ms"],
+           "kernel": "step_kernel", "workload": workload, "launch": list(pt["launch"]),
+           "working_set": working_set}
+    if copy:
+        out["copy_ceiling"] = copy
+        out["frac_of_copy"] = achieved / copy["copy_gbs"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,7 +466,14 @@ def main():
     ap.add_argument("--seg-h", type=int, default=0, help="launch shape (see --block-w)")
     ap.add_argument("--autotune", action="store_true", help="always run the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="CPU-baseline budget; 0 disables it")
+                    help="CPU-baseline budget on all host threads; 0 disables the CPU baseline")
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0,
+                    help="CPU-baseline budget on one thread (0: none)")
+    ap.add_argument("--hbm-point", default="film3_2d_4096",
+                    help="workload of the HBM-bound roofline point timed after the main one ('' : none)")
+    ap.add_argument("--hbm-steps", type=int, default=200)
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip timing the streaming copy on buffers of the workloads' sizes")
     ap.add_argument("--batch", action="store_true",
                     help="batched stability scan instead: 256 uneven films, one launch per step "
                          "(graph-captured, autotuned) against the same films stepped back to back "
@@ -250,16 +489,29 @@ def main():
                     help="d1q3: pseudo-1D workloads on the D1Q3 lattice (film held in LDS, many steps "
                          "per launch)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="time a plain device copy of one population buffer instead (copy ceiling; "
-                         "the reference kernel for scaling rocprofv3 byte counters)")
+                    help="time the library's streaming probe (read, write, copy) on a buffer of one "
+                         "population buffer's size instead (the copy ceiling; the reference kernel "
+                         "for scaling rocprofv3 byte counters)")
+    ap.add_argument("--ingest-kt", default=None,
+                    help="with --ingest-fetch/--ingest-write/--ingest-fetch-copy/--ingest-write-copy: rocprofv3 "
+                         "output folders of this workload's bench run (kernel trace, FETCH_SIZE, WRITE_SIZE) and of "
+                         "its --copy-probe run (both counters); writes the workload's profiles/traffic.json entry "
+                         "for launch --block-w x --seg-h, timed dispatches = the last --steps (--hbm-steps for the "
+                         "HBM point) after --warmup; no GPU needed")
+    ap.add_argument("--ingest-fetch", default=None)
+    ap.add_argument("--ingest-write", default=None)
+    ap.add_argument("--ingest-fetch-copy", default=None)
+    ap.add_argument("--ingest-write-copy", default=None)
     args = ap.parse_args()
+
+    if args.ingest_kt:
+        return ingest_profile(args)
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.batch:
@@ -272,67 +524,20 @@ def main():
     if not os.path.exists(mlfilm._build.lib_path()):
         mlfilm._build.build()
     assert torch.cuda.is_available(), "bench needs a GPU"
-    film, h0, spec = inputs.workload(args.workload)
-    prec = args.precision or spec["precision"]
-    n_lu = film["n_layers"] * film["nx"] * film["ny"]
-    bytes_per_lu = mlfilm.bytes_per_update(prec)
+    prec = args.precision or inputs.WORKLOADS[args.workload]["precision"]
 
     if args.copy_probe:
-        nbytes = n_lu * bytes_per_lu // 2
-        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record()
-        for _ in range(reps):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / reps * 1e-3
-        print(json.dumps({"probe": "device_copy", "workload": args.workload, "bytes_read": nbytes,
-                          "bytes_written": nbytes, "us": sec * 1e6, "GBs": 2 * nbytes / sec / 1e9}), flush=True)
+        film, _, _ = inputs.workload(args.workload)
+        nbytes = film["n_layers"] * film["nx"] * film["ny"] * mlfilm.bytes_per_update(prec) // 2
+        out = copy_ceiling(nbytes)
+        out.update({"probe": "mlf_stream_probe", "workload": args.workload})
+        print(json.dumps(out), flush=True)
         return
 
     d1 = args.lattice == "d1q3"
-    g = mlfilm.Film(film, prec, check_every=-1, lattice=args.lattice)
-    g.init(h0)
-    pl = None if (args.autotune or d1) else profiled_launch(args.workload, prec)
-    if d1:
-        source = "fixed (D1Q3 kernels)"
-    elif args.block_w or args.seg_h:
-        g.set_launch(args.block_w, args.seg_h)
-        source = "given"
-    elif pl:
-        g.set_launch(*pl)
-        source = "autotuned (profiled run)"
-    else:
-        g.autotune(reps=3)  # library autotuner: times shapes, state unchanged
-        source = "autotuned"
-    launch = g.get_launch()
-    print(f"[bench] {args.workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
-          f"launch={launch} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    g.step(args.warmup)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(g.stream)
-    g.step(args.steps)
-    ev1.record(g.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = ev0.elapsed_time(ev1) / args.steps
-    # guard: the state must still be valid after the timed steps
-    m = g.mass()
-    assert np.all(np.isfinite(m))
-
-    value = n_lu * args.steps / wall
-    achieved = bytes_per_lu * n_lu / (kern_ms * 1e-3) / 1e9
-    traffic = None if d1 else measured_traffic(args.workload, prec, launch)
+    pt = film_point(args.workload, prec, args, args.steps, args.warmup, args.lattice)
+    film, n_lu = pt["film"], pt["n_lu"]
+    value = n_lu * args.steps / pt["wall"]
     out = {
         "metric": "layer-lattice updates/s & % HBM roofline; surrogate/batched speedup @1e-3 L2",
         "value": value,
@@ -340,18 +545,15 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": pt["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32"}.get(prec, "f32"),
         "data": "synthetic",
         "config": {"workload": args.workload, "layers": film["n_layers"], "nx": film["nx"], "ny": film["ny"],
-                   "storage": prec, "lattice": args.lattice.upper(), "tau": film["tau"], "launch": list(launch),
-                   "launch_source": source},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_lu": bytes_per_lu, "kernel_ms": kern_ms},
+                   "storage": prec, "lattice": args.lattice.upper(), "tau": film["tau"],
+                   "launch": list(pt["launch"]), "launch_source": pt["source"]},
     }
     if d1:
         # pseudo-1D films are tiny: the resident D1Q3 kernel keeps the film in
@@ -359,8 +561,26 @@ def main():
         # HBM traffic to price; the figure of merit is us/step
         out["roofline"] = None
         out["note"] = "D1Q3 pseudo-1D film: latency-bound (us/step), no HBM roofline"
+    else:
+        pop_bytes = pt["pop_bytes"]
+        copy = None if args.no_copy_ceiling else copy_ceiling(pop_bytes)
+        resident = 2 * pop_bytes <= 256 * 2 ** 20
+        ws = (f"2 x {pop_bytes / 2 ** 20:.0f} MiB population buffers: "
+              + ("resident in the 256 MB Infinity Cache (cache-resident point; the HBM-bound point is "
+                 "roofline_hbm)" if resident else "HBM-resident"))
+        out["roofline"] = roofline_block(pt, args.workload, prec, ws, copy)
+        if args.hbm_point and args.hbm_point != args.workload:
+            hp = args.hbm_point
+            hprec = inputs.WORKLOADS[hp]["precision"]
+            ph = film_point(hp, hprec, args, args.hbm_steps, max(10, args.hbm_steps // 10))
+            hcopy = None if args.no_copy_ceiling else copy_ceiling(ph["pop_bytes"])
+            hws = f"2 x {ph['pop_bytes'] / 2 ** 30:.2f} GiB population buffers: HBM-resident"
+            out["roofline_hbm"] = roofline_block(ph, hp, hprec, hws, hcopy)
+            out["roofline_hbm"]["lu_per_s"] = ph["n_lu"] * args.hbm_steps / ph["wall"]
+            out["roofline_hbm"]["steps"] = args.hbm_steps
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(film, h0, args.cpu_seconds, args.lattice)
+        out["cpu_baseline"] = cpu_baseline(film, pt["h0"], args.cpu_seconds, args.lattice,
+                                           args.cpu_single_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -315,6 +315,30 @@ const char* mlf_batch_last_error(const mlf_batch* b);
  * for NULL. */
 mlf_status mlf_batch_destroy(mlf_batch* b);
 
+/* ---- measurement helper ----------------------------------------------
+ * Streaming bandwidth probe.  Not a step of the method: one pass of a
+ * read, write or copy kernel over `bytes` bytes with 16-byte buffer
+ * accesses (the widest access the step kernel uses), to measure the rate a
+ * single-pass kernel reaches on a buffer of that size (the practical
+ * ceiling of the HBM-bound step) and to provide a kernel of exactly known
+ * traffic for scaling memory counters (READ: bytes read; WRITE: bytes
+ * written; COPY: both).
+ *  mode         mlf_stream_mode
+ *  schedule     0: chunked, every workgroup walks one contiguous range;
+ *               1: grid-stride, all lanes sweep the buffer together
+ *  nontemporal  nonzero: non-temporal cache policy on every access
+ *  src, dst     caller-owned device buffers of at least `bytes` bytes; dst
+ *               must be writable in every mode (READ may store 4 bytes at
+ *               dst to keep its loads alive); src is not read by WRITE
+ *  bytes        multiple of 16, 16 <= bytes <= 4 GiB - 16
+ *  blocks       workgroups of 256 lanes, 0: 64 per compute unit
+ *  stream       hipStream_t (NULL: default stream)
+ * Asynchronous; time it with events on the same stream.  EINVAL for bad
+ * sizes, modes or NULL pointers; EDEVICE if the launch fails. */
+typedef enum { MLF_STREAM_READ = 0, MLF_STREAM_WRITE = 1, MLF_STREAM_COPY = 2 } mlf_stream_mode;
+mlf_status mlf_stream_probe(int32_t mode, int32_t schedule, int32_t nontemporal, const void* src, void* dst,
+                            uint64_t bytes, int32_t blocks, void* stream);
+
 /* ---- host helpers (no device work) ---------------------------------- */
 
 /* Spreading coefficients from a full symmetric tension table

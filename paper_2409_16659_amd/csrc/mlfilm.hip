@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "d1q3_kernel.hpp"
+#include "stream_probe.hpp"
 #include "step_kernel.hpp"
 
 using mlf::kMaxLayers;
@@ -943,10 +944,52 @@ mlf_status finish_init(mlf_handle* h) {
 
 }  // namespace
 
+namespace {
+template <int MODE, int AUX>
+hipError_t stream_launch(const void* src, void* dst, uint32_t n16, uint32_t chunk, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((mlf::stream_probe_kernel<MODE, AUX>), dim3((unsigned)blocks), dim3(mlf::kStreamThreads), 0, s,
+                     static_cast<const unsigned char*>(src), static_cast<unsigned char*>(dst), n16, chunk);
+  return hipGetLastError();
+}
+template <int MODE>
+hipError_t stream_launch_m(bool nt, const void* src, void* dst, uint32_t n16, uint32_t chunk, int blocks,
+                           hipStream_t s) {
+  return nt ? stream_launch<MODE, 2>(src, dst, n16, chunk, blocks, s)
+            : stream_launch<MODE, 0>(src, dst, n16, chunk, blocks, s);
+}
+}  // namespace
+
 // ================================================================ C ABI ====
 extern "C" {
 
 const char* mlf_version(void) { return "mlfilm 0.1 gfx950"; }
+
+
+mlf_status mlf_stream_probe(int32_t mode, int32_t schedule, int32_t nontemporal, const void* src, void* dst,
+                            uint64_t bytes, int32_t blocks, void* stream) {
+  if (mode < MLF_STREAM_READ || mode > MLF_STREAM_COPY || (schedule != 0 && schedule != 1) || blocks < 0)
+    return MLF_EINVAL;
+  if (!dst || (mode != MLF_STREAM_WRITE && !src)) return MLF_EINVAL;
+  if (bytes < 16 || bytes % 16 != 0 || bytes > 0xfffffff0ull) return MLF_EINVAL;
+  const uint32_t n16 = (uint32_t)(bytes / 16);
+  if (blocks == 0) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return MLF_EDEVICE;
+    blocks = 64 * std::max(1, ncu);
+  }
+  // no more workgroups than 16-byte elements per lane group
+  blocks = (int)std::min<uint64_t>((uint64_t)blocks, ((uint64_t)n16 + mlf::kStreamThreads - 1) / mlf::kStreamThreads);
+  blocks = std::max(blocks, 1);
+  const uint32_t chunk = schedule == 0 ? (uint32_t)(((uint64_t)n16 + blocks - 1) / blocks) : 0u;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (mode == MLF_STREAM_READ) e = stream_launch_m<mlf::kStreamRead>(nontemporal != 0, src, dst, n16, chunk, blocks, s);
+  else if (mode == MLF_STREAM_WRITE) e = stream_launch_m<mlf::kStreamWrite>(nontemporal != 0, dst, dst, n16, chunk, blocks, s);
+  else e = stream_launch_m<mlf::kStreamCopy>(nontemporal != 0, src, dst, n16, chunk, blocks, s);
+  return e == hipSuccess ? MLF_OK : MLF_EDEVICE;
+}
 
 mlf_status mlf_query_sizes(const mlf_params* p, size_t* pop_bytes, size_t* scratch_bytes) {
   mlf_status st = validate(p, nullptr);

@@ -139,6 +139,8 @@ def load_library():
         "mlf_friction_matrix": (st, [C.c_int32, _D, _D, _D, _D]),
         "mlf_friction_matrix_slip": (st, [C.c_int32, _D, _D, _D, _D, _D]),
         "mlf_version": (C.c_char_p, []),
+        "mlf_stream_probe": (st, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                  C.c_int32, C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +238,29 @@ def friction_matrix(h, mu, slip=None):
     if rc:
         raise MlfError(rc, "mlf_friction_matrix")
     return K, rate.value
+
+
+STREAM_MODES = {"read": 0, "write": 1, "copy": 2}
+STREAM_SCHEDULES = {"chunked": 0, "grid": 1}
+
+
+def stream_probe(mode, src, dst, nbytes, schedule="chunked", nontemporal=False, blocks=0, stream=None):
+    """One pass of the library's streaming probe (``mlf_stream_probe``) over
+    ``nbytes`` of the device tensors ``src``/``dst``; asynchronous on
+    ``stream`` (default: torch's current stream)."""
+    import torch
+
+    lib = load_library()
+    nbytes = int(nbytes)
+    for t in (src, dst):
+        if t is not None and t.numel() * t.element_size() < nbytes:
+            raise ValueError("buffer smaller than nbytes")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.mlf_stream_probe(STREAM_MODES[mode], STREAM_SCHEDULES[schedule], 1 if nontemporal else 0,
+                              C.c_void_p(src.data_ptr() if src is not None else 0), C.c_void_p(dst.data_ptr()),
+                              nbytes, int(blocks), C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MlfError(rc, "mlf_stream_probe")
 
 
 def rupture_threshold(film):
