@@ -134,13 +134,24 @@ def test_adam_step_matches_reference_update(mlf, torch_cuda):
 
 
 def test_shift_by_whole_patches(mlf, torch_cuda):
-    s, net, vec, h0, h1, t0, t1 = setup(mlf, torch_cuda, 64, seed=3)
-    t0s = torch_cuda.roll(t0, (4, 8), (2, 3)).contiguous()
+    """A shift of the input by whole patches shifts the increment: the
+    periodic convolutions accumulate every output in a fixed order whatever
+    its position.  The heights lie on a 2^-8 grid, so every partial sum of
+    the per-layer mean that centres the input is exact in FP32 (values below
+    2^13 with 8 fractional bits) and the network sees exactly the shifted
+    input; only the decoder output's own plane mean (the last operation,
+    no bfloat16 rounding after it) sums in another order."""
+    torch = torch_cuda
+    s, net, vec, _, _, _, _ = setup(mlf, torch, 64, seed=3)
+    rng = np.random.default_rng(33)
+    h0 = (1.0 + np.rint(2.56 * rng.normal(size=(2, 3, 16, 256))) / 256.0).astype(np.float32)
+    t0 = torch.from_numpy(h0).cuda()
+    t0s = torch.roll(t0, (4, 8), (2, 3)).contiguous()
     da = (s.predict(t0).cpu().numpy().astype(np.float64) - h0) / 1e-2
     db = (s.predict(t0s).cpu().numpy().astype(np.float64) - t0s.cpu().numpy()) / 1e-2
-    # the per-layer means sum in another order; their last-bit differences
-    # move some bfloat16 roundings, as in the comparison with the reference
-    assert rel(np.roll(da, (4, 8), (2, 3)), db) <= 2e-3
+    e = rel(np.roll(da, (4, 8), (2, 3)), db)
+    print(f"shift by (1, 2) patches: increment rel L2 {e:.2e}", flush=True)
+    assert e <= 1e-4
 
 
 def test_training_reduces_the_loss(mlf, torch_cuda):
