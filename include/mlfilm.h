@@ -150,6 +150,23 @@ mlf_status mlf_read_device(mlf_handle* h, double* hgt, double* ux, double* uy);
  * host array [N].  Synchronises. */
 mlf_status mlf_layer_mass(mlf_handle* h, double* mass);
 
+/* Allocation-free form of mlf_layer_mass, for callers that cannot allocate
+ * device memory or synchronise (code under HIP graph capture, serving
+ * loops).  The same per-layer FP64 sums in the same fixed order (results
+ * bit-identical to mlf_layer_mass), but the reduction partials live in a
+ * fixed 16 KiB device array inside the library (one per GPU, taken on the
+ * first call on each device and held until the process ends; the partial
+ * count does not depend on the film size, so every film fits) instead of
+ * the handle's scratch buffer, and the result goes to the caller-owned
+ * device array mass_dev[N] (FP64, written by a kernel; no memset, no copy).
+ * Asynchronous on the handle's stream, no host synchronisation; call with
+ * the handle's device current.  Calls that overlap on one GPU (any handle,
+ * any stream) share that array and race: order them on one stream or
+ * synchronise between them.  Allocates nothing.  EINVAL for NULL pointers
+ * or before init; EDEVICE if the array's address cannot be taken or a
+ * launch fails. */
+mlf_status mlf_layer_mass_static(mlf_handle* h, double* mass_dev);
+
 /* Per-layer minimum height min_x h_i in FP64, host array [N]; the heights
  * are bit-identical to those mlf_read returns (same summation order).
  * Synchronises.  A layer has ruptured once it shows its first hole, i.e.

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -959,6 +960,63 @@ hipError_t stream_launch_m(bool nt, const void* src, void* dst, uint32_t n16, ui
 }
 }  // namespace
 
+// ---- allocation-free per-layer mass -----------------------------------------
+// Reduction partials of mlf_layer_mass_static live in this fixed array, one
+// copy per GPU, for the life of the process.  Host code never uses the
+// array's name as an address: it takes each device's address once with
+// hipGetSymbolAddress and passes that pointer to the kernels.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)kRedBlocks * kMaxLayers * sizeof(double);  // 16 KiB
+constexpr int kStaticMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kStaticMaxDevices];  // device address of `scratch` per device, null until taken
+
+// Address of `scratch` on the current device; set-up on the first call per device.
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kStaticMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return hipSuccess;
+}
+
+// out[i] = base[i] + fixed-order sum of the partials of layer i (the same
+// order as finish_partials); base[i] = nx ny h_ref_i, formed on the host.
+struct MassBase {
+  double v[kMaxLayers];
+};
+__global__ void __launch_bounds__(256) finish_mass(const double* __restrict__ part, double* __restrict__ out,
+                                                   int nblocks, int nl, MassBase base) {
+  __shared__ double red[256];
+  for (int i = 0; i < nl; ++i) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += part[b * kMaxLayers + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = base.v[i] + red[0];
+    __syncthreads();
+  }
+}
+}  // namespace
+
 // ================================================================ C ABI ====
 extern "C" {
 
@@ -1377,6 +1435,31 @@ mlf_status mlf_layer_mass(mlf_handle* h, double* mass) {
   HIPCHK(hipStreamSynchronize(h->stream));
   const double nn = (double)p.nx * (double)p.ny;
   for (int i = 0; i < p.n_layers; ++i) mass[i] = nn * h->hbar[i] + dev[i];
+  return MLF_OK;
+}
+
+mlf_status mlf_layer_mass_static(mlf_handle* h, double* mass_dev) {
+  if (!h || !mass_dev) return MLF_EINVAL;
+  if (!h->initialised) return fail(h, MLF_EINVAL, "mass before init");
+  const mlf_params& p = h->p;
+  void* sp = nullptr;
+  HIPCHK(static_scratch(&sp));
+  double* part = static_cast<double*>(sp);
+  const Layers L = layers_of(h);
+  by_storage(h, [&](auto* rt, auto* st) {
+    using R = std::remove_pointer_t<decltype(rt)>;
+    using S = std::remove_pointer_t<decltype(st)>;
+    const PopView<R, S> f{static_cast<unsigned char*>(h->pop[h->cur]), (long long)h->plane, p.n_layers,
+                          nq_of(&p)};
+    hipLaunchKernelGGL((mass_partials<R, S>), dim3(kRedBlocks), dim3(256), 0, h->stream, f, part, p.nx, p.ny,
+                       h->pitch, p.n_layers, L);
+  });
+  HIPCHK(hipGetLastError());
+  MassBase base{};
+  const double nn = (double)p.nx * (double)p.ny;
+  for (int i = 0; i < p.n_layers; ++i) base.v[i] = nn * h->hbar[i];
+  hipLaunchKernelGGL(finish_mass, dim3(1), dim3(256), 0, h->stream, part, mass_dev, kRedBlocks, p.n_layers, base);
+  HIPCHK(hipGetLastError());
   return MLF_OK;
 }
 

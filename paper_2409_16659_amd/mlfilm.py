@@ -87,6 +87,7 @@ def load_library():
         "mlf_read_device": (st, [H, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_layer_mass": (st, [H, _D]),
         "mlf_layer_min": (st, [H, _D]),
+        "mlf_layer_mass_static": (st, [H, C.c_void_p]),
         "mlf_step_until": (st, [H, C.c_int64, C.c_int32, _D, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
         "mlf_read_populations": (st, [H, _D]),
         "mlf_write_populations": (st, [H, _D]),
