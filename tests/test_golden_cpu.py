@@ -1,0 +1,36 @@
+"""Consistency of the oracle-written fixture the full-size parity test
+compares against (tests/golden/film3_1024_t10k.npz, written by
+tests/golden/make_film3_1024_t10k.py): shapes and row sets, finite positive
+heights, the oracle's own per-layer mass conservation over the 10^4 steps,
+and the state of the linear regime (the perturbation has neither vanished
+nor grown to the film's scale)."""
+import os
+
+import numpy as np
+
+from paper_2409_16659_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "film3_1024_t10k.npz")
+
+
+def test_t10k_fixture_is_consistent():
+    ref = np.load(GOLDEN)
+    film, h0, _ = inputs.workload("film3_2d_1024")
+    n, ny, nx = film["n_layers"], film["ny"], film["nx"]
+    assert int(ref["steps"]) == 10_000
+    assert np.array_equal(ref["rows_h"], np.arange(0, ny, 16))
+    assert np.array_equal(ref["rows_u"], np.arange(0, ny, 64))
+    assert ref["h"].shape == (n, ny // 16, nx)
+    assert ref["ux"].shape == ref["uy"].shape == (n, ny // 64, nx)
+    h = ref["h"]
+    assert np.all(np.isfinite(h)) and np.all(h > film["hstar"])
+    # the initial mass is the seeded input's own sum
+    assert np.allclose(ref["mass0"], h0.sum(axis=(1, 2)), rtol=1e-14, atol=0)
+    # the oracle conserves every layer's mass (FP64)
+    assert np.abs(ref["mass"] - ref["mass0"]).max() <= 1e-12 * ref["mass0"].max()
+    # layer means unchanged; perturbations small (linear regime) but alive
+    hbar = np.array([1.0, 0.8, 0.6])
+    assert np.abs(h.mean(axis=(1, 2)) - hbar).max() < 1e-4
+    pert = np.abs(h - h.mean(axis=(1, 2), keepdims=True)).max()
+    assert 1e-7 < pert < 1e-2
+    assert np.abs(ref["ux"]).max() < 1e-3 and np.abs(ref["ux"]).max() > 0

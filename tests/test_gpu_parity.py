@@ -8,6 +8,7 @@ Gates (relative to the reference's maximum):
   mass:  per-layer relative drift <= 1e-12 (FP64 storage)
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -209,25 +210,52 @@ def test_fp32_three_layer_full_size(mlf, oracle_mod):
     check(g, o, 1e-5, 1e-4)
 
 
-def test_fp32_full_size_parity_horizon(mlf):
-    """The FP32 bar over the workload's first 10^4 steps at full size, in the
-    benchmark's launch shape: against the FP64 path (pinned to the oracle to
-    1e-12 above), e_h <= 1e-5 and e_U <= 1e-4; per-layer mass of the FP32
-    run within 1e-9 (the oracle at this size and length takes ~15 minutes
-    on 16 cores)."""
+GOLDEN_T10K = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "film3_1024_t10k.npz")
+
+
+@pytest.mark.parametrize("prec,tol_h,tol_u,tol_pert,tol_m", [("f32", 1e-5, 1e-4, 1e-3, 1e-9),
+                                                            ("f64", 1e-12, 1e-8, 1e-8, 1e-12)])
+def test_full_size_parity_horizon_vs_oracle(mlf, prec, tol_h, tol_u, tol_pert, tol_m):
+    """The full 1024^2 three-layer workload over its first 10^4 steps (the
+    linear regime) against the FP64 oracle's state, written by
+    tests/golden/make_film3_1024_t10k.py: every stored height row (every
+    16th row) and velocity row (every 64th), element by element.  Bars:
+    e_h <= 1e-5 / 1e-12 and e_U <= 1e-4 / 1e-8 (FP32 / FP64, relative to
+    the reference's maximum); the height error relative to the largest
+    perturbation max|h_ref - mean h_ref| <= 1e-3 / 1e-8; per-layer mass
+    against the oracle's <= 1e-9 / 1e-12.  FP32 runs in the benchmark's
+    launch shape.
+
+    The FP64 velocity bar follows from the oracle's own rounding: it takes
+    the stencils of absolute interface heights z ~ 2.4, whose FP64 rounding
+    puts ~1e-15 on the Laplacian and, through the capillary pressure
+    (gamma ~ 1e-2) and the flux's friction relaxation time (~170 steps),
+    ~1e-15 absolute on U, against max|U| = 2.7e-7 at this time: ~5e-9
+    relative (measured 1.5e-9).  The heights meet the 1e-12 bar (6e-13)."""
+    ref = np.load(GOLDEN_T10K)
+    assert int(ref["steps"]) == 10_000
     film, h0, _ = inputs.workload("film3_2d_1024")
-    launch = bench_launch()
-    say(f"case film3_2d_1024 f32 vs f64, 10^4 steps, launch {launch}")
-    a = mlf.Film(film, "f32")
-    a.set_launch(*launch)
-    b = mlf.Film(film, "f64")
-    for g in (a, b):
-        g.init(h0)
-    m0 = b.mass()
-    a.step(10_000)
-    b.step(10_000)
-    check(a, b, 1e-5, 1e-4)
-    assert np.abs(a.mass() - m0).max() <= 1e-9 * m0.max()
+    launch = bench_launch() if prec == "f32" else None
+    say(f"case film3_2d_1024 {prec} vs oracle state at 10^4 steps, launch {launch}")
+    g = mlf.Film(film, prec)
+    if launch:
+        g.set_launch(*launch)
+    g.init(h0)
+    g.step(10_000)
+    h, ux, uy = g.read()
+    rh, ru = ref["rows_h"], ref["rows_u"]
+    href = ref["h"]
+    eh = err(h[:, rh], href)
+    uscale = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max())
+    eu = float(max(np.abs(ux[:, ru] - ref["ux"]).max(), np.abs(uy[:, ru] - ref["uy"]).max()) / uscale)
+    pert = np.abs(href - href.mean(axis=(1, 2), keepdims=True)).max()
+    ep = float(np.abs(h[:, rh] - href).max() / pert)
+    em = float(np.abs(g.mass() - ref["mass"]).max() / ref["mass"].max())
+    say(f"   e_h={eh:.3e} e_U={eu:.3e} e_h/perturbation={ep:.3e} (perturbation {pert:.2e}) mass {em:.2e}")
+    assert eh <= tol_h, eh
+    assert eu <= tol_u, eu
+    assert ep <= tol_pert, ep
+    assert em <= tol_m, em
 
 
 # ------------------------------------------------------------ properties --
