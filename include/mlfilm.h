@@ -198,7 +198,13 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f);
 mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes);
 mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
 
-/* Launch shape of the step kernel: block_w threads (64, 128, 192 or 256),
+/* D2Q9 films one row high (ny == 1) with F64 or F32 storage whose state
+ * fits one workgroup's LDS (11 N nx values within 160 KiB, nx <= 1024)
+ * run many steps per launch with the film held on chip, with results
+ * bit-identical to the step kernel; once a graph is captured
+ * (mlf_capture) mlf_step replays it with the step kernel instead.
+ *
+ * Launch shape of the step kernel: block_w threads (64, 128, 192 or 256),
  * one per column of a strip of block_w - 4 columns plus two halo columns on
  * each side, and seg_h rows per workgroup (>= 1).  Results do not depend on
  * the shape.  0 = default.  D1Q3 films keep their fixed kernel shapes (the
@@ -270,6 +276,11 @@ mlf_status mlf_batch_init_device(mlf_batch* b, int32_t film, const double* hgt, 
  * array of n device pointers, hgts[f] of film f's shape [N][ny][nx].  Same
  * checks as mlf_init for each film, one synchronisation for all. */
 mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts);
+/* As mlf_batch_init_device_all with initial velocities: uxs, uys host
+ * arrays of n device pointers to FP64 [N][ny][nx] (both NULL: U = 0, the
+ * plain form), f = f^eq(h, U) for every film. */
+mlf_status mlf_batch_init_device_all_u(mlf_batch* b, const double* const* hgts, const double* const* uxs,
+                                       const double* const* uys);
 
 /* Advance every film by nsteps >= 0 steps: one launch per step, or replays
  * of the captured graph where it fits.  The guard flags of all films are
@@ -331,6 +342,25 @@ const char* mlf_batch_last_error(const mlf_batch* b);
 /* Free the batch's host state and graph (not the device buffers); EINVAL
  * for NULL. */
 mlf_status mlf_batch_destroy(mlf_batch* b);
+
+/* Stokes-limit velocities of a height field: U_i = q_i / h_i with the
+ * flux q at which the pressure force -h_i grad p_i and the inter-layer
+ * friction balance, q = K^-1 diag(h) grad p = -M grad Delta (M the
+ * mobility of Eq. thin_film_equation_n, Delta the pressure jumps), the
+ * flux of the thin-film equation's Stokes limit (Sec. II.B).  Pressures,
+ * stencils and friction as in the step (isotropic 9-point gradient and
+ * Laplacian, Eqs. Laplace_pressure and disjoining_pressure; friction from
+ * the boundary conditions of Sec. II.A.2 without slip), in FP64.  For a
+ * restart f = f^eq(h, U) (mlf_init_device) that starts the scheme on its
+ * friction-dominated trajectory instead of from rest.
+ *  p       film parameters (n_layers, nx, ny, hstar, exponents, gamma, mu,
+ *          spread; precision, tau and lattice are ignored)
+ *  hgt     device FP64 [N][ny][nx], h > 0; ux, uy device FP64 [N][ny][nx]
+ *          (caller-owned, not aliased with hgt)
+ *  stream  hipStream_t (NULL: default); asynchronous.
+ * EINVAL for bad parameters or NULL pointers, EUNSUPPORTED for slip
+ * lengths != 0, EDEVICE if the launch fails. */
+mlf_status mlf_stokes_velocity(const mlf_params* p, const double* hgt, double* ux, double* uy, void* stream);
 
 /* ---- measurement helper ----------------------------------------------
  * Streaming bandwidth probe.  Not a step of the method: one pass of a

@@ -11,8 +11,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlfilm.so")
-SOURCES = [os.path.join(CSRC, "mlfilm.hip"), os.path.join(CSRC, "surrogate.hip")]
+SOURCES = [os.path.join(CSRC, "mlfilm.hip"), os.path.join(CSRC, "surrogate.hip"), os.path.join(CSRC, "stokes.hip")]
 HEADERS = [os.path.join(CSRC, "step_kernel.hpp"), os.path.join(CSRC, "nop_kernels.hpp"),
+           os.path.join(CSRC, "stream_probe.hpp"), os.path.join(CSRC, "d1q3_kernel.hpp"),
+           os.path.join(CSRC, "d2q9_row_kernel.hpp"),
            os.path.join(ROOT, "include", "mlfilm.h"), os.path.join(ROOT, "include", "mlf_surrogate.h")]
 ARCH = os.environ.get("MLF_OFFLOAD_ARCH", "gfx950")
 

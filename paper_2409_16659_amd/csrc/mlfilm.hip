@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "d1q3_kernel.hpp"
+#include "d2q9_row_kernel.hpp"
 #include "stream_probe.hpp"
 #include "step_kernel.hpp"
 
@@ -835,6 +836,59 @@ hipError_t d1_advance(mlf_handle* h, int steps) {
   return h->p.precision == MLF_F64 ? d1_advance_c<double>(h, steps) : d1_advance_c<float>(h, steps);
 }
 
+// ---- D2Q9 films one row high: resident multi-step kernel ------------------
+
+bool row_resident(const mlf_params& p) {
+  if (p.lattice != MLF_D2Q9 || p.ny != 1) return false;
+  if (p.precision != MLF_F64 && p.precision != MLF_F32) return false;
+  const size_t c = p.precision == MLF_F64 ? 8 : 4;
+  return p.nx <= mlf::kRowMaxPerThread * mlf::kRowThreads &&
+         (size_t)11 * p.n_layers * p.nx * c <= mlf::kRowMaxLds;
+}
+
+template <typename C, int NL, bool T1, int EA, int EB>
+hipError_t row_launch_nl(mlf_handle* h, int steps) {
+  mlf::StepConsts<C> kc = make_consts<C>(h);
+  const mlf_params& p = h->p;
+  const size_t lds = mlf::row_resident_lds<C>(p.nx, NL);
+  auto kern = mlf::d2q9_row_resident<C, NL, T1, EA, EB>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int threads = std::min(mlf::kRowThreads, std::max(64, (p.nx + 63) / 64 * 64));
+  hipLaunchKernelGGL(kern, dim3(1), dim3((unsigned)threads), lds, h->stream, static_cast<const C*>(h->pop[h->cur]),
+                     static_cast<C*>(h->pop[h->cur ^ 1]), kc, steps);
+  h->cur ^= 1;
+  return hipGetLastError();
+}
+
+template <typename C, bool T1, int EA, int EB>
+hipError_t row_launch_t(mlf_handle* h, int steps) {
+  switch (h->p.n_layers) {
+    case 1: return row_launch_nl<C, 1, T1, EA, EB>(h, steps);
+    case 2: return row_launch_nl<C, 2, T1, EA, EB>(h, steps);
+    case 3: return row_launch_nl<C, 3, T1, EA, EB>(h, steps);
+    default: return row_launch_nl<C, 4, T1, EA, EB>(h, steps);
+  }
+}
+
+// Advances a one-row D2Q9 film by `steps` (1..kD1MaxStepsPerLaunch); flips h->cur.
+template <typename C>
+hipError_t row_advance_c(mlf_handle* h, int steps) {
+  const bool t1 = h->p.tau == 1.0;
+  const bool e93 = h->p.exp_a == 9 && h->p.exp_b == 3;
+  if (t1 && e93) return row_launch_t<C, true, 9, 3>(h, steps);
+  if (t1) return row_launch_t<C, true, 0, 0>(h, steps);
+  if (e93) return row_launch_t<C, false, 9, 3>(h, steps);
+  return row_launch_t<C, false, 0, 0>(h, steps);
+}
+
+hipError_t row_advance(mlf_handle* h, int steps) {
+  return h->p.precision == MLF_F64 ? row_advance_c<double>(h, steps) : row_advance_c<float>(h, steps);
+}
+
 int step_occupancy(const mlf_handle* h) {
   int occ = 0;
   by_storage(h, [&](auto* rt, auto* st) {
@@ -1302,12 +1356,15 @@ mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
   if (!h || nsteps < 0) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_step before mlf_init");
   const int every = h->p.check_every;
-  if (h->p.lattice == MLF_D1Q3) {
+  // D1Q3 films, and D2Q9 films one row high without a captured graph, run
+  // many steps per launch with the film held in LDS
+  const bool row = !h->graph && row_resident(h->p);
+  if (h->p.lattice == MLF_D1Q3 || row) {
     int64_t left = nsteps, since = 0;
     while (left > 0) {
       int64_t chunk = std::min<int64_t>(left, kD1MaxStepsPerLaunch);
       if (every > 0) chunk = std::min<int64_t>(chunk, every - since);
-      HIPCHK(d1_advance(h, (int)chunk));
+      HIPCHK(row ? row_advance(h, (int)chunk) : d1_advance(h, (int)chunk));
       left -= chunk;
       since += chunk;
       h->steps += chunk;
@@ -2012,8 +2069,12 @@ mlf_status mlf_batch_init_device(mlf_batch* b, int32_t film, const double* hgt, 
   return MLF_OK;
 }
 
-mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
-  if (!b || !hgts) return MLF_EINVAL;
+mlf_status mlf_batch_init_device_all_u(mlf_batch* b, const double* const* hgts, const double* const* uxs,
+                                       const double* const* uys) {
+  if (!b || !hgts || (!uxs) != (!uys)) return MLF_EINVAL;
+  if (uxs)
+    for (int f = 0; f < b->n; ++f)
+      if (!uxs[f] || !uys[f]) return bfail(b, MLF_EINVAL, "null velocity array");
   double* sums = reinterpret_cast<double*>(b->scratch + kBatchSumOff);
   for (int f = 0; f < b->n; ++f) {
     if (!hgts[f]) return bfail(b, MLF_EINVAL, "null height array");
@@ -2049,7 +2110,9 @@ mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
     mlf_handle* h = b->film[f];
     h->cur = b->cur;
     mlf_status st = zero_buffers(h);
-    if (st == MLF_OK) st = launch_init(h, hgts[f], nullptr, nullptr, (long long)h->p.nx * h->p.ny, 0, 0, h->p.ny);
+    if (st == MLF_OK)
+      st = launch_init(h, hgts[f], uxs ? uxs[f] : nullptr, uys ? uys[f] : nullptr, (long long)h->p.nx * h->p.ny, 0,
+                       0, h->p.ny);
     if (st != MLF_OK) return bfail(b, st, h->err);
   }
   BHIPCHK(hipMemsetAsync(batch_flags(b), 0, b->n * sizeof(int), b->stream));
@@ -2061,6 +2124,10 @@ mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
   }
   b->table_dirty = true;
   return MLF_OK;
+}
+
+mlf_status mlf_batch_init_device_all(mlf_batch* b, const double* const* hgts) {
+  return mlf_batch_init_device_all_u(b, hgts, nullptr, nullptr);
 }
 
 mlf_status mlf_batch_read_device_all(mlf_batch* b, double* const* outs) {

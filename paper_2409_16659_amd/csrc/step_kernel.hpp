@@ -324,6 +324,208 @@ __device__ inline int tile_of_block(int b, int nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// Pressures p_i = sum_{j>=i} Delta_j of one node (Eqs. Laplace_pressure,
+// disjoining_pressure, wetting_potential) from the interface deviations of
+// its 3x3 neighbourhood: z(i, r, c) for interface i + 1, rows r = 0, 1, 2 at
+// y - 1, y, y + 1 and columns c at x - 1, x, x + 1 (read where used, so
+// that they are not all live at once).
+template <typename C, int NL, int EA, int EB, typename Z>
+__device__ inline void node_pressure(const StepConsts<C>& kc, Z&& z, C (&p)[NL]) {
+  C dzv[NL + 1], lap[NL + 1], qq[NL + 1];
+  dzv[0] = C(0);
+  qq[0] = C(0);
+  lap[0] = C(0);
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const C sw = z(i, 0, 0), s = z(i, 0, 1), se = z(i, 0, 2);
+    const C wv = z(i, 1, 0), cc = z(i, 1, 1), e = z(i, 1, 2);
+    const C nw = z(i, 2, 0), nn = z(i, 2, 1), ne = z(i, 2, 2);
+    const C gx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
+    const C gy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
+    lap[i + 1] = (C(4) * ((e + wv) + (nn + s)) + ((ne + nw) + (se + sw)) - C(20) * cc) * C(1.0 / 6.0);
+    qq[i + 1] = gx * gx + gy * gy;
+    dzv[i + 1] = cc;
+  }
+  C sphi[NL + 1], dup[NL + 1], ddn[NL + 1];
+#pragma unroll
+  for (int i = 0; i <= NL; ++i) sphi[i] = dup[i] = ddn[i] = C(0);
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+#pragma unroll
+    for (int kk = 1; kk <= NL - l; ++kk) {
+      // pairs with S_lk = 0 contribute exactly zero (uniform branch)
+      if (!(kc.pairs >> (l * 4 + kk - 1) & 1u)) continue;
+      const C d = kc.dbar[l][kk - 1] + (dzv[l + kk] - dzv[l]);
+      const C rd = rcp(d);
+      const C rr = kc.khs[kk - 1] * rd;
+      C ra, rb;
+      pow_ab<EA, EB>(rr, kc, ra, rb);
+      C phi, dphi;
+      wetting<EA, EB>(kc, l, kk, ra, rb, rd, phi, dphi);
+      sphi[l] += phi;
+      dup[l] += dphi;
+      ddn[l + kk] += dphi * (C(1) + C(0.5) * qq[l]);
+    }
+  }
+  C acc = C(0);
+#pragma unroll
+  for (int i = NL; i >= 1; --i) {
+    const C delta = -(kc.gamma[i - 1] + sphi[i]) * lap[i] - dup[i] * (C(1) + C(0.5) * qq[i]) + ddn[i];
+    acc += delta;
+    p[i - 1] = acc;
+  }
+}
+
+// Force (pressure gradient from the 3x3 pressure neighbourhood pz(i, r, c),
+// laid out as z above and read where used, plus friction), and the BGK
+// collision with forcing of one node from its moments dh (rest-height
+// deviation), qx, qy.  With tau = 1 fo is the post-collision state
+// f^eq + 3 w_k c_k.F; otherwise it is omega (f^eq) + forcing and the caller
+// adds (1 - omega) f.
+template <typename C, int NL, bool TAU1, typename P>
+__device__ inline void node_collide(const StepConsts<C>& kc, const C (&dh2)[NL], const C (&qx2)[NL],
+                                    const C (&qy2)[NL], P&& pz, C (&fo)[NL][kQ]) {
+  C h[NL], ux[NL], uy[NL], g[NL + 1], rh[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    h[i] = kc.hbar[i] + dh2[i];
+    rh[i] = rcp(h[i]);
+    ux[i] = qx2[i] * rh[i];
+    uy[i] = qy2[i] * rh[i];
+    g[i] = kc.mu[i] * rh[i];
+  }
+  g[NL] = C(0);
+  // Thomas elimination for the interface velocities v (x and y share
+  // pivots) and the bottom velocities w of the layers' profiles
+  C cpr[NL], vx[NL], vy[NL], wx[NL], wy[NL];
+  if (!kc.slip_on) {
+    // no slip: w_i = v_{i-1}
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const C diag = C(2) * (g[i] + g[i + 1]);
+      const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
+      const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
+      if (i == 0) {
+        const C im = rcp(diag);
+        cpr[i] = g[i + 1] * im;
+        vx[i] = rx * im;
+        vy[i] = ry * im;
+      } else {
+        const C im = rcp(diag - g[i] * cpr[i - 1]);
+        cpr[i] = g[i + 1] * im;
+        vx[i] = (rx - g[i] * vx[i - 1]) * im;
+        vy[i] = (ry - g[i] * vy[i - 1]) * im;
+      }
+    }
+#pragma unroll
+    for (int i = NL - 2; i >= 0; --i) {
+      vx[i] -= cpr[i] * vx[i + 1];
+      vy[i] -= cpr[i] * vy[i + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      wx[i] = i > 0 ? vx[i - 1] : C(0);
+      wy[i] = i > 0 ? vy[i - 1] : C(0);
+    }
+  } else {
+    // slip lengths beta_i, rho = beta_i / h_i:
+    //   w_i = A_i v_{i-1} + B_i v_i + E_i U_i,  A = 1 / ((1 + rho)(1 + 3 rho)),
+    //   B = -rho (3 rho + 2) A,  E = 6 rho (rho + 1) A;
+    // stress continuity g_i (4 v_i + 2 w_i - 6 U_i) + g_{i+1} (4 w_{i+1} + 2 v_{i+1} - 6 U_{i+1}) = 0
+    C sa[NL + 1], sb[NL + 1], se[NL + 1];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const C r = kc.slip[i] * rh[i];
+      sa[i] = rcp((C(1) + r) * (C(1) + C(3) * r));
+      sb[i] = -r * (C(3) * r + C(2)) * sa[i];
+      se[i] = C(6) * r * (r + C(1)) * sa[i];
+    }
+    sa[NL] = sb[NL] = se[NL] = C(0);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const C sub = C(2) * g[i] * sa[i];
+      const C diag = g[i] * (C(4) + C(2) * sb[i]) + C(4) * g[i + 1] * sa[i + 1];
+      const C sup = g[i + 1] * (C(4) * sb[i + 1] + C(2));
+      const C k0 = g[i] * (C(6) - C(2) * se[i]), k1 = g[i + 1] * (C(6) - C(4) * se[i + 1]);
+      const C rx = k0 * ux[i] + (i + 1 < NL ? k1 * ux[i + 1] : C(0));
+      const C ry = k0 * uy[i] + (i + 1 < NL ? k1 * uy[i + 1] : C(0));
+      if (i == 0) {
+        const C im = rcp(diag);
+        cpr[i] = sup * im;
+        vx[i] = rx * im;
+        vy[i] = ry * im;
+      } else {
+        const C im = rcp(diag - sub * cpr[i - 1]);
+        cpr[i] = sup * im;
+        vx[i] = (rx - sub * vx[i - 1]) * im;
+        vy[i] = (ry - sub * vy[i - 1]) * im;
+      }
+    }
+#pragma unroll
+    for (int i = NL - 2; i >= 0; --i) {
+      vx[i] -= cpr[i] * vx[i + 1];
+      vy[i] -= cpr[i] * vy[i + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      wx[i] = sa[i] * (i > 0 ? vx[i - 1] : C(0)) + sb[i] * vx[i] + se[i] * ux[i];
+      wy[i] = sa[i] * (i > 0 ? vy[i - 1] : C(0)) + sb[i] * vy[i] + se[i] * uy[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const C sw = pz(i, 0, 0), s = pz(i, 0, 1), se = pz(i, 0, 2);
+    const C wv = pz(i, 1, 0), e = pz(i, 1, 2);
+    const C nw = pz(i, 2, 0), nn = pz(i, 2, 1), ne = pz(i, 2, 2);
+    const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
+    const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
+    const C frx = C(6) * g[i] * ((wx[i] + vx[i]) - C(2) * ux[i]);
+    const C fry = C(6) * g[i] * ((wy[i] + vy[i]) - C(2) * uy[i]);
+    const C Fx = -h[i] * gpx + frx;
+    const C Fy = -h[i] * gpy + fry;
+    const C qx = qx2[i], qy = qy2[i];
+    const C qu = qx * ux[i] + qy * uy[i];
+    const C t15 = C(1.5) * qu;
+    // Shallow-water equilibrium with the rest population as deviation
+    // from hbar, split into its even part (quadratic in U, shared by
+    // opposite directions) and odd part c.q/c_s^2 w_k; the forcing
+    // 3 w_k c_k.F is odd too.  With q_k = c_k.q and u_k = c_k.U:
+    //   f^eq_k = w_k (3 q_k + 4.5 q_k u_k - 1.5 q.U),  k >= 1.
+    const C ex = C(1.0 / 9.0) * (C(4.5) * qx * ux[i] - t15);  // axial x, even
+    const C ey = C(1.0 / 9.0) * (C(4.5) * qy * uy[i] - t15);  // axial y, even
+    const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
+    const C ep = C(1.0 / 36.0) * (C(4.5) * spq * spu - t15);  // diagonal (1,1), even
+    const C em = C(1.0 / 36.0) * (C(4.5) * smq * smu - t15);  // diagonal (-1,1), even
+    C ox, oy;                                                  // axial odd parts
+    if constexpr (TAU1) {
+      ox = C(1.0 / 3.0) * (qx + Fx);
+      oy = C(1.0 / 3.0) * (qy + Fy);
+      fo[i][0] = dh2[i] - C(2.0 / 3.0) * qu;
+    } else {
+      const C w = kc.omega;
+      ox = C(1.0 / 3.0) * (w * qx + Fx);
+      oy = C(1.0 / 3.0) * (w * qy + Fy);
+      fo[i][0] = w * (dh2[i] - C(2.0 / 3.0) * qu);
+    }
+    const C op = C(0.25) * (ox + oy), om = C(0.25) * (oy - ox);  // diagonal odd parts
+    C gx = ex, gy = ey, gp = ep, gm = em;
+    if constexpr (!TAU1) {
+      gx = kc.omega * ex;
+      gy = kc.omega * ey;
+      gp = kc.omega * ep;
+      gm = kc.omega * em;
+    }
+    fo[i][1] = gx + ox;
+    fo[i][5] = gx - ox;
+    fo[i][3] = gy + oy;
+    fo[i][7] = gy - oy;
+    fo[i][2] = gp + op;
+    fo[i][6] = gp - op;
+    fo[i][4] = gm + om;
+    fo[i][8] = gm - om;
+  }
+}
+
 // One tile (strip x segment) of one step: the whole workgroup marches the
 // segment's rows.  `tile` is uniform and < kc.nstrip * kc.nseg.
 template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
@@ -543,148 +745,9 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
       if (st_ok) {
         const int pA = (it - 4) % 3, pC = (it - 3) % 3, pB = (it - 2) % 3;
         const int pS = dir > 0 ? pA : pB, pN = dir > 0 ? pB : pA;  // rows y-1, y+1
-        C h[NL], ux[NL], uy[NL], g[NL + 1], rh[NL];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-          h[i] = kc.hbar[i] + dh2[i];
-          rh[i] = rcp(h[i]);
-          ux[i] = qx2[i] * rh[i];
-          uy[i] = qy2[i] * rh[i];
-          g[i] = kc.mu[i] * rh[i];
-        }
-        g[NL] = C(0);
-        // Thomas elimination for the interface velocities v (x and y share
-        // pivots) and the bottom velocities w of the layers' profiles
-        C cpr[NL], vx[NL], vy[NL], wx[NL], wy[NL];
-        if (!kc.slip_on) {
-          // no slip: w_i = v_{i-1}
-#pragma unroll
-          for (int i = 0; i < NL; ++i) {
-            const C diag = C(2) * (g[i] + g[i + 1]);
-            const C rx = C(3) * (g[i] * ux[i] + (i + 1 < NL ? g[i + 1] * ux[i + 1] : C(0)));
-            const C ry = C(3) * (g[i] * uy[i] + (i + 1 < NL ? g[i + 1] * uy[i + 1] : C(0)));
-            if (i == 0) {
-              const C im = rcp(diag);
-              cpr[i] = g[i + 1] * im;
-              vx[i] = rx * im;
-              vy[i] = ry * im;
-            } else {
-              const C im = rcp(diag - g[i] * cpr[i - 1]);
-              cpr[i] = g[i + 1] * im;
-              vx[i] = (rx - g[i] * vx[i - 1]) * im;
-              vy[i] = (ry - g[i] * vy[i - 1]) * im;
-            }
-          }
-#pragma unroll
-          for (int i = NL - 2; i >= 0; --i) {
-            vx[i] -= cpr[i] * vx[i + 1];
-            vy[i] -= cpr[i] * vy[i + 1];
-          }
-#pragma unroll
-          for (int i = 0; i < NL; ++i) {
-            wx[i] = i > 0 ? vx[i - 1] : C(0);
-            wy[i] = i > 0 ? vy[i - 1] : C(0);
-          }
-        } else {
-          // slip lengths beta_i, rho = beta_i / h_i:
-          //   w_i = A_i v_{i-1} + B_i v_i + E_i U_i,  A = 1 / ((1 + rho)(1 + 3 rho)),
-          //   B = -rho (3 rho + 2) A,  E = 6 rho (rho + 1) A;
-          // stress continuity g_i (4 v_i + 2 w_i - 6 U_i) + g_{i+1} (4 w_{i+1} + 2 v_{i+1} - 6 U_{i+1}) = 0
-          C sa[NL + 1], sb[NL + 1], se[NL + 1];
-#pragma unroll
-          for (int i = 0; i < NL; ++i) {
-            const C r = kc.slip[i] * rh[i];
-            sa[i] = rcp((C(1) + r) * (C(1) + C(3) * r));
-            sb[i] = -r * (C(3) * r + C(2)) * sa[i];
-            se[i] = C(6) * r * (r + C(1)) * sa[i];
-          }
-          sa[NL] = sb[NL] = se[NL] = C(0);
-#pragma unroll
-          for (int i = 0; i < NL; ++i) {
-            const C sub = C(2) * g[i] * sa[i];
-            const C diag = g[i] * (C(4) + C(2) * sb[i]) + C(4) * g[i + 1] * sa[i + 1];
-            const C sup = g[i + 1] * (C(4) * sb[i + 1] + C(2));
-            const C k0 = g[i] * (C(6) - C(2) * se[i]), k1 = g[i + 1] * (C(6) - C(4) * se[i + 1]);
-            const C rx = k0 * ux[i] + (i + 1 < NL ? k1 * ux[i + 1] : C(0));
-            const C ry = k0 * uy[i] + (i + 1 < NL ? k1 * uy[i + 1] : C(0));
-            if (i == 0) {
-              const C im = rcp(diag);
-              cpr[i] = sup * im;
-              vx[i] = rx * im;
-              vy[i] = ry * im;
-            } else {
-              const C im = rcp(diag - sub * cpr[i - 1]);
-              cpr[i] = sup * im;
-              vx[i] = (rx - sub * vx[i - 1]) * im;
-              vy[i] = (ry - sub * vy[i - 1]) * im;
-            }
-          }
-#pragma unroll
-          for (int i = NL - 2; i >= 0; --i) {
-            vx[i] -= cpr[i] * vx[i + 1];
-            vy[i] -= cpr[i] * vy[i + 1];
-          }
-#pragma unroll
-          for (int i = 0; i < NL; ++i) {
-            wx[i] = sa[i] * (i > 0 ? vx[i - 1] : C(0)) + sb[i] * vx[i] + se[i] * ux[i];
-            wy[i] = sa[i] * (i > 0 ? vy[i - 1] : C(0)) + sb[i] * vy[i] + se[i] * uy[i];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-          const C* a = pr + (pS * NL + i) * W + tid;
-          const C* c = pr + (pC * NL + i) * W + tid;
-          const C* n = pr + (pN * NL + i) * W + tid;
-          const C sw = a[-1], s = a[0], se = a[1];
-          const C wv = c[-1], e = c[1];
-          const C nw = n[-1], nn = n[0], ne = n[1];
-          const C gpx = (e - wv) * C(1.0 / 3.0) + ((ne + se) - (nw + sw)) * C(1.0 / 12.0);
-          const C gpy = (nn - s) * C(1.0 / 3.0) + ((ne + nw) - (se + sw)) * C(1.0 / 12.0);
-          const C frx = C(6) * g[i] * ((wx[i] + vx[i]) - C(2) * ux[i]);
-          const C fry = C(6) * g[i] * ((wy[i] + vy[i]) - C(2) * uy[i]);
-          const C Fx = -h[i] * gpx + frx;
-          const C Fy = -h[i] * gpy + fry;
-          const C qx = qx2[i], qy = qy2[i];
-          const C qu = qx * ux[i] + qy * uy[i];
-          const C t15 = C(1.5) * qu;
-          // Shallow-water equilibrium with the rest population as deviation
-          // from hbar, split into its even part (quadratic in U, shared by
-          // opposite directions) and odd part c.q/c_s^2 w_k; the forcing
-          // 3 w_k c_k.F is odd too.  With q_k = c_k.q and u_k = c_k.U:
-          //   f^eq_k = w_k (3 q_k + 4.5 q_k u_k - 1.5 q.U),  k >= 1.
-          const C ex = C(1.0 / 9.0) * (C(4.5) * qx * ux[i] - t15);  // axial x, even
-          const C ey = C(1.0 / 9.0) * (C(4.5) * qy * uy[i] - t15);  // axial y, even
-          const C spq = qx + qy, smq = qy - qx, spu = ux[i] + uy[i], smu = uy[i] - ux[i];
-          const C ep = C(1.0 / 36.0) * (C(4.5) * spq * spu - t15);  // diagonal (1,1), even
-          const C em = C(1.0 / 36.0) * (C(4.5) * smq * smu - t15);  // diagonal (-1,1), even
-          C ox, oy;                                                  // axial odd parts
-          if constexpr (TAU1) {
-            ox = C(1.0 / 3.0) * (qx + Fx);
-            oy = C(1.0 / 3.0) * (qy + Fy);
-            fo[i][0] = dh2[i] - C(2.0 / 3.0) * qu;
-          } else {
-            const C w = kc.omega;
-            ox = C(1.0 / 3.0) * (w * qx + Fx);
-            oy = C(1.0 / 3.0) * (w * qy + Fy);
-            fo[i][0] = w * (dh2[i] - C(2.0 / 3.0) * qu);
-          }
-          const C op = C(0.25) * (ox + oy), om = C(0.25) * (oy - ox);  // diagonal odd parts
-          C gx = ex, gy = ey, gp = ep, gm = em;
-          if constexpr (!TAU1) {
-            gx = kc.omega * ex;
-            gy = kc.omega * ey;
-            gp = kc.omega * ep;
-            gm = kc.omega * em;
-          }
-          fo[i][1] = gx + ox;
-          fo[i][5] = gx - ox;
-          fo[i][3] = gy + oy;
-          fo[i][7] = gy - oy;
-          fo[i][2] = gp + op;
-          fo[i][6] = gp - op;
-          fo[i][4] = gm + om;
-          fo[i][8] = gm - om;
-        }
+        const int ps3[3] = {pS, pC, pN};
+        auto pz = [&](int i, int rr, int cc) { return pr[(ps3[rr] * NL + i) * W + tid + cc - 1]; };
+        node_collide<C, NL, TAU1>(kc, dh2, qx2, qy2, pz, fo);
       } else {
 #pragma unroll
         for (int i = 0; i < NL; ++i)

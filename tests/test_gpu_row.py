@@ -1,0 +1,76 @@
+"""D2Q9 films one row high: the LDS-resident kernel (many steps per launch)
+against the strip kernel, which mlf_step runs while a graph is captured.
+Both take the same arithmetic per node, so the populations must agree bit
+for bit; the oracle pins the path through the two-layer workload in
+test_gpu_parity.py (10^4 steps, 1e-12)."""
+import numpy as np
+import pytest
+
+from paper_2409_16659_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mlf(torch_cuda):
+    from paper_2409_16659_amd import mlfilm
+
+    mlfilm.load_library()
+    return mlfilm
+
+
+def _film(n, nx, seed, tau=1.0, exps=(9, 3), slip=None):
+    rng = np.random.default_rng(seed)
+    gam = list(rng.uniform(0.5e-2, 1.5e-2, size=n))
+    spread = {(l, 1): inputs.young_spreading(gam[l], 20.0) for l in range(n)}
+    for l in range(n):
+        for k in range(2, n - l + 1):
+            spread[(l, k)] = rng.uniform(-2e-3, 2e-3)
+    film = inputs.film_params(n, nx, 1, gamma=gam, mu=[0.003] * n, hstar=0.15, spread=spread, tau=tau,
+                              exp_a=exps[0], exp_b=exps[1], slip=slip)
+    hbar = [1.0, 0.8, 0.6, 0.4][:n]
+    rng2 = np.random.default_rng(seed + 1)
+    h0 = np.stack([hbar[i] + 1e-2 * rng2.uniform(-1, 1, size=(1, nx)) for i in range(n)])
+    return film, h0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,nx,kw", [(1, 1, {}), (2, 2, {}), (2, 512, {}), (3, 37, {"tau": 0.8}),
+                                     (4, 700, {}), (2, 1024, {"exps": (4, 2)}),
+                                     (3, 200, {"slip": [0.1, 0.0, 0.2]}), (4, 130, {"tau": 1.3})])
+def test_resident_row_equals_strip_kernel(mlf, torch_cuda, prec, n, nx, kw):
+    film, h0 = _film(n, nx, 300 + n + nx, **kw)
+    steps = 600
+    print(f"case row N={n} nx={nx} {prec} {kw}", flush=True)
+    a = mlf.Film(film, prec)                             # resident kernel
+    b = mlf.Film(film, prec, stream=torch_cuda.cuda.Stream())
+    for g in (a, b):
+        g.init(h0)
+    b.capture(2)                                         # strip kernel through the graph
+    a.step(steps)
+    b.step(steps)
+    fa, fb = a.populations(), b.populations()
+    assert np.array_equal(fa, fb)
+    assert a.steps_done == b.steps_done == steps
+
+
+def test_resident_row_guard(mlf, torch_cuda):
+    """A forced non-positive height trips the guard in the resident kernel."""
+    film, h0 = _film(2, 64, 9)
+    g = mlf.Film(film, "f64", check_every=50)
+    g.init(h0)
+    f = g.populations()
+    f[0, 0, 0, 10] = -5.0  # rest population of layer 1 at one node: h < 0
+    g.set_populations(f)
+    with pytest.raises(mlf.MlfError) as e:
+        g.step(100)
+    assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
