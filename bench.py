@@ -330,7 +330,10 @@ def bench_batch(args):
 def bench_surrogate(args):
     """Learned surrogate: speedup over the plain GPU solver per 100-step
     window of 256^2 three-layer films, judge and fallback costs included,
-    at <= 1e-3 relative L2 height error per judged window."""
+    at <= 1e-3 relative L2 height error per judged window.  Judged runs
+    start at t = 80,000 and cross the films' rupture (~9-10 x 10^4 steps),
+    where predicting no change fails the gate; a persistence (identity)
+    predictor is judged the same way beside the surrogate."""
     import numpy as np
     import torch
 
@@ -338,12 +341,13 @@ def bench_surrogate(args):
     from paper_2409_16659_amd import surrogate as S
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    tol = 1e-3
     t0 = time.perf_counter()
     train_films = S.films(48, 5000)
     X0, X1 = S.windows(train_films, list(range(30000, 95001, 500)))
     t_data = time.perf_counter() - t0
     test_films = S.films(8, 5048)
-    eval_t = list(range(40000, 90001, 10000))
+    eval_t = list(range(40000, 100001, 10000))
     T0, T1 = S.windows(test_films, eval_t)
     m = mlfilm.Surrogate(3, 256, 256, width=128, blocks=3, batch=64, scale=1e-2)
     m.set_params(S.init_params(m, seed=0))
@@ -355,30 +359,48 @@ def bench_surrogate(args):
           f"{t_train:.1f} s, final loss {losses[-1]:.3e}", file=sys.stderr, flush=True)
     P = torch.cat([m.predict(T0[i:i + 8].contiguous()) for i in range(0, T0.shape[0], 8)])
     torch.cuda.synchronize()
-    es, ep = S.rel_l2(P, T1), S.persistence_error(T0, T1)
-    held_out = [{"t": t, "surrogate_rel_l2": float(es[k * 8:(k + 1) * 8].mean()),
-                 "persistence_rel_l2": float(ep[k * 8:(k + 1) * 8].mean())} for k, t in enumerate(eval_t)]
+    es, ep = S.errors(m, P, T1), S.errors(m, T0, T1)
+    held_out = [{"t": t, "surrogate_rel_l2": float(es[k * 8:(k + 1) * 8, 0].mean()),
+                 "persistence_rel_l2": float(ep[k * 8:(k + 1) * 8, 0].mean()),
+                 "surrogate_rel_l2_pert": float(es[k * 8:(k + 1) * 8, 1].mean()),
+                 "persistence_rel_l2_pert": float(ep[k * 8:(k + 1) * 8, 1].mean())} for k, t in enumerate(eval_t)]
     # dominant kernel: the MFMA 3x3 convolution (forward), batch 64
     m.predict(T0[:8].repeat(8, 1, 1, 1).contiguous())
     ms_f, ms_w = m.time_conv(64, reps=20)
     flops = m.conv_flops(64)
-    runs = [S.judged_run(m, test_films, 60000, 40, k, 1e-3, overlap=ov) for ov in (False, True) for k in (4, 8, 16)]
-    for r in runs:
-        r["judge_errors_max"] = max(r.pop("judge_errors"))
-    ok = [r for r in runs if max(r["final_rel_l2"]) <= 1e-3] or runs
-    best = max(ok, key=lambda r: r["speedup"])
+
+    def summary(r):
+        r = dict(r)
+        for key in ("judge_errors", "judge_errors_pert", "persistence_errors", "persistence_errors_pert"):
+            v = r.pop(key)
+            r[key + "_max"] = max(v)
+            r[key + "_min"] = min(v)
+        return r
+
+    # the restart of judge and fallback: carried velocities, at rest, Stokes-limit velocities
+    restarts = [summary(S.judged_run(m, test_films, 60000, 16, 8, tol, restart=rs))
+                for rs in ("carried", "rest", "stokes")]
+    t_judge0 = 80000
+    runs = [summary(S.judged_run(m, test_films, t_judge0, 20, k, tol, overlap=ov))
+            for ov in (False, True) for k in (4, 8, 16)]
+    ident = summary(S.judged_run(S.Identity(), test_films, t_judge0, 20, 8, tol, judge_model=m))
+    ok = [r for r in runs if max(r["final_rel_l2"]) <= tol]
+    best = max(ok, key=lambda r: r["speedup"]) if ok else None
     tf = flops / (ms_f * 1e-3) / 1e12
+    ref = best or max(runs, key=lambda r: r["speedup"])
     out = {
         "metric": "surrogate speedup over the plain GPU solver per 100-step window (judge + fallback counted), "
                   "<= 1e-3 relative L2 height error",
-        "value": best["speedup"], "unit": "x", "n_gpus": 1, "steps": best["windows"] * 100, "warmup": 0,
-        "ms_per_step": best["total_s"] * 1e3 / (best["windows"] * 100), "higher_is_better": True,
+        "value": best["speedup"] if best else None, "unit": "x", "n_gpus": 1,
+        "steps": ref["windows"] * 100, "warmup": 0,
+        "ms_per_step": ref["total_s"] * 1e3 / (ref["windows"] * 100), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "surrogate_film3_256", "films": len(test_films), "window": 100,
                    "params": m.param_count, "width": 128, "blocks": 3, "train_pairs": int(X0.shape[0]),
-                   "train_steps": args.train_steps, "judge_every": best["k"], "judge_overlap": best["overlap"],
-                   "tol": 1e-3},
-        "judged_runs": runs, "held_out": held_out,
+                   "train_steps": args.train_steps, "judge_every": ref["k"], "judge_overlap": ref["overlap"],
+                   "judged_from_t": t_judge0, "restart": "carried", "tol": tol},
+        "met_tolerance": best is not None,
+        "judged_runs": runs, "identity_run": ident, "restart_comparison": restarts, "held_out": held_out,
         "training_s": t_train, "data_s": t_data,
         "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
                      "traffic": None, "kernel": "conv3x3_fwd<128>", "kernel_ms": ms_f, "flops": flops,

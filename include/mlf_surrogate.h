@@ -87,6 +87,22 @@ mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const 
  * Synchronises. */
 mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad);
 
+/* Judge arithmetic.  Errors of n samples of a against the reference b
+ * (device FP32 [n][N][ny][nx] each), reduced in FP64 in a fixed order:
+ * out[2s] = |a_s - b_s| / |b_s| (relative L2 over all layers and nodes)
+ * and out[2s+1] = |a_s - b_s| / |b_s - mean b_s| (relative to the
+ * reference's perturbation, the per-layer means removed).  out: device
+ * FP64 [2n], caller-owned.  Asynchronous.  EINVAL for NULL pointers or
+ * n < 1. */
+mlf_status mlf_nop_errors(mlf_nop* m, int32_t n, const float* a, const float* b, double* out);
+
+/* Height conversion between the solver (FP64) and the network (FP32):
+ * n elements; to_f32 != 0: src FP64 -> dst FP32 (round to nearest), else
+ * src FP32 -> dst FP64 (exact).  Device arrays, caller-owned, not
+ * aliased; stream: hipStream_t (NULL: default).  Asynchronous.  EINVAL
+ * for NULL pointers or n < 1, EDEVICE if the launch fails. */
+mlf_status mlf_convert_heights(const void* src, int32_t to_f32, void* dst, int64_t n, void* stream);
+
 /* Adam steps taken since the parameters were last set (-1 for NULL). */
 int32_t mlf_nop_steps_done(const mlf_nop* m);
 /* Text of the last failure on this handle ("" if none); valid until the

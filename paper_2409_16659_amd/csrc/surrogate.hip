@@ -447,6 +447,65 @@ dim3 plane_grid(long long n_plane, long long planes) {
 
 }  // namespace
 
+// ---- judge arithmetic ---------------------------------------------------------
+// Errors of sample blockIdx.x of a against b (each [S][N][plane] FP32), in
+// FP64 with a fixed summation order: out[2s] = |a - b| / |b| and
+// out[2s+1] = |a - b| / |b - mean_i b| (L2 norms over all layers and
+// nodes; mean_i b the per-layer mean, so the second is relative to the
+// perturbation of the reference).  Two passes: per-layer sums of b, then
+// the three squared norms.
+constexpr int kErrThreads = 1024;
+__global__ void __launch_bounds__(kErrThreads) sample_errors(const float* __restrict__ a, const float* __restrict__ b,
+                                                             double* __restrict__ out, int nl, long long plane) {
+  __shared__ double red[kErrThreads / 64][3];
+  __shared__ double means[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kErrThreads / 64;
+  const long long base = (long long)blockIdx.x * nl * plane;
+  for (int i = 0; i < nl; ++i) {
+    double s = 0.0;
+    for (long long e = threadIdx.x; e < plane; e += kErrThreads) s += (double)b[base + i * plane + e];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) red[wv][0] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int j = 0; j < nw; ++j) t += red[j][0];
+      means[i] = t / (double)plane;
+    }
+    __syncthreads();
+  }
+  double d2 = 0.0, b2 = 0.0, p2 = 0.0;
+  for (int i = 0; i < nl; ++i) {
+    const double mu = means[i];
+    for (long long e = threadIdx.x; e < plane; e += kErrThreads) {
+      const double bv = b[base + i * plane + e], av = a[base + i * plane + e];
+      d2 += (av - bv) * (av - bv);
+      b2 += bv * bv;
+      p2 += (bv - mu) * (bv - mu);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    d2 += __shfl_down(d2, off, 64);
+    b2 += __shfl_down(b2, off, 64);
+    p2 += __shfl_down(p2, off, 64);
+  }
+  if (lane == 0) red[wv][0] = d2, red[wv][1] = b2, red[wv][2] = p2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sd = 0.0, sb = 0.0, sp = 0.0;
+    for (int j = 0; j < nw; ++j) sd += red[j][0], sb += red[j][1], sp += red[j][2];
+    out[2 * blockIdx.x] = sqrt(sd / sb);
+    out[2 * blockIdx.x + 1] = sqrt(sd / sp);
+  }
+}
+
+// Element conversion between the solver's FP64 heights and the network's FP32.
+template <typename S, typename D>
+__global__ void __launch_bounds__(256) convert(const S* __restrict__ src, D* __restrict__ dst, long long n) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    dst[t] = (D)src[t];
+}
+
 // ============================================================= handle ====
 struct mlf_nop {
   mlf_nop_params p;
@@ -923,6 +982,25 @@ mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_
   if (ms_fwd) *ms_fwd = a / reps;
   if (ms_wgrad) *ms_wgrad = b / reps;
   return MLF_OK;
+}
+
+mlf_status mlf_nop_errors(mlf_nop* m, int32_t n, const float* a, const float* b, double* out) {
+  if (!m || !a || !b || !out || n < 1) return MLF_EINVAL;
+  const long long plane = (long long)m->p.ny * m->p.nx;
+  NLAUNCH(sample_errors, dim3((unsigned)n), dim3(kErrThreads), 0, m->stream, a, b, out, m->p.n_layers, plane);
+  return MLF_OK;
+}
+
+mlf_status mlf_convert_heights(const void* src, int32_t to_f32, void* dst, int64_t n, void* stream) {
+  if (!src || !dst || n < 1) return MLF_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (to_f32)
+    hipLaunchKernelGGL((convert<double, float>), dim3(grid1(n)), dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<float*>(dst), (long long)n);
+  else
+    hipLaunchKernelGGL((convert<float, double>), dim3(grid1(n)), dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<double*>(dst), (long long)n);
+  return hipGetLastError() == hipSuccess ? MLF_OK : MLF_EDEVICE;
 }
 
 int32_t mlf_nop_steps_done(const mlf_nop* m) { return m ? m->adam_t : -1; }

@@ -114,6 +114,8 @@ def load_library():
         "mlf_batch_read_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_batch_init_device": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_batch_init_device_all": (st, [H, C.POINTER(C.c_void_p)]),
+        "mlf_batch_init_device_all_u": (st, [H, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_void_p)]),
         "mlf_batch_read_device_all": (st, [H, C.POINTER(C.c_void_p)]),
         "mlf_batch_set_launch": (st, [H, C.c_int32, C.c_int32, C.c_int32]),
         "mlf_batch_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -133,6 +135,9 @@ def load_library():
                                   C.POINTER(C.c_double)]),
         "mlf_nop_train_step": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_float, C.POINTER(C.c_double)]),
         "mlf_nop_time_conv": (st, [H, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+        "mlf_nop_errors": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "mlf_convert_heights": (st, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
+        "mlf_stokes_velocity": (st, [P, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_nop_steps_done": (C.c_int32, [H]),
         "mlf_nop_last_error": (C.c_char_p, [H]),
         "mlf_nop_destroy": (st, [H]),
@@ -262,6 +267,28 @@ def stream_probe(mode, src, dst, nbytes, schedule="chunked", nontemporal=False, 
                               nbytes, int(blocks), C.c_void_p(s.cuda_stream))
     if rc:
         raise MlfError(rc, "mlf_stream_probe")
+
+
+def convert_heights(src, dst, stream=None):
+    """Copy heights between FP64 and FP32 device tensors of one shape
+    (mlf_convert_heights) on `stream` (default: torch's current stream);
+    returns dst."""
+    import torch
+
+    lib = load_library()
+    assert src.is_contiguous() and dst.is_contiguous() and src.shape == dst.shape
+    if src.dtype == torch.float64 and dst.dtype == torch.float32:
+        to32 = 1
+    elif src.dtype == torch.float32 and dst.dtype == torch.float64:
+        to32 = 0
+    else:
+        raise ValueError("convert_heights needs FP64 -> FP32 or FP32 -> FP64")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.mlf_convert_heights(C.c_void_p(src.data_ptr()), to32, C.c_void_p(dst.data_ptr()), src.numel(),
+                                 C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MlfError(rc, "mlf_convert_heights")
+    return dst
 
 
 def rupture_threshold(film):
@@ -530,12 +557,30 @@ class Batch:
         step = t[0].numel() * 8
         return (C.c_void_p * self.n)(*[t.data_ptr() + f * step for f in range(self.n)])
 
-    def init_all(self, h):
+    def init_all(self, h, ux=None, uy=None):
         """Initialise every film (all of one shape) from a device FP64 tensor
-        [films][N][ny][nx], with one synchronisation."""
+        [films][N][ny][nx] (and optional velocities of the same shape), with
+        one synchronisation."""
         ptrs = self._ptrs(h)
         self.torch.cuda.current_stream(self.device).synchronize()
-        self._check(self.lib.mlf_batch_init_device_all(self.h, ptrs), "mlf_batch_init_device_all")
+        if ux is None and uy is None:
+            self._check(self.lib.mlf_batch_init_device_all(self.h, ptrs), "mlf_batch_init_device_all")
+            return
+        self._check(self.lib.mlf_batch_init_device_all_u(self.h, ptrs, self._ptrs(ux), self._ptrs(uy)),
+                    "mlf_batch_init_device_all_u")
+
+    def stokes_velocity(self, h, ux, uy):
+        """Stokes-limit velocities (mlf_stokes_velocity) of every film's
+        heights h into ux, uy (device FP64 tensors [films][N][ny][nx]), on the
+        batch's stream."""
+        hp, xp, yp = self._ptrs(h), self._ptrs(ux), self._ptrs(uy)
+        # h may come from torch's stream; the batch reads it on its own
+        self.torch.cuda.current_stream(self.device).synchronize()
+        for f in range(self.n):
+            rc = self.lib.mlf_stokes_velocity(C.byref(self.params[f]), hp[f], xp[f], yp[f],
+                                              C.c_void_p(self.stream.cuda_stream))
+            if rc:
+                raise MlfError(rc, "mlf_stokes_velocity")
 
     def read_all(self, out=None):
         """Heights of every film (all of one shape) as a device FP64 tensor
@@ -547,6 +592,16 @@ class Batch:
         self._check(self.lib.mlf_batch_read_device_all(self.h, self._ptrs(out)), "mlf_batch_read_device_all")
         self.stream.synchronize()
         return out
+
+    def read_all_hu(self, h, ux, uy):
+        """Heights and velocities of every film (all of one shape) into device
+        FP64 tensors [films][N][ny][nx]; the batch's stream is synchronised
+        before return."""
+        hp, xp, yp = self._ptrs(h), self._ptrs(ux), self._ptrs(uy)
+        for f in range(self.n):
+            self._check(self.lib.mlf_batch_read_device(self.h, f, hp[f], xp[f], yp[f]), "mlf_batch_read_device")
+        self.stream.synchronize()
+        return h, ux, uy
 
     def mass(self, f):
         m = np.empty(self.params[f].n_layers)
@@ -684,6 +739,18 @@ class Surrogate:
                                               C.c_void_p(h1.data_ptr()), g.ctypes.data_as(C.POINTER(C.c_float)),
                                               C.byref(v)), "mlf_nop_gradient")
         return v.value, g
+
+    def errors(self, a, b):
+        """Per-sample (relative L2, perturbation-relative L2) errors of the
+        FP32 height tensors a against the reference b (mlf_nop_errors, FP64
+        reduction on the device), returned as a host array [S][2]."""
+        a, b = self._dev(a), self._dev(b)
+        assert a.shape == b.shape
+        out = self.torch.empty((a.shape[0], 2), dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.mlf_nop_errors(self.h, a.shape[0], C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                            C.c_void_p(out.data_ptr())), "mlf_nop_errors")
+        self.stream.synchronize()
+        return out.cpu().numpy()
 
     def time_conv(self, batch, reps=20):
         """Average ms of one MFMA 3x3 convolution (forward, weight gradient)."""
