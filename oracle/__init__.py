@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build of the same source (the sanitizer build)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 MAX_LAYERS = 4
 D2Q9, D1Q3 = 0, 1
 OK, ENONPOSITIVE, ENONFINITE, EINVAL = 0, 1, 2, 3
