@@ -37,19 +37,30 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-o", LIB + ".tmp", *SOURCES]
+LIB_SAN = os.path.join(HERE, "libmlfilm_hostsan.so")
+# AddressSanitizer + UBSan on the host code only (the device code is built
+# as usual); load it with MLFILM_LIB pointing at it and clang's ASan runtime
+# (libclang_rt.asan-x86_64.so) preloaded.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, extra=None, sanitize_host: bool = False) -> str:
+    out = LIB_SAN if sanitize_host else LIB
+    cmd = [hipcc(), *HIPCC_FLAGS, *(HOST_SANITIZE if sanitize_host else []), *(extra or []), "-o", out + ".tmp",
+           *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def lib_path() -> str:
-    return LIB
+    """The library the binding loads: MLFILM_LIB (another build of the same
+    sources, e.g. the host-sanitizer one) or the in-tree build."""
+    return os.environ.get("MLFILM_LIB") or LIB
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    print(build(verbose="-v" in sys.argv, sanitize_host="--sanitize-host" in sys.argv))
