@@ -370,7 +370,8 @@ def bench_surrogate(args):
                  "persistence_rel_l2_pert": float(ep[k * 8:(k + 1) * 8, 1].mean())} for k, t in enumerate(eval_t)]
     # dominant kernel: the MFMA 3x3 convolution (forward), batch 64
     m.predict(T0[:8].repeat(8, 1, 1, 1).contiguous())
-    ms_f, ms_w = m.time_conv(64, reps=20)
+    conv_ms = m.time_conv(64, reps=20)
+    ms_f = conv_ms["fwd"]
     flops = m.conv_flops(64)
 
     def summary(r):
@@ -411,8 +412,36 @@ def bench_surrogate(args):
         "training_s": t_train, "data_s": t_data,
         "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
                      "traffic": None, "kernel": "conv3x3_fwd<128>", "kernel_ms": ms_f, "flops": flops,
-                     "wgrad_ms": ms_w, "wgrad_tflops": flops / (ms_w * 1e-3) / 1e12},
+                     "variants": {k: {"ms": v, "tflops": flops / (v * 1e-3) / 1e12,
+                                      "frac": flops / (v * 1e-3) / 1e12 / 2500.0} for k, v in conv_ms.items()}},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_conv_kernels(args):
+    """The surrogate's MFMA 3x3 convolutions alone (3-layer 256^2 films,
+    width 128, batch 64 of the training step): event-timed average of each
+    forward epilogue variant and of the weight gradient on activations of a
+    prediction with seeded random weights and heights."""
+    import numpy as np
+    import torch
+
+    from paper_2409_16659_amd import mlfilm
+    from paper_2409_16659_amd import surrogate as S
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    m = mlfilm.Surrogate(3, 256, 256, width=128, blocks=3, batch=64, scale=1e-2)
+    m.set_params(S.init_params(m, seed=0))
+    rng = np.random.default_rng(1)
+    h = torch.from_numpy((1.0 + 1e-2 * rng.normal(size=(64, 3, 256, 256))).astype(np.float32)).cuda()
+    m.predict(h)
+    ms = m.time_conv(64, reps=args.steps)
+    flops = m.conv_flops(64)
+    out = {"metric": "BF16 MFMA 3x3 convolution throughput", "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "dtype": "bf16", "data": "synthetic", "peak": 2500.0, "flops": flops,
+           "config": {"workload": "surrogate_conv_film3_256", "width": 128, "batch": 64, "latent": [64, 64]},
+           "kernels": {k: {"ms": v, "tflops": flops / (v * 1e-3) / 1e12, "frac": flops / (v * 1e-3) / 1e12 / 2500.0}
+                       for k, v in ms.items()}}
     print(json.dumps(out), flush=True)
 
 
@@ -514,6 +543,9 @@ def main():
                     help="learned surrogate instead: solver-generated training windows, training, and judged "
                          "runs against the plain solver (256^2 three-layer films, 100-step windows)")
     ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--conv-kernels", action="store_true",
+                    help="the surrogate's MFMA convolutions alone (forward with each epilogue, weight "
+                         "gradient; batch 64 of 256^2 films, width 128): --steps launches of each")
     ap.add_argument("--lattice", choices=["d2q9", "d1q3"], default="d2q9",
                     help="d1q3: pseudo-1D workloads on the D1Q3 lattice (film held in LDS, many steps "
                          "per launch)")
@@ -547,6 +579,8 @@ def main():
         return bench_batch(args)
     if args.surrogate:
         return bench_surrogate(args)
+    if args.conv_kernels:
+        return bench_conv_kernels(args)
 
     from paper_2409_16659_amd import inputs, mlfilm
 

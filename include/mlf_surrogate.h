@@ -81,11 +81,13 @@ mlf_status mlf_nop_gradient(mlf_nop* m, int32_t batch, const float* h0, const fl
 mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const float* h1, float lr, double* loss);
 
 /* Event-timed average duration (ms) of one 3x3 convolution of the first
- * block on `batch` samples: forward (also the input-gradient kernel) and
- * weight gradient, `reps` launches each, on the activations as they stand
- * (run mlf_nop_predict first).  Overwrites scratch activations only.
- * Synchronises. */
-mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad);
+ * block on `batch` samples, `reps` launches each, on the activations as
+ * they stand (run mlf_nop_predict first): ms[0] forward with the plain
+ * epilogue (also the input-gradient kernel), ms[1] forward with the GELU
+ * epilogue, ms[2] forward with the residual epilogue, ms[3] weight
+ * gradient.  ms: host float[4].  Overwrites the first block's activations
+ * and scratch only.  Synchronises.  EINVAL for NULL pointers or reps < 1. */
+mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms);
 
 /* Judge arithmetic.  Errors of n samples of a against the reference b
  * (device FP32 [n][N][ny][nx] each), reduced in FP64 in a fixed order:

@@ -29,19 +29,27 @@ typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
 __device__ inline int pwrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// tanh-form GELU and, if dg is given, its derivative
+// tanh-form GELU, 0.5 a (1 + tanh(u)) with u = k0 (a + k1 a^3), and, if dg
+// is given, its derivative.  Evaluated through the identity
+// 0.5 (1 + tanh(u)) = 1 / (1 + exp(-2u)) = s with the hardware exp2 and
+// reciprocal (each within about an ulp): gelu = a s and
+// gelu' = s + 2 a s (1 - s) u'.  For large |a| the exponential saturates to
+// 0 or infinity and s to 1 or 0 exactly.
 __device__ inline float gelu_f(float a, float* dg) {
   const float k0 = 0.7978845608028654f, k1 = 0.044715f;
   const float u = k0 * (a + k1 * a * a * a);
-  const float th = tanhf(u);
-  if (dg) *dg = 0.5f * (1.f + th) + 0.5f * a * (1.f - th * th) * k0 * (1.f + 3.f * k1 * a * a);
-  return 0.5f * a * (1.f + th);
+  const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * u);  // exp(-2u), 2 log2(e) = 2.885...
+  const float s = __builtin_amdgcn_rcpf(1.f + e);
+  if (dg) *dg = s + 2.f * a * s * (1.f - s) * k0 * (1.f + 3.f * k1 * a * a);
+  return a * s;
 }
 
 // Epilogues of the forward convolution: v = products + bias, then
 //  kEpiPlain: out = v;
 //  kEpiGelu:  out = v (pre-activation, FP32), outb = bf16(gelu(v));
-//  kEpiResid: out = res + v, outb = bf16(out)  (residual block output).
+//  kEpiResid: out = res + v, outb = bf16(out)  (residual block output; res
+//             joins the accumulators partway through the products, in an
+//             order fixed per output channel).
 enum { kEpiPlain = 0, kEpiGelu = 1, kEpiResid = 2 };
 
 __device__ inline bf16x8 ld8(const __bf16* p) {
@@ -54,37 +62,41 @@ __device__ inline bf16x8 ld8(const __bf16* p) {
 // A workgroup of WAVES waves covers WAVES rows of 64 pixels of one image and
 // CO of the C output channels (channel group blockIdx.y); each wave computes
 // 64 pixels x CO channels (CO / 16 column tiles).  The input channels are
-// taken in slabs of 32 (one MFMA k-step): per slab the workgroup stages in
+// taken in slabs of 32 (one MFMA k-step).  Per slab the workgroup stages in
 // LDS its WAVES + 2 input rows with one halo pixel on each side
-// ([row][66][40] bf16) and the slab's weights of all nine offsets for its
-// output channels ([9][CO][40] bf16; the stride of 40 spreads the 16 rows a
-// wave reads over the banks), then every product of the slab reads LDS
-// only.  Accumulation order per output: slabs, then offsets.  Dynamic LDS
-// conv3x3_fwd_lds() bytes (up to ~142 KiB).  Requires gx % 64 == 0,
-// gy % WAVES == 0, C % 32 == 0, CO | C.
-constexpr int kConvPS = 40;  // LDS stride of a pixel / weight row (bf16)
-
+// ([row][66 pixels][32 channels] bf16), and the weights one row offset dy
+// at a time ([3 dx][CO][32] bf16, three stages per slab), so that the
+// LDS of a 4-wave workgroup (49 KiB at CO = 128) lets two workgroups share
+// a CU: one's staging and epilogue overlap the other's products.  LDS rows
+// are 64 bytes with their four 16-byte chunks permuted by XOR with
+// (row / 2) % 4: the eight consecutive rows that eight lanes of a fragment
+// read fall in distinct banks without padding.  Accumulation order per
+// output: slabs, then offsets.  Dynamic LDS conv3x3_fwd_lds() bytes.
+// Requires gx % 64 == 0, gy % WAVES == 0, C % 32 == 0, CO | C.
+// Column tiles per epilogue pass (two: 32 channels, one 128-byte FP32 line
+// per pixel) and the LDS of the products and of the epilogue.
+__host__ __device__ constexpr int conv_epi_group(int CO) { return CO / 16 < 2 ? CO / 16 : 2; }
 __host__ __device__ constexpr size_t conv3x3_fwd_lds(int CO, int waves) {
-  return (size_t)((waves + 2) * 66 + 9 * CO) * kConvPS * 2;
+  const size_t prod = (size_t)((waves + 2) * 66 + 3 * CO) * 64;
+  const size_t epi = (size_t)waves * 64 * (16 * conv_epi_group(CO) + 4) * 4;
+  return prod > epi ? prod : epi;
 }
 
+// byte offset of 16-byte chunk q of 64-byte LDS row `row`
+__device__ inline int swz(int row, int q) { return row * 64 + ((q ^ (row >> 1)) & 3) * 16; }
+
 template <int C, int CO, int WAVES, int EPI>
-__global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restrict__ in,
-                                                           const __bf16* __restrict__ w,
-                                                           const float* __restrict__ bias, float* __restrict__ out,
-                                                           const float* __restrict__ res, __bf16* __restrict__ outb,
-                                                           int gy, int gx) {
-  constexpr int NT = CO / 16, NTH = 64 * WAVES, PS = kConvPS, ROWS = WAVES + 2, PX = 66;
-  constexpr int NXP = ROWS * PX * 4, NWP = 9 * CO * 4;  // 16-byte pieces of a slab
-  constexpr int XPER = (NXP + NTH - 1) / NTH, WPER = (NWP + NTH - 1) / NTH, NP = XPER + WPER;
-  // Prefetch the next slab into registers during this slab's products when
-  // the staging registers fit beside the accumulators; otherwise stage each
-  // slab after the barrier that frees LDS, in groups of loads issued together.
-  constexpr bool kPrefetch = 16 * NT + 4 * NP <= 160;
-  constexpr int G = kPrefetch ? NP : 4;
-  extern __shared__ __bf16 conv_smem[];
-  __bf16* sx = conv_smem;                 // [ROWS][PX][PS]
-  __bf16* sw = conv_smem + ROWS * PX * PS; // [9][CO][PS]
+__global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __restrict__ in,
+                                                              const __bf16* __restrict__ w,
+                                                              const float* __restrict__ bias, float* __restrict__ out,
+                                                              const float* __restrict__ res, __bf16* __restrict__ outb,
+                                                              int gy, int gx) {
+  constexpr int NT = CO / 16, NTH = 64 * WAVES, ROWS = WAVES + 2, PX = 66;
+  constexpr int NXP = ROWS * PX * 4, NWP = 3 * CO * 4;  // 16-byte pieces: input rows, one offset row of weights
+  constexpr int XPER = (NXP + NTH - 1) / NTH, WPER = (NWP + NTH - 1) / NTH;
+  extern __shared__ __attribute__((aligned(16))) unsigned char conv_lds[];
+  unsigned char* sx = conv_lds;                   // [ROWS * PX] rows of 64 bytes
+  unsigned char* sw = conv_lds + ROWS * PX * 64;  // [3 * CO] rows of 64 bytes
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int xtiles = gx / 64;
   const int xt = blockIdx.x % xtiles;
@@ -100,224 +112,301 @@ __global__ void __launch_bounds__(64 * WAVES) conv3x3_fwd(const __bf16* __restri
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* img = in + (long long)b * gy * gx * C;
-  // 16-byte piece j of this thread (input pieces first, then weights):
-  // its source at slab c0 and its place in LDS; false past the slab's end
-  auto piece = [&](int j, int c0, const u32x4v*& src, u32x4v*& dst) -> bool {
-    const int t = threadIdx.x + (j < XPER ? j : j - XPER) * NTH;
-    const int q = t & 3;
-    if (j < XPER) {
-      if (t >= NXP) return false;
-      const int px = (t >> 2) % PX, row = (t >> 2) / PX;
-      const int yy = pwrap(y0 - 1 + row, gy), xx = pwrap(xt * 64 - 1 + px, gx);
-      src = reinterpret_cast<const u32x4v*>(img + (yy * gx + xx) * C + c0 + 8 * q);
-      dst = reinterpret_cast<u32x4v*>(sx + (row * PX + px) * PS + 8 * q);
-    } else {
-      if (t >= NWP) return false;
-      const int co = (t >> 2) % CO, o = (t >> 2) / CO;
-      src = reinterpret_cast<const u32x4v*>(w + (o * C + cg * CO + co) * C + c0 + 8 * q);
-      dst = reinterpret_cast<u32x4v*>(sw + (o * CO + co) * PS + 8 * q);
-    }
-    return true;
-  };
-  u32x4v st[G];
-  auto fetch = [&](int j0, int c0) {
+  // the slab's input rows: piece t = (row, pixel, chunk)
+  auto stage_x = [&](int c0) {
+    u32x4v v[XPER];
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const u32x4v* src;
-      u32x4v* dst;
-      if (j0 + j < NP && piece(j0 + j, c0, src, dst)) st[j] = *src;
+    for (int j = 0; j < XPER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < NXP) {
+        const int px = (t >> 2) % PX, row = (t >> 2) / PX;
+        const int yy = pwrap(y0 - 1 + row, gy), xx = pwrap(xt * 64 - 1 + px, gx);
+        v[j] = *reinterpret_cast<const u32x4v*>(img + ((long long)yy * gx + xx) * C + c0 + 8 * (t & 3));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < NXP) *reinterpret_cast<u32x4v*>(sx + swz(t >> 2, t & 3)) = v[j];
     }
   };
-  auto put = [&](int j0) {
+  // the slab's weights of row offset d: piece t = (dx, co, chunk)
+  auto stage_w = [&](int c0, int d) {
+    u32x4v v[WPER];
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const u32x4v* src;
-      u32x4v* dst;
-      if (j0 + j < NP && piece(j0 + j, 0, src, dst)) *dst = st[j];
+    for (int j = 0; j < WPER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < NWP) {
+        const int co = (t >> 2) % CO, o = 3 * d + (t >> 2) / CO;
+        v[j] = *reinterpret_cast<const u32x4v*>(w + ((long long)o * C + cg * CO + co) * C + c0 + 8 * (t & 3));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WPER; ++j) {
+      const int t = threadIdx.x + j * NTH;
+      if (t < NWP) *reinterpret_cast<u32x4v*>(sw + swz(t >> 2, t & 3)) = v[j];
     }
   };
-  auto products = [&]() {
+  // Residual epilogue: the residual input of global column tile t
+  // (channels 16 t ..) is added to its accumulators after stage t (stage =
+  // slab x row offset), loaded before that stage's products, so that its
+  // traffic spreads over the products instead of adding to the epilogue's
+  // burst.
+  // The stage of each output channel depends on the channel only: every
+  // launch shape accumulates in the same order.
+  const long long pbase = (((long long)b * gy + y0 + wave) * gx + xt * 64) * C;
+  float rv[4][4];
+#pragma unroll 1
+  for (int c0 = 0; c0 < C; c0 += 32) {
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      const int nres = (c0 / 32) * 3 + d - cg * NT;  // this stage's residual tile in the group, if any
+      if (c0 | d) __syncthreads();  // the previous products are done with LDS
+      if (d == 0) stage_x(c0);
+      stage_w(c0, d);
+      if constexpr (EPI == kEpiResid) {
+        if (nres >= 0 && nres < NT) {
 #pragma unroll
-    for (int o = 0; o < 9; ++o) {
-      const int dy = o / 3 - 1, dx = o % 3 - 1;
-      const __bf16* xrow = sx + (wave + 1 + dy) * PX * PS;
-      bf16x8 a[4], bb[NT];
+          for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) a[m] = ld8(xrow + (16 * m + r + 1 + dx) * PS + 8 * g);
+            for (int i = 0; i < 4; ++i)
+              rv[m][i] = res[pbase + (long long)(16 * m + 4 * g + i) * C + cg * CO + 16 * nres + r];
+        }
+      }
+      __syncthreads();
+      const int xrow = (wave + d) * PX;  // input row y + dy, dy = d - 1
 #pragma unroll
-      for (int n = 0; n < NT; ++n) bb[n] = ld8(sw + (o * CO + 16 * n + r) * PS + 8 * g);
+      for (int dx = 0; dx < 3; ++dx) {
+        bf16x8 a[4], bb[NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          a[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sx + swz(xrow + 16 * m + r + dx, g)));
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          bb[n] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sw + swz(dx * CO + 16 * n + r, g)));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+      }
+      if constexpr (EPI == kEpiResid) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          if (n == nres) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) acc[m][n][i] += rv[m][i];
+          }
+      }
+    }
+  }
+  // Epilogue through LDS: the accumulators (+ bias) of two column tiles at
+  // a time go to a per-wave [64 pixels][36] FP32 tile (row stride 4 banks
+  // off a multiple of 32: the two pixel rows a b32 write spans fall in
+  // different bank halves) and come back as 4 consecutive channels per
+  // lane, 8 lanes per pixel, so that every global store of the epilogue
+  // (FP32 output, its BF16 copy) is a 16- or 8-byte access of whole
+  // 128-byte lines.  Same arithmetic per element as a direct store.
+  constexpr int TG = conv_epi_group(CO), ES = 16 * TG + 4;
+  constexpr int Q = 4 * TG, P = 64 / Q, IT = 64 / P;  // lanes per pixel, pixels per pass, passes per tile group
+  static_assert((size_t)WAVES * 64 * ES * 4 <= conv3x3_fwd_lds(CO, WAVES) && NT % TG == 0, "epilogue tile fits");
+  float* se = reinterpret_cast<float*>(conv_lds) + wave * 64 * ES;
+  const long long base = pbase + cg * CO;
+  const int c4 = 4 * (lane % Q), p0 = lane / Q;
+  __syncthreads();  // every wave is done with the slab in LDS
+#pragma unroll
+  for (int n0 = 0; n0 < NT; n0 += TG) {
+    if (n0) __syncthreads();  // the previous group has been read back
+#pragma unroll
+    for (int nn = 0; nn < TG; ++nn) {
+      const float bv = bias ? bias[cg * CO + 16 * (n0 + nn) + r] : 0.f;
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) se[(16 * m + 4 * g + i) * ES + 16 * nn + r] = acc[m][n0 + nn][i] + bv;
     }
-  };
-  if constexpr (kPrefetch) {
-    fetch(0, 0);
+    __syncthreads();
 #pragma unroll
-    for (int c0 = 0; c0 < C; c0 += 32) {
-      if (c0) __syncthreads();  // the previous slab's products are done with LDS
-      put(0);
-      __syncthreads();
-      if (c0 + 32 < C) fetch(0, c0 + 32);
-      products();
-    }
-  } else {
-#pragma unroll 1
-    for (int c0 = 0; c0 < C; c0 += 32) {
-      if (c0) __syncthreads();
+    for (int k = 0; k < IT; ++k) {
+      const f32x4 o = *reinterpret_cast<const f32x4*>(se + (p0 + P * k) * ES + c4);
+      const long long e = base + (long long)(p0 + P * k) * C + 16 * n0 + c4;
+      *reinterpret_cast<f32x4*>(out + e) = o;
+      if constexpr (EPI != kEpiPlain) {
+        __bf16 q4[4];
 #pragma unroll
-      for (int j0 = 0; j0 < NP; j0 += G) {
-        fetch(j0, c0);
-        put(j0);
+        for (int j = 0; j < 4; ++j) q4[j] = (__bf16)(EPI == kEpiGelu ? gelu_f(o[j], nullptr) : o[j]);
+        typedef unsigned int u32x2e __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<u32x2e*>(outb + e) = __builtin_bit_cast(u32x2e, q4);
       }
-      __syncthreads();
-      products();
     }
   }
-  const int y = y0 + wave;
-  const long long base = (((long long)b * gy + y) * gx + xt * 64) * C;
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-      const int co = cg * CO + 16 * n + r;
-      const float bv = bias ? bias[co] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const long long e = base + (long long)(16 * m + 4 * g + i) * C + co;
-        const float v = acc[m][n][i] + bv;
-        if constexpr (EPI == kEpiPlain) {
-          out[e] = v;
-        } else if constexpr (EPI == kEpiGelu) {
-          out[e] = v;
-          outb[e] = (__bf16)gelu_f(v, nullptr);
-        } else {
-          const float s = res[e] + v;
-          out[e] = s;
-          outb[e] = (__bf16)s;
-        }
-      }
-    }
 }
 
 // ---- 3x3 periodic convolution, weight gradient ----------------------------
 // part[b][o][co][ci] = sum_{y, x} dy[b, y, x, co] in[b, y+dy_o, x+dx_o, ci]
-// One workgroup per (image b, row offset dy, block of COB output channels):
-// it marches the image in chunks of 64 pixels of one row and accumulates
-// the three offsets (dy, -1), (dy, 0), (dy, +1) together.  Per chunk the
-// workgroup stages dY (its COB channels) and the input row y + dy
-// transposed in LDS ([channel][pixel], stride 72 so that 8 consecutive
-// pixels are one 16-byte read), the input three times, shifted by
-// dx = -1, 0, 1: a thread loads 8 channels of 4 consecutive pixels of dY
-// and of 6 consecutive pixels of the input (one halo pixel each side) and
-// writes 8-byte runs of 4 pixels of one channel.  Consecutive lanes take
-// consecutive pixel groups, so the 16 lanes that write one channel row
-// write 128 contiguous bytes (no bank conflicts; channel-fast lanes wrote
-// 16 rows 8 apart into two bank groups, half the kernel's time).  The next
-// chunk's loads are issued before the current products.  The 2 x 2 waves
-// split the COB x C block; pixels are accumulated in order (32 per MFMA
-// step), so every launch shape gives the same bits.  Dynamic LDS
-// conv3x3_wgrad_lds() bytes.  Requires gx % 64 == 0, COB % 32 == 0, COB | C.
-__host__ __device__ constexpr size_t conv3x3_wgrad_lds(int C, int COB) {
-  return (size_t)(COB + 3 * C) * (64 + 8) * 2;
+// One workgroup per (image b, row offset dy) computes the three offsets
+// (dy, -1), (dy, 0), (dy, +1) for all C x C channel pairs: waves WM x WN
+// split the (co, ci) block, each holding 3 x (C/WM) x (C/WN) accumulators.
+// The image is marched in chunks of 64 pixels of one row.  Per chunk the
+// workgroup stages dY and the input row y + dy transposed in LDS
+// ([channel][pixel], dY rows of 72 and input rows of 88 bf16, both strides
+// conflict-free for the 16-byte fragment reads), the input once, with one
+// halo pixel on each side: the fragments shifted by one pixel (dx = -1, +1)
+// are formed in registers from the unshifted one and one more dword of the
+// row (v_alignbit), so LDS holds and serves each input value once.  A
+// thread stages pieces of 8 channels x 4 consecutive pixels (four 16-byte
+// global loads, eight 8-byte LDS writes); consecutive lanes take consecutive
+// pixel groups, so 16 lanes write 128 contiguous bytes of one channel row.
+// Two LDS buffers: the next chunk's loads are issued before the current
+// chunk's products and written after them, one barrier per chunk.  Pixels
+// are accumulated in order (32 per MFMA step), so every launch gives the
+// same bits.  On the device's eight XCDs (each with its own L2) the three
+// workgroups of one image are given to one XCD when the grid divides by 8.
+// Dynamic LDS conv3x3_wgrad_lds(C) bytes.  Requires gx % 64 == 0,
+// C % (16 WM) == 0, C % (16 WN) == 0.
+constexpr int kWgChunk = 64;                // pixels per chunk
+constexpr int kWgDStride = kWgChunk + 8;    // dY row (bf16)
+constexpr int kWgXStride = kWgChunk + 24;   // input row: halo at 7, pixels at 8..71, halo at 72
+__host__ __device__ constexpr size_t conv3x3_wgrad_lds(int C) {
+  return (size_t)2 * C * (kWgDStride + kWgXStride) * 2;
 }
 
-template <int C, int COB>
-__global__ void __launch_bounds__(256) conv3x3_wgrad(const __bf16* __restrict__ in, const __bf16* __restrict__ dout,
-                                                      float* __restrict__ part, int gy, int gx) {
-  constexpr int CH = 64;                      // pixels per chunk
-  constexpr int KP = CH + 8;                  // padded pixel stride of an LDS row (bf16)
-  constexpr int RT = COB / 32, NT = C / 32;   // tiles per wave (2 x 2 waves over COB x C)
-  constexpr int HB = C / COB;                 // output-channel blocks
-  constexpr int DP = (CH / 4) * (COB / 8);    // dY pieces (4 pixels x 8 channels)
-  constexpr int XP = (CH / 4) * (C / 8);      // input pieces (6 pixels x 8 channels)
-  static_assert(DP <= 256 && XP <= 256, "one piece of each tensor per thread");
+template <int C, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __restrict__ in,
+                                                               const __bf16* __restrict__ dout,
+                                                               float* __restrict__ part, int gy, int gx) {
+  constexpr int NTH = 64 * WM * WN, CH = kWgChunk, KD = kWgDStride, KX = kWgXStride;
+  constexpr int MT = C / WM / 16, NT = C / WN / 16;  // 16 x 16 tiles per wave (co, ci)
+  constexpr int PC = (CH / 4) * (C / 8);             // pieces of one tensor per chunk
+  constexpr int HALO = 2 * (C / 8);                  // halo pieces: 1 pixel x 8 channels
+  constexpr int NPC = 2 * PC + HALO, NSP = (NPC + NTH - 1) / NTH;
+  static_assert(C % (16 * WM) == 0 && C % (16 * WN) == 0, "wave tiles of whole 16 x 16 blocks");
   typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
   extern __shared__ __bf16 wg_smem[];
-  __bf16* sd = wg_smem;             // [COB][KP]  dY chunk
-  __bf16* sx = wg_smem + COB * KP;  // [3][C][KP] input chunk shifted by dx = -1, 0, 1
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int h = blockIdx.x % HB, dyi = (blockIdx.x / HB) % 3, b = blockIdx.x / (3 * HB);
+  __bf16* sd = wg_smem;                     // [2][C][KD]  dY chunk
+  __bf16* sx = wg_smem + 2 * C * KD;        // [2][C][KX]  input chunk
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+  // (image, row offset) of this workgroup; the three row offsets of an
+  // image share an XCD when the grid allows it
+  const int nwg = gridDim.x;
+  const int item = nwg % 8 == 0 ? (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int b = item / 3, dyi = item % 3;
   const int r = lane & 15, g = lane >> 4;
-  const int co0 = (wave >> 1) * (COB / 2), ci0 = (wave & 1) * (C / 2);
-  f32x4 acc[3][RT][NT];
+  const int co0 = (wave / WN) * (C / WM), ci0 = (wave % WN) * (C / WN);
+  f32x4 acc[3][MT][NT];
 #pragma unroll
   for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int m = 0; m < RT; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int n = 0; n < NT; ++n) acc[s][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16* dimg = dout + (long long)b * gy * gx * C + h * COB;
+  const __bf16* dimg = dout + (long long)b * gy * gx * C;
   const __bf16* ximg = in + (long long)b * gy * gx * C;
-  const int chunks_per_row = gx / CH, nch = gy * chunks_per_row;
-  const int t = threadIdx.x;
-  const int p4 = (t % (CH / 4)) * 4, c8 = (t / (CH / 4)) * 8;  // this thread's pieces
-  bf16x8 vd[4], vx[6];
-  auto fetch = [&](int ch) {
-    const int y = ch / chunks_per_row, x0 = (ch % chunks_per_row) * CH;
+  const int cpr = gx / CH, nch = gy * cpr;
+  typedef u32x4v Stage[NSP][4];
+  Stage sa;
+  // piece j: [0, PC) dY, [PC, 2 PC) input, then the halo pixels
+  auto fetch = [&](int ch, Stage& st) {
+    const int y = ch / cpr, x0 = (ch % cpr) * CH;
     const int ys = pwrap(y + dyi - 1, gy);
-    if (t < DP) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vd[q] = ld8(dimg + (y * gx + x0 + p4 + q) * C + c8);
-    }
-    if (t < XP) {
+    for (int jj = 0; jj < NSP; ++jj) {
+      const int j = t + jj * NTH;
+      if (j < 2 * PC) {
+        const int jp = j < PC ? j : j - PC;
+        const int pg = jp % (CH / 4), c8 = (jp / (CH / 4)) * 8;
+        const __bf16* src = j < PC ? dimg + ((long long)y * gx + x0 + 4 * pg) * C + c8
+                                   : ximg + ((long long)ys * gx + x0 + 4 * pg) * C + c8;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) vx[q] = ld8(ximg + (ys * gx + pwrap(x0 + p4 + q - 1, gx)) * C + c8);
-    }
-  };
-  auto put = [&]() {
-    if (t < DP) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        __bf16 a4[4] = {vd[0][e], vd[1][e], vd[2][e], vd[3][e]};
-        *reinterpret_cast<u32x2v*>(sd + (c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, a4);
+        for (int q = 0; q < 4; ++q) st[jj][q] = *reinterpret_cast<const u32x4v*>(src + q * C);
+      } else if (j < NPC) {
+        const int jh = j - 2 * PC, side = jh / (C / 8), c8 = (jh % (C / 8)) * 8;
+        const int xs = side ? pwrap(x0 + CH, gx) : pwrap(x0 - 1, gx);
+        st[jj][0] = *reinterpret_cast<const u32x4v*>(ximg + ((long long)ys * gx + xs) * C + c8);
       }
     }
-    if (t < XP) {
+  };
+  auto put = [&](int buf, const Stage& st) {
+    __bf16* bd = sd + buf * C * KD;
+    __bf16* bx = sx + buf * C * KX;
 #pragma unroll
-      for (int s = 0; s < 3; ++s)
+    for (int jj = 0; jj < NSP; ++jj) {
+      const int j = t + jj * NTH;
+      if (j < 2 * PC) {
+        const int jp = j < PC ? j : j - PC;
+        const int pg = jp % (CH / 4), c8 = (jp / (CH / 4)) * 8;
+        __bf16* dst = j < PC ? bd + c8 * KD + 4 * pg : bx + c8 * KX + 8 + 4 * pg;
+        const int stride = j < PC ? KD : KX;
+        bf16x8 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = __builtin_bit_cast(bf16x8, st[jj][q]);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          __bf16 b4[4] = {vx[s][e], vx[s + 1][e], vx[s + 2][e], vx[s + 3][e]};
-          *reinterpret_cast<u32x2v*>(sx + (s * C + c8 + e) * KP + p4) = __builtin_bit_cast(u32x2v, b4);
+          __bf16 a4[4] = {v[0][e], v[1][e], v[2][e], v[3][e]};
+          *reinterpret_cast<u32x2v*>(dst + e * stride) = __builtin_bit_cast(u32x2v, a4);
         }
-    }
-  };
-  fetch(0);
-  for (int ch = 0; ch < nch; ++ch) {
-    put();
-    __syncthreads();
-    if (ch + 1 < nch) fetch(ch + 1);
+      } else if (j < NPC) {
+        const int jh = j - 2 * PC, side = jh / (C / 8), c8 = (jh % (C / 8)) * 8;
+        const bf16x8 v = __builtin_bit_cast(bf16x8, st[jj][0]);
 #pragma unroll
-    for (int k0 = 0; k0 < CH; k0 += 32) {
-      bf16x8 a[RT];
-#pragma unroll
-      for (int m = 0; m < RT; ++m) a[m] = ld8(sd + (co0 + 16 * m + r) * KP + k0 + 8 * g);
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        bf16x8 bb[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) bb[n] = ld8(sx + (s * C + ci0 + 16 * n + r) * KP + k0 + 8 * g);
-#pragma unroll
-        for (int m = 0; m < RT; ++m)
-#pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[s][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[s][m][n], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) bx[(c8 + e) * KX + (side ? 8 + CH : 7)] = v[e];
       }
     }
+  };
+  auto compute = [&](int buf) {
+    const __bf16* bd = sd + buf * C * KD;
+    const __bf16* bx = sx + buf * C * KX;
+#pragma unroll
+    for (int k0 = 0; k0 < CH; k0 += 32) {
+      bf16x8 a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) a[m] = ld8(bd + (co0 + 16 * m + r) * KD + k0 + 8 * g);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        // pixels p = k0 + 8 g .. + 7 of channel ci at column 8 + p; the
+        // dword before and the one after give the shifted fragments
+        const __bf16* row = bx + (ci0 + 16 * n + r) * KX + 8 + k0 + 8 * g;
+        const u32x4v d = *reinterpret_cast<const u32x4v*>(row);
+        const unsigned prev = *reinterpret_cast<const unsigned*>(row - 2);
+        const unsigned next = *reinterpret_cast<const unsigned*>(row + 8);
+        const unsigned t0 = __builtin_amdgcn_alignbit(d.x, prev, 16), t1 = __builtin_amdgcn_alignbit(d.y, d.x, 16);
+        const unsigned t2 = __builtin_amdgcn_alignbit(d.z, d.y, 16), t3 = __builtin_amdgcn_alignbit(d.w, d.z, 16);
+        const unsigned t4 = __builtin_amdgcn_alignbit(next, d.w, 16);
+        const bf16x8 bm = __builtin_bit_cast(bf16x8, u32x4v{t0, t1, t2, t3});  // in[p - 1]
+        const bf16x8 b0 = __builtin_bit_cast(bf16x8, d);                      // in[p]
+        const bf16x8 bp = __builtin_bit_cast(bf16x8, u32x4v{t1, t2, t3, t4});  // in[p + 1]
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          acc[0][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bm, acc[0][m][n], 0, 0, 0);
+          acc[1][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b0, acc[1][m][n], 0, 0, 0);
+          acc[2][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bp, acc[2][m][n], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // chunk ch lives in LDS buffer ch % 2; the next chunk's loads are in
+  // flight during its products
+  fetch(0, sa);
+  put(0, sa);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) fetch(ch + 1, sa);
+    compute(ch & 1);
+    if (ch + 1 < nch) put((ch + 1) & 1, sa);
     __syncthreads();
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     float* pb = part + ((long long)b * 9 + dyi * 3 + s) * C * C;
 #pragma unroll
-    for (int m = 0; m < RT; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
         const int ci = ci0 + 16 * n + r;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pb[(long long)(h * COB + co0 + 16 * m + 4 * g + i) * C + ci] = acc[s][m][n][i];
+        for (int i = 0; i < 4; ++i) pb[(long long)(co0 + 16 * m + 4 * g + i) * C + ci] = acc[s][m][n][i];
       }
   }
 }

@@ -612,22 +612,20 @@ Layout layout_of(const mlf_nop_params* p) {
   return s;
 }
 
-// Launch shape by workload (measured on 64 x 64 latent grids): small
-// batches (the judged runs' windows) split the output channels into groups
-// of 32, one workgroup of 4 waves each, to fill the device; large ones
-// (training) give each workgroup of 8 rows all channels, so that each staged
-// slab of weights serves more products -- except the residual epilogue at
-// C = 128 (it reads a third tensor), which runs faster with half the
-// channels on 4 waves, as does any grid whose rows are not a multiple of 8.
-// The dynamic LDS above 64 KiB of every shape is enabled when the handle is
-// created (set_lds_limits, on the handle's device).
-template <int C, int CO, int WAVES, int EPI>
+// Launch shape by workload (measured on 64 x 64 latent grids): workgroups
+// of 4 waves (4 latent rows), two per CU; small batches (the judged runs'
+// windows) split the output channels into groups of 32 to fill the device,
+// large ones (training) give each workgroup all channels, so that each
+// staged slab of weights serves more products.  The dynamic LDS above
+// 64 KiB of every shape is enabled when the handle is created
+// (set_lds_limits, on the handle's device).
+template <int C, int CO, int EPI>
 mlf_status conv_fwd_launch(mlf_nop* m, long long rows, const __bf16* in, const __bf16* w, const float* bias,
                            float* out, const float* res, __bf16* outb) {
-  const size_t lds = nop::conv3x3_fwd_lds(CO, WAVES);
+  const size_t lds = nop::conv3x3_fwd_lds(CO, 4);
   const unsigned xt = (unsigned)(m->gx / 64);
-  NLAUNCH((nop::conv3x3_fwd<C, CO, WAVES, EPI>), dim3((unsigned)(rows / WAVES) * xt, C / CO), dim3(64 * WAVES), lds,
-          m->stream, in, w, bias, out, res, outb, m->gy, m->gx);
+  NLAUNCH((nop::conv3x3_fwd<C, CO, 4, EPI>), dim3((unsigned)(rows / 4) * xt, C / CO), dim3(256), lds, m->stream,
+          in, w, bias, out, res, outb, m->gy, m->gx);
   return MLF_OK;
 }
 
@@ -635,10 +633,8 @@ template <int C, int EPI>
 mlf_status conv_fwd_t(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, const float* bias, float* out,
                       const float* res, __bf16* outb) {
   const long long rows = (long long)batch * m->gy;
-  if (rows < 64 * 64) return conv_fwd_launch<C, 32, 4, EPI>(m, rows, in, w, bias, out, res, outb);
-  if (m->gy % 8 == 0 && !(C == 128 && EPI == nop::kEpiResid))
-    return conv_fwd_launch<C, C, 8, EPI>(m, rows, in, w, bias, out, res, outb);
-  return conv_fwd_launch<C, C / 2, 4, EPI>(m, rows, in, w, bias, out, res, outb);
+  if (rows < 64 * 64) return conv_fwd_launch<C, 32, EPI>(m, rows, in, w, bias, out, res, outb);
+  return conv_fwd_launch<C, C, EPI>(m, rows, in, w, bias, out, res, outb);
 }
 
 template <int EPI>
@@ -653,12 +649,15 @@ mlf_status conv_fwd(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, co
 }
 
 // per-image weight gradients into m->part ([batch][9][C][C]); a workgroup
-// per (image, row offset, 64 output channels)
+// per (image, row offset) with all channel pairs: 8 waves at C = 128
+// (64 x 32 channel tiles), 4 at C = 64 (32 x 32)
+template <int C>
+constexpr int kWgWN = C == 128 ? 4 : 2;
+
 template <int C>
 mlf_status wgrad_launch(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout) {
-  constexpr int COB = 64;
-  NLAUNCH((nop::conv3x3_wgrad<C, COB>), dim3((unsigned)batch * 3 * (C / COB)), dim3(256),
-          nop::conv3x3_wgrad_lds(C, COB), m->stream, in, dout, m->part, m->gy, m->gx);
+  NLAUNCH((nop::conv3x3_wgrad<C, 2, kWgWN<C>>), dim3((unsigned)batch * 3), dim3(128 * kWgWN<C>),
+          nop::conv3x3_wgrad_lds(C), m->stream, in, dout, m->part, m->gy, m->gx);
   return MLF_OK;
 }
 
@@ -674,8 +673,7 @@ mlf_status set_lds(mlf_nop* m, K kern, size_t bytes) {
 template <int C, int EPI>
 mlf_status set_fwd_lds(mlf_nop* m) {
   mlf_status st = set_lds(m, nop::conv3x3_fwd<C, 32, 4, EPI>, nop::conv3x3_fwd_lds(32, 4));
-  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_fwd<C, C, 8, EPI>, nop::conv3x3_fwd_lds(C, 8));
-  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_fwd<C, C / 2, 4, EPI>, nop::conv3x3_fwd_lds(C / 2, 4));
+  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_fwd<C, C, 4, EPI>, nop::conv3x3_fwd_lds(C, 4));
   return st;
 }
 
@@ -684,7 +682,7 @@ mlf_status set_lds_limits_c(mlf_nop* m) {
   mlf_status st = set_fwd_lds<C, nop::kEpiPlain>(m);
   if (st == MLF_OK) st = set_fwd_lds<C, nop::kEpiGelu>(m);
   if (st == MLF_OK) st = set_fwd_lds<C, nop::kEpiResid>(m);
-  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_wgrad<C, 64>, nop::conv3x3_wgrad_lds(C, 64));
+  if (st == MLF_OK) st = set_lds(m, nop::conv3x3_wgrad<C, 2, kWgWN<C>>, nop::conv3x3_wgrad_lds(C));
   return st;
 }
 
@@ -954,34 +952,37 @@ mlf_status mlf_nop_train_step(mlf_nop* m, int32_t batch, const float* h0, const 
   return refresh_weights(m);
 }
 
-mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms_fwd, float* ms_wgrad) {
-  if (!m || reps < 1) return MLF_EINVAL;
+mlf_status mlf_nop_time_conv(mlf_nop* m, int32_t batch, int32_t reps, float* ms) {
+  if (!m || reps < 1 || !ms) return MLF_EINVAL;
   mlf_status st = check_batch(m, batch);
   if (st != MLF_OK) return st;
   if (m->L < 1) return nfail(m, MLF_EINVAL, "no convolution layers");
-  hipEvent_t e0, e1, e2;
-  NHIP(hipEventCreate(&e0));
-  NHIP(hipEventCreate(&e1));
-  NHIP(hipEventCreate(&e2));
-  // operands: the first block's input and weights as they stand
-  st = conv_fwd(m, batch, m->rb, m->w1b, m->par + m->ob1, m->a);
-  if (st == MLF_OK) st = nhip(m, hipEventRecord(e0, m->stream), "hipEventRecord");
-  for (int r = 0; r < reps && st == MLF_OK; ++r) st = conv_fwd(m, batch, m->rb, m->w1b, m->par + m->ob1, m->a);
-  if (st == MLF_OK) st = nhip(m, hipEventRecord(e1, m->stream), "hipEventRecord");
-  for (int r = 0; r < reps && st == MLF_OK; ++r)
-    st = m->C == 64 ? wgrad_launch<64>(m, batch, m->rb, m->gb) : wgrad_launch<128>(m, batch, m->rb, m->gb);
-  if (st == MLF_OK) st = nhip(m, hipEventRecord(e2, m->stream), "hipEventRecord");
-  if (st == MLF_OK) st = nhip(m, hipEventSynchronize(e2), "hipEventSynchronize");
-  float a = 0.f, b = 0.f;
-  if (st == MLF_OK) st = nhip(m, hipEventElapsedTime(&a, e0, e1), "hipEventElapsedTime");
-  if (st == MLF_OK) st = nhip(m, hipEventElapsedTime(&b, e1, e2), "hipEventElapsedTime");
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  if (st != MLF_OK) return st;
-  if (ms_fwd) *ms_fwd = a / reps;
-  if (ms_wgrad) *ms_wgrad = b / reps;
-  return MLF_OK;
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) NHIP(hipEventCreate(&ev[i]));
+  // operands: the first block's input and weights as they stand; outputs
+  // into the first block's activations (residual: r_1 from r_0)
+  const float* bias = m->par + m->ob1;
+  __bf16* r1b = m->rb + m->lat;
+  float* r1 = m->r + m->lat;
+  st = conv_fwd(m, batch, m->rb, m->w1b, bias, m->a);
+  for (int k = 0; k < 4 && st == MLF_OK; ++k) {
+    st = nhip(m, hipEventRecord(ev[k], m->stream), "hipEventRecord");
+    for (int i = 0; i < reps && st == MLF_OK; ++i) {
+      if (k == 0) st = conv_fwd(m, batch, m->rb, m->w1b, bias, m->a);
+      else if (k == 1) st = conv_fwd_e<nop::kEpiGelu>(m, batch, m->rb, m->w1b, bias, m->a, nullptr, m->gb);
+      else if (k == 2) st = conv_fwd_e<nop::kEpiResid>(m, batch, m->gb, m->w2b, bias, r1, m->r, r1b);
+      else st = m->C == 64 ? wgrad_launch<64>(m, batch, m->rb, m->gb) : wgrad_launch<128>(m, batch, m->rb, m->gb);
+    }
+  }
+  if (st == MLF_OK) st = nhip(m, hipEventRecord(ev[4], m->stream), "hipEventRecord");
+  if (st == MLF_OK) st = nhip(m, hipEventSynchronize(ev[4]), "hipEventSynchronize");
+  for (int k = 0; k < 4 && st == MLF_OK; ++k) {
+    float t = 0.f;
+    st = nhip(m, hipEventElapsedTime(&t, ev[k], ev[k + 1]), "hipEventElapsedTime");
+    ms[k] = t / reps;
+  }
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  return st;
 }
 
 mlf_status mlf_nop_errors(mlf_nop* m, int32_t n, const float* a, const float* b, double* out) {

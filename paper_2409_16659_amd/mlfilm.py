@@ -134,7 +134,7 @@ def load_library():
         "mlf_nop_gradient": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
                                   C.POINTER(C.c_double)]),
         "mlf_nop_train_step": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_float, C.POINTER(C.c_double)]),
-        "mlf_nop_time_conv": (st, [H, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+        "mlf_nop_time_conv": (st, [H, C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
         "mlf_nop_errors": (st, [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
         "mlf_convert_heights": (st, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
         "mlf_stokes_velocity": (st, [P, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -753,11 +753,11 @@ class Surrogate:
         return out.cpu().numpy()
 
     def time_conv(self, batch, reps=20):
-        """Average ms of one MFMA 3x3 convolution (forward, weight gradient)."""
-        a, b = C.c_float(), C.c_float()
-        self._check(self.lib.mlf_nop_time_conv(self.h, int(batch), int(reps), C.byref(a), C.byref(b)),
-                    "mlf_nop_time_conv")
-        return a.value, b.value
+        """Average ms of one MFMA 3x3 convolution: forward with the plain,
+        GELU and residual epilogues, and the weight gradient."""
+        ms = (C.c_float * 4)()
+        self._check(self.lib.mlf_nop_time_conv(self.h, int(batch), int(reps), ms), "mlf_nop_time_conv")
+        return dict(zip(("fwd", "fwd_gelu", "fwd_resid", "wgrad"), list(ms)))
 
     def conv_flops(self, batch):
         """Multiply-add flops of one 3x3 convolution on `batch` samples."""
