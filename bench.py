@@ -419,10 +419,12 @@ def bench_surrogate(args):
 
 
 def bench_conv_kernels(args):
-    """The surrogate's MFMA 3x3 convolutions alone (3-layer 256^2 films,
-    width 128, batch 64 of the training step): event-timed average of each
-    forward epilogue variant and of the weight gradient on activations of a
-    prediction with seeded random weights and heights."""
+    """The surrogate's MFMA 3x3 convolutions (3-layer 256^2 films, width
+    128, batch 64 of the training step): --steps forward and backward
+    passes on seeded random weights and heights (the training step's
+    launches, for a kernel trace), then the event-timed average of each
+    forward epilogue variant and of the weight gradient, --steps
+    back-to-back launches each."""
     import numpy as np
     import torch
 
@@ -434,6 +436,10 @@ def bench_conv_kernels(args):
     m.set_params(S.init_params(m, seed=0))
     rng = np.random.default_rng(1)
     h = torch.from_numpy((1.0 + 1e-2 * rng.normal(size=(64, 3, 256, 256))).astype(np.float32)).cuda()
+    h1 = h + 1e-3
+    for _ in range(args.steps):
+        m.predict(h)
+        m.gradient(h, h1)
     m.predict(h)
     ms = m.time_conv(64, reps=args.steps)
     flops = m.conv_flops(64)

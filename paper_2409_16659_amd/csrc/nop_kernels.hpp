@@ -65,8 +65,9 @@ __device__ inline bf16x8 ld8(const __bf16* p) {
 // taken in slabs of 32 (one MFMA k-step).  Per slab the workgroup stages in
 // LDS its WAVES + 2 input rows with one halo pixel on each side
 // ([row][66 pixels][32 channels] bf16), and the weights one row offset dy
-// at a time ([3 dx][CO][32] bf16, three stages per slab), so that the
-// LDS of a 4-wave workgroup (49 KiB at CO = 128) lets two workgroups share
+// at a time ([3 dx][CO][32] bf16, three stages per slab, two buffers: the
+// next stage's weights load during this stage's products), so that the
+// LDS of a 4-wave workgroup (73 KiB at CO = 128) lets two workgroups share
 // a CU: one's staging and epilogue overlap the other's products.  LDS rows
 // are 64 bytes with their four 16-byte chunks permuted by XOR with
 // (row / 2) % 4: the eight consecutive rows that eight lanes of a fragment
@@ -77,7 +78,7 @@ __device__ inline bf16x8 ld8(const __bf16* p) {
 // per pixel) and the LDS of the products and of the epilogue.
 __host__ __device__ constexpr int conv_epi_group(int CO) { return CO / 16 < 2 ? CO / 16 : 2; }
 __host__ __device__ constexpr size_t conv3x3_fwd_lds(int CO, int waves) {
-  const size_t prod = (size_t)((waves + 2) * 66 + 3 * CO) * 64;
+  const size_t prod = (size_t)((waves + 2) * 66 + 2 * 3 * CO) * 64;
   const size_t epi = (size_t)waves * 64 * (16 * conv_epi_group(CO) + 4) * 4;
   return prod > epi ? prod : epi;
 }
@@ -91,12 +92,13 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
                                                               const float* __restrict__ bias, float* __restrict__ out,
                                                               const float* __restrict__ res, __bf16* __restrict__ outb,
                                                               int gy, int gx) {
-  constexpr int NT = CO / 16, NTH = 64 * WAVES, ROWS = WAVES + 2, PX = 66;
+  constexpr int NT = CO / 16, ROWS = WAVES + 2, PX = 66;
   constexpr int NXP = ROWS * PX * 4, NWP = 3 * CO * 4;  // 16-byte pieces: input rows, one offset row of weights
-  constexpr int XPER = (NXP + NTH - 1) / NTH, WPER = (NWP + NTH - 1) / NTH;
+  constexpr int NXI = (NXP + 63) / 64, NWI = (NWP + 63) / 64;  // LDS-direct wave loads of 64 pieces
+  constexpr int NST = (C / 32) * 3;                            // stages: slab x row offset
   extern __shared__ __attribute__((aligned(16))) unsigned char conv_lds[];
-  unsigned char* sx = conv_lds;                   // [ROWS * PX] rows of 64 bytes
-  unsigned char* sw = conv_lds + ROWS * PX * 64;  // [3 * CO] rows of 64 bytes
+  unsigned char* sx = conv_lds;              // [ROWS * PX] rows of 64 bytes
+  unsigned char* sw0 = conv_lds + NXP * 16;  // [2][3 * CO] rows of 64 bytes
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int xtiles = gx / 64;
   const int xt = blockIdx.x % xtiles;
@@ -112,94 +114,102 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* img = in + (long long)b * gy * gx * C;
-  // the slab's input rows: piece t = (row, pixel, chunk)
-  auto stage_x = [&](int c0) {
-    u32x4v v[XPER];
+  // Staging with LDS-direct loads (global_load_lds_dwordx4): lane l of a
+  // wave's load i writes 16 bytes at base + 1024 i + 16 l, so piece
+  // t = 64 i + l fills position t & 3 of LDS row t / 4; the swizzle is
+  // applied on the source side (that position holds chunk
+  // (t & 3) ^ ((row / 2) % 4)).  No staging registers; the loads are waited
+  // for (vmcnt) before the barrier that publishes them.
+  auto issue_x = [&](int c0) {  // the slab's input rows: row = (tile row, pixel)
 #pragma unroll
-    for (int j = 0; j < XPER; ++j) {
-      const int t = threadIdx.x + j * NTH;
+    for (int i = wave; i < NXI; i += WAVES) {
+      const int t = 64 * i + lane;
       if (t < NXP) {
-        const int px = (t >> 2) % PX, row = (t >> 2) / PX;
-        const int yy = pwrap(y0 - 1 + row, gy), xx = pwrap(xt * 64 - 1 + px, gx);
-        v[j] = *reinterpret_cast<const u32x4v*>(img + ((long long)yy * gx + xx) * C + c0 + 8 * (t & 3));
+        const int R = t >> 2, q = (t & 3) ^ ((R >> 1) & 3);
+        const int yy = pwrap(y0 - 1 + R / PX, gy), xx = pwrap(xt * 64 - 1 + R % PX, gx);
+        __builtin_amdgcn_global_load_lds(img + ((long long)yy * gx + xx) * C + c0 + 8 * q, sx + 1024 * i, 16, 0, 0);
       }
-    }
-#pragma unroll
-    for (int j = 0; j < XPER; ++j) {
-      const int t = threadIdx.x + j * NTH;
-      if (t < NXP) *reinterpret_cast<u32x4v*>(sx + swz(t >> 2, t & 3)) = v[j];
     }
   };
-  // the slab's weights of row offset d: piece t = (dx, co, chunk)
-  auto stage_w = [&](int c0, int d) {
-    u32x4v v[WPER];
+  auto issue_w = [&](int c0, int d, int buf) {  // the slab's weights of row offset d: row = (dx, co)
+    unsigned char* sw = sw0 + buf * NWP * 16;
 #pragma unroll
-    for (int j = 0; j < WPER; ++j) {
-      const int t = threadIdx.x + j * NTH;
+    for (int i = wave; i < NWI; i += WAVES) {
+      const int t = 64 * i + lane;
       if (t < NWP) {
-        const int co = (t >> 2) % CO, o = 3 * d + (t >> 2) / CO;
-        v[j] = *reinterpret_cast<const u32x4v*>(w + ((long long)o * C + cg * CO + co) * C + c0 + 8 * (t & 3));
+        const int R = t >> 2, q = (t & 3) ^ ((R >> 1) & 3);
+        const int o = 3 * d + R / CO, co = R % CO;
+        __builtin_amdgcn_global_load_lds(w + ((long long)o * C + cg * CO + co) * C + c0 + 8 * q, sw + 1024 * i, 16,
+                                         0, 0);
       }
-    }
-#pragma unroll
-    for (int j = 0; j < WPER; ++j) {
-      const int t = threadIdx.x + j * NTH;
-      if (t < NWP) *reinterpret_cast<u32x4v*>(sw + swz(t >> 2, t & 3)) = v[j];
     }
   };
   // Residual epilogue: the residual input of global column tile t
-  // (channels 16 t ..) is added to its accumulators after stage t (stage =
-  // slab x row offset), loaded before that stage's products, so that its
-  // traffic spreads over the products instead of adding to the epilogue's
-  // burst.
-  // The stage of each output channel depends on the channel only: every
-  // launch shape accumulates in the same order.
+  // (channels 16 t ..) is added to its accumulators after stage 3 t / 2,
+  // loaded before that stage's products, so that its traffic spreads over
+  // the products instead of adding to the epilogue's burst.  The stage of each
+  // output channel depends on the channel only: every launch shape
+  // accumulates in the same order.
   const long long pbase = (((long long)b * gy + y0 + wave) * gx + xt * 64) * C;
   float rv[4][4];
+  // Stage s (slab s / 3, row offset d = s % 3) reads the input rows and
+  // weight buffer s % 2; the next stage's weights load into the other
+  // buffer during its products; a new slab's input rows load after the
+  // barrier that ends the previous slab.
+  issue_x(0);
+  issue_w(0, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 #pragma unroll 1
-  for (int c0 = 0; c0 < C; c0 += 32) {
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-      const int nres = (c0 / 32) * 3 + d - cg * NT;  // this stage's residual tile in the group, if any
-      if (c0 | d) __syncthreads();  // the previous products are done with LDS
-      if (d == 0) stage_x(c0);
-      stage_w(c0, d);
-      if constexpr (EPI == kEpiResid) {
-        if (nres >= 0 && nres < NT) {
+  for (int st = 0; st < NST; ++st) {
+    const int c0 = (st / 3) * 32, d = st % 3;
+    if (st + 1 < NST) issue_w(((st + 1) / 3) * 32, (st + 1) % 3, (st + 1) & 1);
+    // global tile t joins after stage 3 t / 2: C / 16 tiles spread over the
+    // 3 C / 32 stages (stages 0, 1, 3, 4, 6, ...)
+    const int tres = (2 * st + 2) / 3;
+    const int nres = ((3 * tres) / 2 == st ? tres : -1 - NT * (C / CO)) - cg * NT;
+    if constexpr (EPI == kEpiResid) {
+      if (nres >= 0 && nres < NT) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            rv[m][i] = res[pbase + (long long)(16 * m + 4 * g + i) * C + cg * CO + 16 * nres + r];
+      }
+    }
+    const unsigned char* sw = sw0 + (st & 1) * NWP * 16;
+    const int xrow = (wave + d) * PX;  // input row y + dy, dy = d - 1
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      bf16x8 a[4], bb[NT];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        a[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sx + swz(xrow + 16 * m + r + dx, g)));
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        bb[n] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sw + swz(dx * CO + 16 * n + r, g)));
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+    }
+    if constexpr (EPI == kEpiResid) {
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        if (n == nres) {
 #pragma unroll
           for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              rv[m][i] = res[pbase + (long long)(16 * m + 4 * g + i) * C + cg * CO + 16 * nres + r];
+            for (int i = 0; i < 4; ++i) acc[m][n][i] += rv[m][i];
         }
-      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the next stage's weights are in LDS
+    __syncthreads();                // and every wave is done with this stage's
+    if (st + 1 < NST && d == 2) {   // a new slab: its input rows
+      issue_x(c0 + 32);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      const int xrow = (wave + d) * PX;  // input row y + dy, dy = d - 1
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        bf16x8 a[4], bb[NT];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          a[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sx + swz(xrow + 16 * m + r + dx, g)));
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-          bb[n] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sw + swz(dx * CO + 16 * n + r, g)));
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
-      }
-      if constexpr (EPI == kEpiResid) {
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-          if (n == nres) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) acc[m][n][i] += rv[m][i];
-          }
-      }
     }
   }
   // Epilogue through LDS: the accumulators (+ bias) of two column tiles at
@@ -215,7 +225,6 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
   float* se = reinterpret_cast<float*>(conv_lds) + wave * 64 * ES;
   const long long base = pbase + cg * CO;
   const int c4 = 4 * (lane % Q), p0 = lane / Q;
-  __syncthreads();  // every wave is done with the slab in LDS
 #pragma unroll
   for (int n0 = 0; n0 < NT; n0 += TG) {
     if (n0) __syncthreads();  // the previous group has been read back
