@@ -8,7 +8,9 @@ which now and then moves a value across a bfloat16 rounding boundary (one
 bfloat16 ulp, 2^-8 relative); such flips pass through the following
 layers and are amplified by their gain.  Measured as relative L2 norms
 over whole tensors on these random networks: increments 4e-4 (C = 64) and
-6e-4 (C = 128), three times closer than to the unrounded FP64 network;
+6e-4 (C = 128), three times closer than to the unrounded FP64 network
+(element by element, relative to the largest increment: 4.4e-4 to
+6.3e-4, so the flips spread rather than concentrate; bar 5e-3);
 gradients at most 2.1e-3 (first convolution of a block).  The tests allow
 2e-3 for increments and 1e-2 for gradients, and compare the Adam update on
 the GPU's own gradient to 1e-6.  The oracle runs small batches; the launch
@@ -67,8 +69,14 @@ def test_predict_matches_reference(mlf, torch_cuda, C, N):
     d_ref, _ = net.forward(vec, h0)
     d_64, _ = nop.Net(N, C, 2, 1e-2, use_bf16=False).forward(vec, h0)
     e = rel(d_gpu, d_ref)
-    print(f"C={C} increment rel L2 {e:.2e} (vs unrounded FP64 network {rel(d_gpu, d_64):.2e})", flush=True)
+    # element by element, relative to the largest increment: a localised
+    # error (a wrong halo or tile) would reach O(1) here while the L2 norm
+    # of the whole tensor stayed small
+    em = float(np.abs(d_gpu - d_ref).max() / np.abs(d_ref).max())
+    print(f"C={C} increment rel L2 {e:.2e} (vs unrounded FP64 network {rel(d_gpu, d_64):.2e}), "
+          f"max-norm {em:.2e}", flush=True)
     assert e <= 2e-3
+    assert em <= 5e-3
     # each layer's mass is unchanged (FP32 sums)
     assert np.abs(out.sum(axis=(2, 3)) - h0.sum(axis=(2, 3))).max() <= 1e-6 * h0.sum(axis=(2, 3)).max()
 
