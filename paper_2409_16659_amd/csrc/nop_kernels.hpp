@@ -259,15 +259,17 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
 // (dy, -1), (dy, 0), (dy, +1) for all C x C channel pairs: waves WM x WN
 // split the (co, ci) block, each holding 3 x (C/WM) x (C/WN) accumulators.
 // The image is marched in chunks of 64 pixels of one row.  Per chunk the
-// workgroup stages dY and the input row y + dy transposed in LDS
-// ([channel][pixel], dY rows of 72 and input rows of 88 bf16, both strides
-// conflict-free for the 16-byte fragment reads), the input once, with one
-// halo pixel on each side: the fragments shifted by one pixel (dx = -1, +1)
-// are formed in registers from the unshifted one and one more dword of the
-// row (v_alignbit), so LDS holds and serves each input value once.  A
-// thread stages pieces of 8 channels x 4 consecutive pixels (four 16-byte
-// global loads, eight 8-byte LDS writes); consecutive lanes take consecutive
-// pixel groups, so 16 lanes write 128 contiguous bytes of one channel row.
+// workgroup stages dY and the input row y + dy transposed in LDS, the input
+// once: [k-half][channel] rows of 64 bytes (32 pixels, one MFMA k-step)
+// whose four 16-byte chunks are permuted by XOR with (row / 2) % 4, the
+// layout whose fragment reads (16 consecutive rows x 4 chunks) run without
+// bank conflicts on gfx950 (rows padded to 72 or 88 bf16 cost twice as
+// much); the input's two halo pixels sit in two dword arrays.  The
+// fragments shifted by one pixel (dx = -1, +1) are formed in registers
+// from the unshifted one and the dwords on either side (v_alignbit), so
+// LDS holds and serves each input value once.  A thread stages pieces of
+// 8 channels x 4 consecutive pixels (four 16-byte global loads, eight
+// 8-byte LDS writes); consecutive lanes take consecutive pixel groups.
 // Two LDS buffers: the next chunk's loads are issued before the current
 // chunk's products and written after them, one barrier per chunk.  Pixels
 // are accumulated in order (32 per MFMA step), so every launch gives the
@@ -275,27 +277,26 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
 // workgroups of one image are given to one XCD when the grid divides by 8.
 // Dynamic LDS conv3x3_wgrad_lds(C) bytes.  Requires gx % 64 == 0,
 // C % (16 WM) == 0, C % (16 WN) == 0.
-constexpr int kWgChunk = 64;                // pixels per chunk
-constexpr int kWgDStride = kWgChunk + 8;    // dY row (bf16)
-constexpr int kWgXStride = kWgChunk + 24;   // input row: halo at 7, pixels at 8..71, halo at 72
+constexpr int kWgChunk = 64;  // pixels per chunk (two k-halves of 32)
 __host__ __device__ constexpr size_t conv3x3_wgrad_lds(int C) {
-  return (size_t)2 * C * (kWgDStride + kWgXStride) * 2;
+  return (size_t)2 * (2 * 2 * C * 64 + 2 * C * 4);  // per buffer: dY and input half-rows, halo dwords
 }
 
 template <int C, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __restrict__ in,
                                                                const __bf16* __restrict__ dout,
                                                                float* __restrict__ part, int gy, int gx) {
-  constexpr int NTH = 64 * WM * WN, CH = kWgChunk, KD = kWgDStride, KX = kWgXStride;
+  constexpr int NTH = 64 * WM * WN, CH = kWgChunk;
   constexpr int MT = C / WM / 16, NT = C / WN / 16;  // 16 x 16 tiles per wave (co, ci)
   constexpr int PC = (CH / 4) * (C / 8);             // pieces of one tensor per chunk
   constexpr int HALO = 2 * (C / 8);                  // halo pieces: 1 pixel x 8 channels
   constexpr int NPC = 2 * PC + HALO, NSP = (NPC + NTH - 1) / NTH;
+  constexpr int BUFB = 2 * 2 * C * 64 + 2 * C * 4;   // bytes per buffer
   static_assert(C % (16 * WM) == 0 && C % (16 * WN) == 0, "wave tiles of whole 16 x 16 blocks");
   typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
-  extern __shared__ __bf16 wg_smem[];
-  __bf16* sd = wg_smem;                     // [2][C][KD]  dY chunk
-  __bf16* sx = wg_smem + 2 * C * KD;        // [2][C][KX]  input chunk
+  extern __shared__ __attribute__((aligned(16))) unsigned char wg_lds[];
+  // buffer layout: dY rows [2][C], input rows [2][C] (64 bytes each), then
+  // halo dwords [2][C]: (0, in[-1]) and (in[64], 0) as bf16 pairs
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
   // (image, row offset) of this workgroup; the three row offsets of an
   // image share an XCD when the grid allows it
@@ -316,7 +317,8 @@ __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __re
   const int cpr = gx / CH, nch = gy * cpr;
   typedef u32x4v Stage[NSP][4];
   Stage sa;
-  // piece j: [0, PC) dY, [PC, 2 PC) input, then the halo pixels
+  // piece j: [0, PC) dY, [PC, 2 PC) input (pixel group j % 16, channels
+  // 8 (j / 16) ..), then the halo pixels
   auto fetch = [&](int ch, Stage& st) {
     const int y = ch / cpr, x0 = (ch % cpr) * CH;
     const int ys = pwrap(y + dyi - 1, gy);
@@ -338,48 +340,63 @@ __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __re
     }
   };
   auto put = [&](int buf, const Stage& st) {
-    __bf16* bd = sd + buf * C * KD;
-    __bf16* bx = sx + buf * C * KX;
+    unsigned char* base = wg_lds + buf * BUFB;
 #pragma unroll
     for (int jj = 0; jj < NSP; ++jj) {
       const int j = t + jj * NTH;
       if (j < 2 * PC) {
-        const int jp = j < PC ? j : j - PC;
+        const bool isd = j < PC;
+        const int jp = isd ? j : j - PC;
         const int pg = jp % (CH / 4), c8 = (jp / (CH / 4)) * 8;
-        __bf16* dst = j < PC ? bd + c8 * KD + 4 * pg : bx + c8 * KX + 8 + 4 * pg;
-        const int stride = j < PC ? KD : KX;
+        const int kh = pg / 8, q = (pg % 8) / 2;
+        const int row0 = (isd ? 0 : 2 * C) + kh * C + c8;
         bf16x8 v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = __builtin_bit_cast(bf16x8, st[jj][q]);
+        for (int qq = 0; qq < 4; ++qq) v[qq] = __builtin_bit_cast(bf16x8, st[jj][qq]);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           __bf16 a4[4] = {v[0][e], v[1][e], v[2][e], v[3][e]};
-          *reinterpret_cast<u32x2v*>(dst + e * stride) = __builtin_bit_cast(u32x2v, a4);
+          *reinterpret_cast<u32x2v*>(base + swz(row0 + e, q) + 8 * (pg % 2)) = __builtin_bit_cast(u32x2v, a4);
         }
       } else if (j < NPC) {
         const int jh = j - 2 * PC, side = jh / (C / 8), c8 = (jh % (C / 8)) * 8;
-        const bf16x8 v = __builtin_bit_cast(bf16x8, st[jj][0]);
+        // channels c8 .. c8 + 7, two per dword (low half first); taken apart
+        // with shifts: a bit cast of a vector element compiled to element 0
+        // for every e here
+        const u32x4v w = st[jj][0];
+        unsigned* hx = reinterpret_cast<unsigned*>(base + 4 * C * 64) + side * C + c8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bx[(c8 + e) * KX + (side ? 8 + CH : 7)] = v[e];
+        for (int e = 0; e < 8; ++e) {
+          const unsigned bits = (e & 1) ? w[e / 2] >> 16 : w[e / 2] & 0xffffu;
+          hx[e] = side ? bits : bits << 16;
+        }
       }
     }
   };
   auto compute = [&](int buf) {
-    const __bf16* bd = sd + buf * C * KD;
-    const __bf16* bx = sx + buf * C * KX;
+    const unsigned char* base = wg_lds + buf * BUFB;
+    const unsigned* hx = reinterpret_cast<const unsigned*>(base + 4 * C * 64);
 #pragma unroll
-    for (int k0 = 0; k0 < CH; k0 += 32) {
+    for (int kh = 0; kh < 2; ++kh) {
       bf16x8 a[MT];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) a[m] = ld8(bd + (co0 + 16 * m + r) * KD + k0 + 8 * g);
+      for (int m = 0; m < MT; ++m)
+        a[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(base + swz(kh * C + co0 + 16 * m + r, g)));
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
-        // pixels p = k0 + 8 g .. + 7 of channel ci at column 8 + p; the
-        // dword before and the one after give the shifted fragments
-        const __bf16* row = bx + (ci0 + 16 * n + r) * KX + 8 + k0 + 8 * g;
-        const u32x4v d = *reinterpret_cast<const u32x4v*>(row);
-        const unsigned prev = *reinterpret_cast<const unsigned*>(row - 2);
-        const unsigned next = *reinterpret_cast<const unsigned*>(row + 8);
+        const int ci = ci0 + 16 * n + r, xr = 2 * C + ci;  // input row of k-half 0
+        // pixels p = 32 kh + 8 g .. + 7 of channel ci; the dword holding
+        // pixel p - 1 (high half) and the one holding p + 8 (low half)
+        const u32x4v d = *reinterpret_cast<const u32x4v*>(base + swz(xr + kh * C, g));
+        const unsigned* pp = (kh == 0 && g == 0)
+                                 ? hx + ci
+                                 : reinterpret_cast<const unsigned*>(
+                                       base + swz(xr + (g == 0 ? kh - 1 : kh) * C, (g + 3) & 3) + 12);
+        const unsigned* pn = (kh == 1 && g == 3)
+                                 ? hx + C + ci
+                                 : reinterpret_cast<const unsigned*>(base + swz(xr + (g == 3 ? kh + 1 : kh) * C,
+                                                                                (g + 1) & 3));
+        const unsigned prev = *pp, next = *pn;
         const unsigned t0 = __builtin_amdgcn_alignbit(d.x, prev, 16), t1 = __builtin_amdgcn_alignbit(d.y, d.x, 16);
         const unsigned t2 = __builtin_amdgcn_alignbit(d.z, d.y, 16), t3 = __builtin_amdgcn_alignbit(d.w, d.z, 16);
         const unsigned t4 = __builtin_amdgcn_alignbit(next, d.w, 16);
