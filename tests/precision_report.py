@@ -2,13 +2,15 @@
 over time, on the 512 x 512 crop of the 4-layer workload (the [0:512, 0:512]
 window of its seeded 4096^2 fields, run as its own periodic domain).
 
-For each format (FP32; FP32 rest with IEEE-half or bfloat16 moving
+For each format (FP64 and FP32; FP32 rest with IEEE-half or bfloat16 moving
 populations; all-IEEE-half or all-bfloat16 deviations) and each time t it
 prints, per layer, the relative L2 error of the heights
 ||h - h_ref|| / ||h_ref||, the same error relative to the perturbation
 ||h - h_ref|| / ||h_ref - mean(h_ref)||, and the relative mass change since
-t = 0.  Beyond the oracle's horizon (--oracle-steps) the 16-bit formats are
-compared with the FP32 GPU run instead, which is marked in the output.
+t = 0.  Up to --oracle-steps the oracle runs alongside; at 10^4, 2 10^4
+and 5 10^4 steps the reference is the oracle's stored state
+(tests/golden/film4_512_long.npz, every 8th row, written by
+tests/golden/make_film4_512_long.py).
 
     python tests/precision_report.py [--oracle-steps 3000] [--long-steps 50000]
 """
@@ -24,6 +26,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 from paper_2409_16659_amd import inputs  # noqa: E402
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "film4_512_long.npz")
 
 
 def errors(h, ref):
@@ -46,9 +50,11 @@ def main():
 
     mlfilm.load_library()
     film, h0, _ = inputs.workload("film4_2d_512")
-    checkpoints = [t for t in (100, 300, 1000, 3000, 10_000, 20_000, 50_000)
-                   if t <= max(args.oracle_steps, args.long_steps)]
-    precs = ["f32", "f16mix", "bf16mix", "f16", "bf16"]
+    gold = np.load(GOLDEN)
+    stored = {int(t): k for k, t in enumerate(gold["t"])}
+    checkpoints = [t for t in (100, 300, 1000, 3000) if t <= args.oracle_steps]
+    checkpoints += [t for t in sorted(stored) if t <= args.long_steps]
+    precs = ["f64", "f32", "f16mix", "bf16mix", "f16", "bf16"]
     films = {p: mlfilm.Film(film, p, check_every=-1) for p in precs}
     for f in films.values():
         f.init(h0)
@@ -56,33 +62,32 @@ def main():
     o = oracle.Oracle(film)
     o.init(h0)
     mo0 = o.mass()
+    rows_kept = gold["rows"]
     t = 0
     rows = []
     for tc in checkpoints:
         for f in films.values():
             f.step(tc - t)
-        ref_name = "oracle" if tc <= args.oracle_steps else "gpu_f32"
-        if ref_name == "oracle":
+        if tc in stored:
+            ref_name, sel = "oracle (stored)", rows_kept
+            ref = gold["h"][stored[tc]]
+            mo = gold["mass"][stored[tc]]
+        else:
             t0 = time.perf_counter()
-            o.step(tc - t)
+            o.step(tc - o.steps_done)
             print(f"[report] oracle reached t={tc} ({time.perf_counter() - t0:.1f} s)", flush=True)
+            ref_name, sel = "oracle", slice(None)
             ref, _, _ = o.read()
             mo = o.mass()
-        else:
-            ref, _, _ = films["f32"].read()
-            mo = None
         t = tc
         for p in precs:
-            if ref_name == "gpu_f32" and p == "f32":
-                continue
             h, _, _ = films[p].read()
             m = films[p].mass()
-            e = errors(h, ref)
+            e = errors(h[:, sel], ref)
             row = {"t": tc, "storage": p, "against": ref_name,
                    "l2": [a for a, _ in e], "l2_pert": [b for _, b in e],
-                   "mass_drift": [float(abs(m[i] - m0[p][i]) / m0[p][i]) for i in range(len(m))]}
-            if mo is not None:
-                row["oracle_mass_drift"] = [float(abs(mo[i] - mo0[i]) / mo0[i]) for i in range(len(mo))]
+                   "mass_drift": [float(abs(m[i] - m0[p][i]) / m0[p][i]) for i in range(len(m))],
+                   "oracle_mass_drift": [float(abs(mo[i] - mo0[i]) / mo0[i]) for i in range(len(mo))]}
             rows.append(row)
             print(json.dumps(row), flush=True)
     print()
