@@ -204,11 +204,13 @@ mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
  * bit-identical to the step kernel; once a graph is captured
  * (mlf_capture) mlf_step replays it with the step kernel instead.
  *
- * Launch shape of the step kernel: block_w threads (64, 128, 192 or 256),
- * one per column of a strip of block_w - 4 columns plus two halo columns on
- * each side, and seg_h rows per workgroup (>= 1).  Results do not depend on
- * the shape.  0 = default.  D1Q3 films keep their fixed kernel shapes (the
- * values are stored and ignored; mlf_autotune returns them unchanged). */
+ * Launch shape of the step kernel: block_w threads (64, 128, 192, 256 or 512;
+ * 512 is MLF_EINVAL for FP64 films of four layers, whose kernel is compiled
+ * for at most 256), one per column of a strip of block_w - 4 columns plus two
+ * halo columns on each side, and seg_h rows per workgroup (>= 1).  Results
+ * do not depend on the shape.  0 = default.  D1Q3 films keep their fixed
+ * kernel shapes (the values are stored and ignored; mlf_autotune returns
+ * them unchanged). */
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h);
 mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h);
 
@@ -217,9 +219,10 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
  * launched `reps` times (>= 1) from the current population buffer into the
  * other one without swapping, so the state and step counter are unchanged;
  * the four fastest are then re-timed twice with 4 x reps launches each and
- * the smallest time wins.  Candidates: block_w in {64, 128, 192, 256} and
- * segment heights from a fixed list plus those that fill whole dispatch
- * rounds of the device.  Synchronises. */
+ * the smallest time wins.  Candidates: block_w in {64, 128, 192, 256, 512}
+ * (not 512 for FP64 films of four layers) and segment heights from a fixed
+ * list plus those that fill whole dispatch rounds of the device.
+ * Synchronises. */
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h);
 
 /* Capture `steps` (even, > 0) consecutive step launches into a HIP graph

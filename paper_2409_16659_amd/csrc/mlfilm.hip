@@ -1161,14 +1161,20 @@ int64_t mlf_steps_done(const mlf_handle* h) { return h ? h->steps : -1; }
 
 const char* mlf_last_error(const mlf_handle* h) { return h ? h->err.c_str() : "null handle"; }
 
+// Widest strip the step kernel is compiled for with these parameters (the
+// kernel's step_max_lanes: FP64 with four layers stops at 256 lanes).
+int max_block_w(const mlf_params& p) { return (p.precision == MLF_F64 && p.n_layers == 4) ? 256 : 512; }
+
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h) {
   if (!h) return MLF_EINVAL;
   drop_single_graph(h);
   int bw, sh;
   default_launch(&h->p, &bw, &sh);
   if (block_w != 0) {
-    if (block_w != 64 && block_w != 128 && block_w != 192 && block_w != 256)
-      return fail(h, MLF_EINVAL, "block_w must be 64, 128, 192 or 256");
+    if (block_w != 64 && block_w != 128 && block_w != 192 && block_w != 256 && block_w != 512)
+      return fail(h, MLF_EINVAL, "block_w must be 64, 128, 192, 256 or 512");
+    if (block_w > max_block_w(h->p))
+      return fail(h, MLF_EINVAL, "block_w 512 is not available for FP64 films of four layers");
     bw = block_w;
   }
   if (seg_h != 0) {
@@ -1203,7 +1209,8 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
   const int keep_w = h->block_w, keep_h = h->seg_h;
   std::vector<std::pair<int, int>> cand;
   const int fixed[] = {2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64, 96, 128};
-  for (int w : {64, 128, 192, 256}) {
+  for (int w : {64, 128, 192, 256, 512}) {
+    if (w > max_block_w(p)) continue;
     h->block_w = w;
     const int nstrip = mlf::strip_count(p.nx, w);
     for (int sh : fixed)

@@ -805,8 +805,17 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
   if (it < niter) body(std::true_type{}, it, fa, fb);
 }
 
+// Largest workgroup the step kernel is compiled for: 512 lanes (two waves
+// per SIMD, at most 256 VGPRs each), except FP64 arithmetic on four layers,
+// whose working set needs more registers than that and keeps one wave per
+// SIMD (256 lanes).
+template <typename C, int NL>
+constexpr int step_max_lanes() {
+  return (sizeof(C) == 8 && NL == 4) ? 256 : 512;
+}
+
 template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__((step_max_lanes<C, NL>()))
 step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
   const int tile = tile_of_block(blockIdx.x, gridDim.x);
   if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)

@@ -266,7 +266,7 @@ def test_launch_shape_independence(mlf):
         film = small_film(3, 300, 45, seed=16)
         h0 = noisy(3, 300, 45, seed=17)
         ref = None
-        for launch in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 45), (128, 3)]:
+        for launch in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 45), (512, 4), (512, 45), (128, 3)]:
             say(f"shape {prec} {launch}")
             g = mlf.Film(film, prec)
             g.set_launch(*launch)
@@ -277,6 +277,40 @@ def test_launch_shape_independence(mlf):
                 ref = f
             else:
                 assert np.array_equal(f, ref), launch
+
+
+def test_wide_strip_launch_shapes(mlf):
+    """512-lane strips on a film wider than one of them (1100 columns: three
+    strips of at most 508 columns) give the same populations as 64- and
+    192-lane strips."""
+    film = small_film(2, 1100, 24, seed=40)
+    h0 = noisy(2, 1100, 24, seed=41)
+    for prec in ("f64", "f32"):
+        ref = None
+        for launch in [(64, 3), (192, 24), (512, 5), (512, 24)]:
+            say(f"wide shape {prec} {launch}")
+            g = mlf.Film(film, prec)
+            g.set_launch(*launch)
+            g.init(h0)
+            g.step(30)
+            f = g.populations()
+            if ref is None:
+                ref = f
+            else:
+                assert np.array_equal(f, ref), launch
+
+
+def test_fp64_four_layers_stop_at_256_lanes(mlf):
+    """The FP64 four-layer step kernel is compiled for at most 256 lanes:
+    512 is refused with an error and the autotuner does not pick it."""
+    film = small_film(4, 1100, 24, seed=42)
+    g = mlf.Film(film, "f64")
+    with pytest.raises(mlf.MlfError, match="512"):
+        g.set_launch(512, 8)
+    g.init(noisy(4, 1100, 24, seed=43))
+    bw, sh = g.autotune(reps=1)
+    assert bw in (64, 128, 192, 256) and sh >= 1
+    g.step(2)
 
 
 def test_flat_film_fixed_point(mlf):
@@ -431,7 +465,7 @@ def test_autotune_keeps_state(mlf):
         f0 = a.populations()
         bw, sh = a.autotune(reps=2)
         say(f"   autotune {prec}: {bw}x{sh}")
-        assert bw in (64, 128, 192, 256) and 1 <= sh <= 90
+        assert bw in (64, 128, 192, 256, 512) and 1 <= sh <= 90
         assert a.get_launch() == (bw, sh)
         assert a.steps_done == 5
         assert np.array_equal(a.populations(), f0)
