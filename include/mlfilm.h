@@ -198,11 +198,13 @@ mlf_status mlf_write_populations(mlf_handle* h, const double* f);
 mlf_status mlf_save(mlf_handle* h, void* blob, size_t* bytes);
 mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
 
-/* D2Q9 films one row high (ny == 1) with F64 or F32 storage whose state
- * fits one workgroup's LDS (11 N nx values within 160 KiB, nx <= 1024)
- * run many steps per launch with the film held on chip, with results
- * bit-identical to the step kernel; once a graph is captured
- * (mlf_capture) mlf_step replays it with the step kernel instead.
+/* D2Q9 films one row high (ny == 1) with F64 or F32 storage run many steps
+ * per launch with the film held on chip, with results bit-identical to the
+ * step kernel: up to 128 columns in one workgroup; wider rows in tiles of
+ * 32 columns, one workgroup each, that also hold 48 columns on either side
+ * (what 16 steps can carry across a tile edge) and run 16 steps per launch.
+ * Once a graph is captured (mlf_capture) mlf_step replays it with the step
+ * kernel instead.
  *
  * Launch shape of the step kernel: block_w threads (64, 128, 192, 256 or 512;
  * 512 is MLF_EINVAL for FP64 films of four layers, whose kernel is compiled

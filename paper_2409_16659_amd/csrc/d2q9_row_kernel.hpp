@@ -7,9 +7,9 @@
 // node's own row; the arithmetic per node is that of the strip kernel
 // (same moment sums, the same pressure expressions, the shared
 // node_collide), so results are bit-identical to stepping the film with
-// step_kernel.  One workgroup of up to 512 lanes, each owning at most two
-// nodes; LDS holds the nine population planes, the interface deviations
-// and the pressures (11 N nx values).  Three barriers per step: every read
+// step_kernel.  One workgroup of up to 128 lanes, one node each (wider rows
+// take d2q9_row_tiled below); LDS holds the nine population planes, the
+// interface deviations and the pressures (11 N nx values).  Three barriers per step: every read
 // of a step's populations happens before the first one, every write after
 // the second, so one LDS copy of the populations suffices.  A one-row film
 // of a few hundred nodes does about a microsecond of work per step, less
@@ -20,8 +20,8 @@
 
 namespace mlf {
 
-constexpr int kRowThreads = 512;
-constexpr int kRowMaxPerThread = 2;        // nodes per lane: nx <= 1024
+constexpr int kRowThreads = 128;
+constexpr int kRowMaxPerThread = 1;        // nodes per lane: nx <= 128
 constexpr size_t kRowMaxLds = 160 * 1024;  // LDS of one workgroup on gfx950
 
 // Bytes of LDS the resident one-row kernel needs for nx nodes of nl layers.
@@ -83,7 +83,8 @@ __device__ inline void row_pressure(const StepConsts<C>& kc, Z&& z, C (&p)[NL]) 
 // FP32 storage (the arithmetic type; the rest plane holds deviations from
 // hbar).  Global layout as for the strip kernel: plane k (0..8) of `plane`
 // nodes, each node holding the N layers' values; plane k keeps at column x
-// the population of node x + c_kx.  Lane t owns nodes t and t + blockDim.
+// the population of node x + c_kx.  Lane t owns node t (and t + j blockDim
+// for j < kRowMaxPerThread).
 template <typename C, int NL, bool TAU1, int EA, int EB>
 __global__ void __launch_bounds__(kRowThreads)
 d2q9_row_resident(const C* __restrict__ src, C* __restrict__ dst, const StepConsts<C> kc, int steps) {
@@ -171,6 +172,122 @@ d2q9_row_resident(const C* __restrict__ src, C* __restrict__ dst, const StepCons
   for (int e = t; e < nx * NL; e += nt)
 #pragma unroll
     for (int k = 0; k < kQ; ++k) dst[k * plane * NL + e] = sf[k * nx * NL + e];
+  if (bad) kc.flag[0] = bad;
+}
+
+// ---- the same step on a row split over several workgroups ----------------
+//
+// A node's populations after a step depend on the populations of the nodes
+// up to kRowReach columns away before it (moments read the neighbours'
+// streamed values, the pressure reads the neighbours' interface deviations,
+// the force the neighbours' pressures).  A workgroup that holds its `core`
+// columns plus kRowReach * s columns on each side can therefore run s steps
+// alone: errors from the cut edges of its tile move inwards by at most
+// kRowReach columns a step and never reach the core.  Each workgroup runs
+// on its own CU with one column per lane, so a step costs one wave's
+// instruction stream instead of the whole row's share of one CU; the halo
+// columns are computed redundantly.  Per-node arithmetic is that of
+// d2q9_row_resident (and of the strip kernel): results are bit-identical.
+constexpr int kRowReach = 3;
+constexpr int kRowTileThreads = 128;  // lanes = tile columns
+constexpr int kRowTileSteps = 16;     // steps per launch
+constexpr int kRowTileCore = kRowTileThreads - 2 * kRowReach * kRowTileSteps;
+static_assert(kRowTileCore > 0, "tile too narrow for its halo");
+
+template <typename C>
+__host__ __device__ constexpr size_t row_tile_lds(int nl) {
+  return (size_t)11 * nl * kRowTileThreads * sizeof(C);
+}
+
+// `steps` (1..kRowTileSteps) steps of a one-row film whose columns are
+// split into tiles of `core` columns (the last one may hold fewer), one
+// workgroup of kRowTileThreads lanes each; src -> dst in the global layout
+// of d2q9_row_resident.  The guard checks each node in the tile that owns
+// it.
+template <typename C, int NL, bool TAU1, int EA, int EB>
+__global__ void __launch_bounds__(kRowTileThreads)
+d2q9_row_tiled(const C* __restrict__ src, C* __restrict__ dst, const StepConsts<C> kc, int steps, int core) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int kCxRow[kQ] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+  const int nx = kc.nx;
+  const int halo = kRowReach * steps;
+  const int w = core + 2 * halo;  // tile columns, <= kRowTileThreads (host-checked)
+  const int x0 = blockIdx.x * core;
+  const int ncore = min(core, nx - x0);
+  C* sf = reinterpret_cast<C*>(smem_raw);  // [9][w][NL]
+  C* sz = sf + kQ * w * NL;                // [w][NL]
+  C* sp = sz + w * NL;                     // [w][NL]
+  const long long plane = kc.plane;
+  const int l = threadIdx.x;  // the lane's tile column
+  const bool live = l < w;
+  const bool owned = l >= halo && l < halo + ncore;
+  for (int e = l; e < w * NL; e += kRowTileThreads) {
+    const int c = e / NL, i = e - c * NL;
+    int g = (x0 - halo + c) % nx;  // periodic; x0 - halo + c >= -halo
+    if (g < 0) g += nx;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) sf[(k * w + c) * NL + i] = src[k * plane * NL + (long long)g * NL + i];
+  }
+  __syncthreads();
+  const int cm = max(l - 1, 0), cp = min(l + 1, w - 1);  // clamped at the cut edges
+  int bad = 0;
+  C f[NL][kQ];
+  C dh[NL], qx[NL], qy[NL];
+  for (int s = 0; s < steps; ++s) {
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        const int col = min(max(l - kCxRow[k], 0), w - 1);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) f[i][k] = sf[(k * w + col) * NL + i];
+      }
+      C dz = C(0);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const C* ff = f[i];
+        dh[i] = ff[0] + ff[1] + ff[2] + ff[3] + ff[4] + ff[5] + ff[6] + ff[7] + ff[8];
+        qx[i] = (ff[1] + ff[2] + ff[8]) - (ff[4] + ff[5] + ff[6]);
+        qy[i] = (ff[2] + ff[3] + ff[4]) - (ff[6] + ff[7] + ff[8]);
+        dz += dh[i];
+        sz[l * NL + i] = dz;
+        if (owned) {
+          const C h = kc.hbar[i] + dh[i];
+          const C chk = h + qx[i] + qy[i];
+          if (!(h > C(0))) bad = bad > 1 ? bad : 1;
+          if (!(chk - chk == C(0))) bad = 2;
+        }
+      }
+    }
+    __syncthreads();
+    if (live) {
+      auto z = [&](int i, int, int c) { return sz[(c == 0 ? cm : (c == 1 ? l : cp)) * NL + i]; };
+      C p[NL];
+      row_pressure<C, NL, EA, EB>(kc, z, p);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) sp[l * NL + i] = p[i];
+    }
+    __syncthreads();
+    if (live) {
+      auto pz = [&](int i, int, int c) { return sp[(c == 0 ? cm : (c == 1 ? l : cp)) * NL + i]; };
+      C fo[NL][kQ];
+      node_collide<C, NL, TAU1>(kc, dh, qx, qy, pz, fo);
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+          C v = fo[i][k];
+          if constexpr (!TAU1) v += (C(1) - kc.omega) * f[i][k];
+          sf[(k * w + l) * NL + i] = v;
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = l; e < ncore * NL; e += kRowTileThreads) {
+    const int c = e / NL, i = e - c * NL;
+    const long long g = x0 + c;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) dst[k * plane * NL + g * NL + i] = sf[(k * w + halo + c) * NL + i];
+  }
   if (bad) kc.flag[0] = bad;
 }
 

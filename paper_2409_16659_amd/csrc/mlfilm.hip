@@ -838,9 +838,20 @@ hipError_t d1_advance(mlf_handle* h, int steps) {
 
 // ---- D2Q9 films one row high: resident multi-step kernel ------------------
 
+// One-row films wider than one tile run tiled over several workgroups
+// (kRowTileSteps steps per launch); narrower ones fit one workgroup of at
+// most two waves, which holds them for up to kD1MaxStepsPerLaunch steps per
+// launch.
+bool row_tiled(const mlf_params& p) {
+  if (p.lattice != MLF_D2Q9 || p.ny != 1) return false;
+  if (p.precision != MLF_F64 && p.precision != MLF_F32) return false;
+  return p.nx > mlf::kRowTileThreads;
+}
+
 bool row_resident(const mlf_params& p) {
   if (p.lattice != MLF_D2Q9 || p.ny != 1) return false;
   if (p.precision != MLF_F64 && p.precision != MLF_F32) return false;
+  if (row_tiled(p)) return true;
   const size_t c = p.precision == MLF_F64 ? 8 : 4;
   return p.nx <= mlf::kRowMaxPerThread * mlf::kRowThreads &&
          (size_t)11 * p.n_layers * p.nx * c <= mlf::kRowMaxLds;
@@ -850,6 +861,22 @@ template <typename C, int NL, bool T1, int EA, int EB>
 hipError_t row_launch_nl(mlf_handle* h, int steps) {
   mlf::StepConsts<C> kc = make_consts<C>(h);
   const mlf_params& p = h->p;
+  if (row_tiled(p)) {
+    if (steps < 1 || steps > mlf::kRowTileSteps) return hipErrorInvalidValue;
+    const size_t lds = mlf::row_tile_lds<C>(NL);
+    auto kern = mlf::d2q9_row_tiled<C, NL, T1, EA, EB>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    const int tiles = (p.nx + mlf::kRowTileCore - 1) / mlf::kRowTileCore;
+    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(mlf::kRowTileThreads), lds, h->stream,
+                       static_cast<const C*>(h->pop[h->cur]), static_cast<C*>(h->pop[h->cur ^ 1]), kc, steps,
+                       mlf::kRowTileCore);
+    h->cur ^= 1;
+    return hipGetLastError();
+  }
   const size_t lds = mlf::row_resident_lds<C>(p.nx, NL);
   auto kern = mlf::d2q9_row_resident<C, NL, T1, EA, EB>;
   if (lds > 65536) {
@@ -874,7 +901,8 @@ hipError_t row_launch_t(mlf_handle* h, int steps) {
   }
 }
 
-// Advances a one-row D2Q9 film by `steps` (1..kD1MaxStepsPerLaunch); flips h->cur.
+// Advances a one-row D2Q9 film by `steps` (1..kD1MaxStepsPerLaunch; 1..kRowTileSteps when
+// tiled); flips h->cur.
 template <typename C>
 hipError_t row_advance_c(mlf_handle* h, int steps) {
   const bool t1 = h->p.tau == 1.0;
@@ -1369,7 +1397,7 @@ mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
   if (h->p.lattice == MLF_D1Q3 || row) {
     int64_t left = nsteps, since = 0;
     while (left > 0) {
-      int64_t chunk = std::min<int64_t>(left, kD1MaxStepsPerLaunch);
+      int64_t chunk = std::min<int64_t>(left, row && row_tiled(h->p) ? mlf::kRowTileSteps : kD1MaxStepsPerLaunch);
       if (every > 0) chunk = std::min<int64_t>(chunk, every - since);
       HIPCHK(row ? row_advance(h, (int)chunk) : d1_advance(h, (int)chunk));
       left -= chunk;

@@ -1,8 +1,9 @@
-"""D2Q9 films one row high: the LDS-resident kernel (many steps per launch)
-against the strip kernel, which mlf_step runs while a graph is captured.
-Both take the same arithmetic per node, so the populations must agree bit
-for bit; the oracle pins the path through the two-layer workload in
-test_gpu_parity.py (10^4 steps, 1e-12)."""
+"""D2Q9 films one row high: the LDS-resident kernels (one workgroup for rows
+of up to 128 columns; tiles of 32 columns with 48-column halos, 16 steps per
+launch, for wider rows) against the strip kernel, which mlf_step runs while
+a graph is captured.  All take the same arithmetic per node, so the
+populations must agree bit for bit; the oracle pins the path through the
+two-layer workload in test_gpu_parity.py (10^4 steps, 1e-12)."""
 import numpy as np
 import pytest
 
@@ -46,7 +47,9 @@ def _film(n, nx, seed, tau=1.0, exps=(9, 3), slip=None):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,nx,kw", [(1, 1, {}), (2, 2, {}), (2, 512, {}), (3, 37, {"tau": 0.8}),
                                      (4, 700, {}), (2, 1024, {"exps": (4, 2)}),
-                                     (3, 200, {"slip": [0.1, 0.0, 0.2]}), (4, 130, {"tau": 1.3})])
+                                     (3, 200, {"slip": [0.1, 0.0, 0.2]}), (4, 130, {"tau": 1.3}),
+                                     (2, 128, {}), (2, 129, {}), (1, 3000, {}), (4, 330, {"tau": 0.8}),
+                                     (3, 1500, {"slip": [0.1, 0.0, 0.2]})])
 def test_resident_row_equals_strip_kernel(mlf, torch_cuda, prec, n, nx, kw):
     film, h0 = _film(n, nx, 300 + n + nx, **kw)
     steps = 600
@@ -74,3 +77,41 @@ def test_resident_row_guard(mlf, torch_cuda):
     with pytest.raises(mlf.MlfError) as e:
         g.step(100)
     assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
+
+
+@pytest.mark.parametrize("steps", [1, 15, 16, 17, 95])
+def test_tiled_row_chunks(mlf, torch_cuda, steps):
+    """Step counts around the tiled kernel's 16 steps per launch (and a
+    guard interval that splits its launches) give the strip kernel's
+    populations."""
+    film, h0 = _film(2, 600, 77)
+    print(f"case tiled row steps={steps}", flush=True)
+    a = mlf.Film(film, "f64", check_every=7)
+    b = mlf.Film(film, "f64", stream=torch_cuda.cuda.Stream())
+    for g in (a, b):
+        g.init(h0)
+    b.capture(2)
+    a.step(steps)
+    b.step(steps)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("col", [0, 31, 32, 511])
+def test_tiled_row_guard(mlf, torch_cuda, col):
+    """A non-positive height at any column, including the first and last
+    column of a tile and the row's wrap-around edge, trips the guard of the
+    tiled kernel; a healthy film of the same size does not."""
+    film, h0 = _film(2, 512, 9)
+    print(f"case tiled row guard col={col}", flush=True)
+    g = mlf.Film(film, "f64", check_every=40)
+    g.init(h0)
+    g.step(40)
+    f = g.populations()
+    f[0, 0, 0, col] = -5.0
+    g.set_populations(f)
+    with pytest.raises(mlf.MlfError) as e:
+        g.step(40)
+    assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
+    ok = mlf.Film(film, "f64", check_every=40)
+    ok.init(h0)
+    ok.step(200)
