@@ -254,11 +254,16 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
 }
 
 // ---- 3x3 periodic convolution, weight gradient ----------------------------
-// part[b][o][co][ci] = sum_{y, x} dy[b, y, x, co] in[b, y+dy_o, x+dx_o, ci]
-// One workgroup per (image b, row offset dy) computes the three offsets
-// (dy, -1), (dy, 0), (dy, +1) for all C x C channel pairs: waves WM x WN
-// split the (co, ci) block, each holding 3 x (C/WM) x (C/WN) accumulators.
-// The image is marched in chunks of 64 pixels of one row.  Per chunk the
+// part[s][o][co][ci] = sum over the pixels (b, y, x) of slice s of
+//                      dy[b, y, x, co] in[b, y+dy_o, x+dx_o, ci]
+// The batch's pixels, in chunks of 64 of one row in (image, row, column)
+// order, are cut into nslice slices of consecutive chunks (a slice may span
+// images; the row offset wraps within each image).  One workgroup per
+// (slice, row offset dy) computes the three offsets (dy, -1), (dy, 0),
+// (dy, +1) for all C x C channel pairs: waves WM x WN split the (co, ci)
+// block, each holding 3 x (C/WM) x (C/WN) accumulators; with 3 nslice no
+// larger than the CU count every CU holds one workgroup, whatever the
+// batch.  The slice is marched chunk by chunk.  Per chunk the
 // workgroup stages dY and the input row y + dy transposed in LDS, the input
 // once: [k-half][channel] rows of 64 bytes (32 pixels, one MFMA k-step)
 // whose four 16-byte chunks are permuted by XOR with (row / 2) % 4, the
@@ -272,9 +277,10 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
 // 8-byte LDS writes); consecutive lanes take consecutive pixel groups.
 // Two LDS buffers: the next chunk's loads are issued before the current
 // chunk's products and written after them, one barrier per chunk.  Pixels
-// are accumulated in order (32 per MFMA step), so every launch gives the
-// same bits.  On the device's eight XCDs (each with its own L2) the three
-// workgroups of one image are given to one XCD when the grid divides by 8.
+// are accumulated in order (32 per MFMA step), so every launch with the
+// same nslice gives the same bits.  On the device's eight XCDs (each with
+// its own L2) the three workgroups of one slice are given to one XCD when
+// the grid divides by 8.
 // Dynamic LDS conv3x3_wgrad_lds(C) bytes.  Requires gx % 64 == 0,
 // C % (16 WM) == 0, C % (16 WN) == 0.
 constexpr int kWgChunk = 64;  // pixels per chunk (two k-halves of 32)
@@ -285,7 +291,8 @@ __host__ __device__ constexpr size_t conv3x3_wgrad_lds(int C) {
 template <int C, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __restrict__ in,
                                                                const __bf16* __restrict__ dout,
-                                                               float* __restrict__ part, int gy, int gx) {
+                                                               float* __restrict__ part, int batch, int gy, int gx,
+                                                               int nslice) {
   constexpr int NTH = 64 * WM * WN, CH = kWgChunk;
   constexpr int MT = C / WM / 16, NT = C / WN / 16;  // 16 x 16 tiles per wave (co, ci)
   constexpr int PC = (CH / 4) * (C / 8);             // pieces of one tensor per chunk
@@ -298,11 +305,13 @@ __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __re
   // buffer layout: dY rows [2][C], input rows [2][C] (64 bytes each), then
   // halo dwords [2][C]: (0, in[-1]) and (in[64], 0) as bf16 pairs
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
-  // (image, row offset) of this workgroup; the three row offsets of an
-  // image share an XCD when the grid allows it
+  // (slice, row offset) of this workgroup; the three row offsets of a
+  // slice share an XCD when the grid divides by 8 (padding workgroups
+  // beyond 3 nslice exit)
   const int nwg = gridDim.x;
   const int item = nwg % 8 == 0 ? (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int b = item / 3, dyi = item % 3;
+  if (item >= 3 * nslice) return;
+  const int sl = item / 3, dyi = item % 3;
   const int r = lane & 15, g = lane >> 4;
   const int co0 = (wave / WN) * (C / WM), ci0 = (wave % WN) * (C / WN);
   f32x4 acc[3][MT][NT];
@@ -312,16 +321,21 @@ __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __re
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int n = 0; n < NT; ++n) acc[s][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16* dimg = dout + (long long)b * gy * gx * C;
-  const __bf16* ximg = in + (long long)b * gy * gx * C;
-  const int cpr = gx / CH, nch = gy * cpr;
+  // chunks of CH pixels in (image, row, column) order; slice sl takes
+  // [c0, c1) of the batch's chunks
+  const int cpr = gx / CH, cpi = gy * cpr;
+  const long long total = (long long)batch * cpi;
+  const int c0 = (int)(total * sl / nslice), c1 = (int)(total * (sl + 1) / nslice);
   typedef u32x4v Stage[NSP][4];
   Stage sa;
   // piece j: [0, PC) dY, [PC, 2 PC) input (pixel group j % 16, channels
   // 8 (j / 16) ..), then the halo pixels
   auto fetch = [&](int ch, Stage& st) {
-    const int y = ch / cpr, x0 = (ch % cpr) * CH;
+    const int b = ch / cpi, cc = ch - b * cpi;
+    const int y = cc / cpr, x0 = (cc % cpr) * CH;
     const int ys = pwrap(y + dyi - 1, gy);
+    const __bf16* dimg = dout + (long long)b * gy * gx * C;
+    const __bf16* ximg = in + (long long)b * gy * gx * C;
 #pragma unroll
     for (int jj = 0; jj < NSP; ++jj) {
       const int j = t + jj * NTH;
@@ -414,18 +428,18 @@ __global__ void __launch_bounds__(64 * WM * WN) conv3x3_wgrad(const __bf16* __re
   };
   // chunk ch lives in LDS buffer ch % 2; the next chunk's loads are in
   // flight during its products
-  fetch(0, sa);
+  fetch(c0, sa);
   put(0, sa);
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    if (ch + 1 < nch) fetch(ch + 1, sa);
-    compute(ch & 1);
-    if (ch + 1 < nch) put((ch + 1) & 1, sa);
+  for (int ch = c0; ch < c1; ++ch) {
+    if (ch + 1 < c1) fetch(ch + 1, sa);
+    compute((ch - c0) & 1);
+    if (ch + 1 < c1) put((ch + 1 - c0) & 1, sa);
     __syncthreads();
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    float* pb = part + ((long long)b * 9 + dyi * 3 + s) * C * C;
+    float* pb = part + ((long long)sl * 9 + dyi * 3 + s) * C * C;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll

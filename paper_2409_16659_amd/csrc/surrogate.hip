@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kPatch = 4;
 constexpr int kRedBlocks = 512;  // partial sums of the pixel reductions
+constexpr int kWgSlices = 85;    // slices of the weight gradient (3 x 85 workgroups: one per CU of 256)
 
 // ---- elementwise and reduction kernels (FP32) ------------------------------
 
@@ -590,7 +591,7 @@ Layout layout_of(const mlf_nop_params* p) {
   const long long gy = p->ny / kPatch, gx = p->nx / kPatch;
   s.lat = (long long)p->batch * gy * gx * C;
   s.img = (long long)p->batch * N * p->ny * p->nx;
-  s.part_floats = std::max<long long>({(long long)p->batch * 9 * C * C, (long long)kRedBlocks * J * C,
+  s.part_floats = std::max<long long>({(long long)kWgSlices * 9 * C * C, (long long)kRedBlocks * J * C,
                                        (long long)kRedBlocks * C, (long long)kRedBlocks});
   // regions: floats then bf16, 256-byte aligned
   const long long npa = a64(s.npar);
@@ -648,18 +649,27 @@ mlf_status conv_fwd(mlf_nop* m, int batch, const __bf16* in, const __bf16* w, co
   return conv_fwd_e<nop::kEpiPlain>(m, batch, in, w, bias, out, nullptr, nullptr);
 }
 
-// per-image weight gradients into m->part ([batch][9][C][C]); a workgroup
-// per (image, row offset) with all channel pairs: 16 waves at C = 128
-// (32 x 32 channel tiles: 4 waves per SIMD hide more of the staging and
-// LDS latency than 8 waves with 64 x 32 tiles, 122 vs 127 us at batch 64),
-// 4 at C = 64 (32 x 32)
+// weight gradients of nslice slices of the batch's pixels into m->part
+// ([nslice][9][C][C]); a workgroup per (slice, row offset) with all channel
+// pairs: 16 waves at C = 128 (32 x 32 channel tiles: 4 waves per SIMD hide
+// more of the staging and LDS latency than 8 waves with 64 x 32 tiles),
+// 4 at C = 64 (32 x 32).  kWgSlices slices (3 kWgSlices workgroups, one per
+// CU of a 256-CU device), fewer when the batch has fewer chunks; the grid
+// is padded to a multiple of 8 for the kernel's XCD grouping.
 template <int C>
 constexpr int kWgW = C == 128 ? 4 : 2;  // waves along each of co and ci
 
+int wgrad_slices(const mlf_nop* m, int batch) {
+  const long long chunks = (long long)batch * m->gy * (m->gx / nop::kWgChunk);
+  return (int)std::max<long long>(1, std::min<long long>(chunks, kWgSlices));
+}
+
 template <int C>
 mlf_status wgrad_launch(mlf_nop* m, int batch, const __bf16* in, const __bf16* dout) {
-  NLAUNCH((nop::conv3x3_wgrad<C, kWgW<C>, kWgW<C>>), dim3((unsigned)batch * 3), dim3(64 * kWgW<C> * kWgW<C>),
-          nop::conv3x3_wgrad_lds(C), m->stream, in, dout, m->part, m->gy, m->gx);
+  const int ns = wgrad_slices(m, batch);
+  const unsigned grid = (unsigned)((3 * ns + 7) / 8 * 8);
+  NLAUNCH((nop::conv3x3_wgrad<C, kWgW<C>, kWgW<C>>), dim3(grid), dim3(64 * kWgW<C> * kWgW<C>),
+          nop::conv3x3_wgrad_lds(C), m->stream, in, dout, m->part, batch, m->gy, m->gx, ns);
   return MLF_OK;
 }
 
@@ -695,7 +705,7 @@ mlf_status conv_wgrad(mlf_nop* m, int batch, const __bf16* in, const __bf16* dou
   const mlf_status st = m->C == 64 ? wgrad_launch<64>(m, batch, in, dout) : wgrad_launch<128>(m, batch, in, dout);
   if (st != MLF_OK) return st;
   const long long K = 9LL * m->C * m->C;
-  NLAUNCH(sum_rows, dim3(grid1(K)), dim3(256), 0, m->stream, m->part, dw, batch, K, 0);
+  NLAUNCH(sum_rows, dim3(grid1(K)), dim3(256), 0, m->stream, m->part, dw, wgrad_slices(m, batch), K, 0);
   return MLF_OK;
 }
 
