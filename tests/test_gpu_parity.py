@@ -210,6 +210,18 @@ def test_fp32_three_layer_full_size(mlf, oracle_mod):
     check(g, o, 1e-5, 1e-4)
 
 
+def test_fp32_three_layer_hbm_point(mlf, oracle_mod):
+    """The 3-layer 4096^2 FP32 film, the benchmark's HBM-bound point, in
+    the launch shape the benchmark times for it (512-lane strips), against
+    the oracle over 6 steps, every element."""
+    import bench
+
+    film, h0, _ = inputs.workload("film3_2d_4096")
+    launch = bench.profiled_launch("film3_2d_4096", "f32") or (512, 6)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 6, "f32", launch=launch)
+    check(g, o, 1e-5, 1e-4)
+
+
 GOLDEN_T10K = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "film3_1024_t10k.npz")
 
 
