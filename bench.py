@@ -422,9 +422,9 @@ def bench_conv_kernels(args):
     """The surrogate's MFMA 3x3 convolutions (3-layer 256^2 films, width
     128, batch 64 of the training step): --steps forward and backward
     passes on seeded random weights and heights (the training step's
-    launches, for a kernel trace), then the event-timed average of each
-    forward epilogue variant and of the weight gradient, --steps
-    back-to-back launches each."""
+    launches, for a kernel trace), the wall time of --steps training steps,
+    then the event-timed average of each forward epilogue variant and of
+    the weight gradient, --steps back-to-back launches each."""
     import numpy as np
     import torch
 
@@ -440,6 +440,14 @@ def bench_conv_kernels(args):
     for _ in range(args.steps):
         m.predict(h)
         m.gradient(h, h1)
+    # whole training steps (forward, backward, Adam; a learning rate of
+    # 1e-30 leaves the FP32 weights as they are), wall clock over --steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m.train_step(h, h1, 1e-30)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     m.predict(h)
     ms = m.time_conv(64, reps=args.steps)
     flops = m.conv_flops(64)
@@ -447,7 +455,8 @@ def bench_conv_kernels(args):
            "steps": args.steps, "dtype": "bf16", "data": "synthetic", "peak": 2500.0, "flops": flops,
            "config": {"workload": "surrogate_conv_film3_256", "width": 128, "batch": 64, "latent": [64, 64]},
            "kernels": {k: {"ms": v, "tflops": flops / (v * 1e-3) / 1e12, "frac": flops / (v * 1e-3) / 1e12 / 2500.0}
-                       for k, v in ms.items()}}
+                       for k, v in ms.items()},
+           "train_step_ms": step_ms}
     print(json.dumps(out), flush=True)
 
 
