@@ -181,6 +181,26 @@ def test_set_launch_validation():
         lib.mlf_destroy(h)
 
 
+def test_set_launch_512_lanes():
+    """512-lane strips are accepted for every format except FP64 films of
+    four layers, whose step kernel is compiled for at most 256 lanes."""
+    for prec, n, ok in [("f32", 4, True), ("f64", 3, True), ("f16mix", 4, True), ("f64", 4, False)]:
+        film = inputs.film_params(n, 300, 40, gamma=[0.01] * n, mu=[0.01] * n, hstar=0.1)
+        lib, h = _fake_handle(film, prec)
+        try:
+            rc = lib.mlf_set_launch(h, 512, 8)
+            assert (rc == 0) == ok, (prec, n)
+            a, b = C.c_int32(), C.c_int32()
+            lib.mlf_get_launch(h, C.byref(a), C.byref(b))
+            if ok:
+                assert (a.value, b.value) == (512, 8)
+            else:
+                assert b"512" in lib.mlf_last_error(h)
+                assert a.value != 512
+        finally:
+            lib.mlf_destroy(h)
+
+
 def test_surrogate_sizes_and_validation():
     from oracle import nop
 
