@@ -181,18 +181,20 @@ __global__ void __launch_bounds__(64 * WAVES, 2) conv3x3_fwd(const __bf16* __res
     const int xrow = (wave + d) * PX;  // input row y + dy, dy = d - 1
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      bf16x8 a[4], bb[NT];
+      bf16x8 a[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m)
         a[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sx + swz(xrow + 16 * m + r + dx, g)));
+      // each weight fragment is read just before its four products: holding
+      // all NT of them would take the residual variant past 256 VGPRs
 #pragma unroll
-      for (int n = 0; n < NT; ++n)
-        bb[n] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sw + swz(dx * CO + 16 * n + r, g)));
+      for (int n = 0; n < NT; ++n) {
+        const bf16x8 bn =
+            __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v*>(sw + swz(dx * CO + 16 * n + r, g)));
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb[n], acc[m][n], 0, 0, 0);
+        for (int m = 0; m < 4; ++m)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bn, acc[m][n], 0, 0, 0);
+      }
     }
     if constexpr (EPI == kEpiResid) {
 #pragma unroll
