@@ -62,16 +62,30 @@ def _profile_entry(workload: str, prec: str):
 
 
 def profiled_launch(workload: str, prec: str):
-    """Launch shape the autotuner chose for the profiled run, if current."""
+    """Launch shape (block width, segment height) the autotuner chose for
+    the profiled run, if current."""
     ent = _profile_entry(workload, prec)
-    return tuple(ent["launch"]) if ent else None
+    return tuple(ent["launch"][:2]) if ent else None
+
+
+def profiled_prefetch(workload: str, prec: str) -> int:
+    """Rows in flight (mlf_set_prefetch) of the profiled run: 1 unless the
+    record says otherwise."""
+    ent = _profile_entry(workload, prec)
+    return int(ent["launch"][2]) if ent and len(ent["launch"]) > 2 else 1
 
 
 def measured_traffic(workload: str, prec: str, launch):
     """HBM bytes per launch from rocprofv3 counters, if they were taken on
-    the current kernel source in this launch shape; else None."""
+    the current kernel source in this launch shape (block width, segment
+    height, rows in flight); else None."""
     ent = _profile_entry(workload, prec)
-    if not ent or list(ent.get("launch", [])) != list(launch):
+    if not ent:
+        return None
+    rec = list(ent.get("launch", []))
+    if len(rec) == 2:
+        rec.append(1)
+    if rec != list(launch):
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -170,7 +184,7 @@ def _strip_count(nx, w):
 def step_grid_threads(film, launch):
     """Work-items of one step_kernel dispatch of this film and launch shape
     (the grid is padded to a multiple of the 8 XCDs)."""
-    w, sh = launch
+    w, sh = launch[0], launch[1]
     tiles = _strip_count(film["nx"], w) * ((film["ny"] + sh - 1) // sh)
     return (tiles + 7) // 8 * 8 * w
 
@@ -227,7 +241,7 @@ def ingest_profile(a):
 
     film, _, spec = inputs.workload(a.workload)
     prec = a.precision or spec["precision"]
-    launch = (a.block_w, a.seg_h)
+    launch = (a.block_w, a.seg_h, a.prefetch or 1)
     grid = step_grid_threads(film, launch)
     n_lu = film["n_layers"] * film["nx"] * film["ny"]
     bpl = mlfilm.bytes_per_update(prec)
@@ -479,14 +493,16 @@ def film_point(workload, prec, args, steps, warmup, lattice="d2q9"):
         source = "fixed (D1Q3 kernels)"
     elif (args.block_w or args.seg_h) and workload == args.workload:
         g.set_launch(args.block_w, args.seg_h)
+        g.set_prefetch(args.prefetch)
         source = "given"
     elif pl:
         g.set_launch(*pl)
+        g.set_prefetch(profiled_prefetch(workload, prec))
         source = "autotuned (profiled run)"
     else:
         g.autotune(reps=3)  # library autotuner: times shapes, state unchanged
         source = "autotuned"
-    launch = g.get_launch()
+    launch = (*g.get_launch(), g.get_prefetch())
     print(f"[bench] {workload} {prec} N={film['n_layers']} {film['nx']}x{film['ny']} "
           f"launch={launch} warmup={warmup} steps={steps}", file=sys.stderr, flush=True)
     g.step(warmup)
@@ -537,6 +553,9 @@ def main():
                     help="launch shape; default: the shape the autotuner chose for the profiled run of this "
                          "kernel source, else the autotuner now")
     ap.add_argument("--seg-h", type=int, default=0, help="launch shape (see --block-w)")
+    ap.add_argument("--prefetch", type=int, default=0,
+                    help="rows in flight in the step kernel with --block-w/--seg-h (0: default, 1 or 2); "
+                         "with --ingest-kt: the profiled run's value")
     ap.add_argument("--autotune", action="store_true", help="always run the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget on all host threads; 0 disables the CPU baseline")

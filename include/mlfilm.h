@@ -216,15 +216,26 @@ mlf_status mlf_load(mlf_handle* h, const void* blob, size_t bytes);
 mlf_status mlf_set_launch(mlf_handle* h, int32_t block_w, int32_t seg_h);
 mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h);
 
+/* Rows of populations the step kernel keeps in flight while it processes a
+ * row: 1 (default; 0 selects it) or 2.  Two are available for D2Q9 films
+ * with tau == 1 and storage other than MLF_F64 (FP32 arithmetic): they hide
+ * more load latency on HBM-sized films at the cost of registers (fewer waves
+ * per SIMD).  Results do not depend on it.  MLF_EINVAL for other values, or
+ * for 2 on other films (mlf_last_error says why).  Drops a captured graph.
+ * mlf_get_prefetch writes the current value (rows must not be NULL). */
+mlf_status mlf_set_prefetch(mlf_handle* h, int32_t rows);
+mlf_status mlf_get_prefetch(const mlf_handle* h, int32_t* rows);
+
 /* Autotuner: times candidate launch shapes on the current state and keeps
  * the fastest (written to block_w / seg_h if not NULL).  Each candidate is
  * launched `reps` times (>= 1) from the current population buffer into the
  * other one without swapping, so the state and step counter are unchanged;
  * the four fastest are then re-timed twice with 4 x reps launches each and
  * the smallest time wins.  Candidates: block_w in {64, 128, 192, 256, 512}
- * (not 512 for FP64 films of four layers) and segment heights from a fixed
- * list plus those that fill whole dispatch rounds of the device.
- * Synchronises. */
+ * (not 512 for FP64 films of four layers), segment heights from a fixed
+ * list plus those that fill whole dispatch rounds of the device, and 1 or 2
+ * rows in flight where mlf_set_prefetch allows 2 (the choice is kept; read
+ * it with mlf_get_prefetch).  Synchronises. */
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h);
 
 /* Capture `steps` (even, > 0) consecutive step launches into a HIP graph

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -523,6 +524,7 @@ struct mlf_handle {
   double scale[kMaxLayers];  // storage scale per layer (1 except IEEE half)
   int64_t steps;
   int block_w, seg_h;
+  int ahead;  // rows of populations in flight in the step kernel (1 or 2)
   bool initialised;
   hipGraphExec_t graph;  // captured step loop (constants baked in), or null
   int graph_steps, graph_parity;
@@ -698,27 +700,42 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
 
 // Workgroups of the step kernel that fit on one CU at the handle's block
 // width (0 if unknown).
-template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
-int occupancy_nl(const mlf_handle* h) {
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB, int AH>
+int occupancy_ah(const mlf_handle* h) {
   int nb = 0;
   size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mlf::step_kernel<R, S, C, NL, T1, EA, EB>, h->block_w,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mlf::step_kernel<R, S, C, NL, T1, EA, EB, AH>, h->block_w,
                                                    lds) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
-hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB, int AH>
+hipError_t launch_ah(const mlf_handle* h, const void* src, void* dst) {
   mlf::StepConsts<C> kc = make_consts<C>(h);
   // grid padded to a multiple of the XCD count (tile_of_block)
   const int ntiles = kc.nstrip * kc.nseg;
   const int nblocks = (ntiles + mlf::kXcds - 1) / mlf::kXcds * mlf::kXcds;
   dim3 grid((unsigned)nblocks), block((unsigned)h->block_w);
   size_t lds = (size_t)8 * NL * h->block_w * sizeof(C);
-  hipLaunchKernelGGL((mlf::step_kernel<R, S, C, NL, T1, EA, EB>), grid, block, lds, h->stream,
+  hipLaunchKernelGGL((mlf::step_kernel<R, S, C, NL, T1, EA, EB, AH>), grid, block, lds, h->stream,
                      static_cast<const unsigned char*>(src), static_cast<unsigned char*>(dst), kc);
   return hipGetLastError();
+}
+
+// Two rows ahead exist for tau = 1 with FP32 arithmetic only (prefetch_ok).
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
+int occupancy_nl(const mlf_handle* h) {
+  if constexpr (T1 && sizeof(C) == 4)
+    if (h->ahead == 2) return occupancy_ah<R, S, C, NL, T1, EA, EB, 2>(h);
+  return occupancy_ah<R, S, C, NL, T1, EA, EB, 1>(h);
+}
+
+template <typename R, typename S, typename C, int NL, bool T1, int EA, int EB>
+hipError_t launch_nl(const mlf_handle* h, const void* src, void* dst) {
+  if constexpr (T1 && sizeof(C) == 4)
+    if (h->ahead == 2) return launch_ah<R, S, C, NL, T1, EA, EB, 2>(h, src, dst);
+  return launch_ah<R, S, C, NL, T1, EA, EB, 1>(h, src, dst);
 }
 
 // Dispatch on (layers, tau == 1, exponents == (9, 3)); OCC selects the
@@ -1174,6 +1191,7 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   h->graph_steps = 0;
   h->graph_parity = 0;
   default_launch(p, &h->block_w, &h->seg_h);
+  h->ahead = 1;
   *out = h;
   return MLF_OK;
 }
@@ -1221,6 +1239,28 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
   return MLF_OK;
 }
 
+// Two rows of populations in flight: D2Q9 films with tau = 1 and FP32
+// arithmetic (every storage format but FP64).
+bool prefetch_ok(const mlf_params& p) {
+  return p.lattice == MLF_D2Q9 && p.tau == 1.0 && p.precision != MLF_F64;
+}
+
+mlf_status mlf_set_prefetch(mlf_handle* h, int32_t rows) {
+  if (!h) return MLF_EINVAL;
+  if (rows < 0 || rows > 2) return fail(h, MLF_EINVAL, "prefetch rows must be 0, 1 or 2");
+  if (rows == 2 && !prefetch_ok(h->p))
+    return fail(h, MLF_EINVAL, "two rows ahead needs a D2Q9 film with tau = 1 and non-FP64 storage");
+  drop_single_graph(h);
+  h->ahead = rows == 0 ? 1 : rows;
+  return MLF_OK;
+}
+
+mlf_status mlf_get_prefetch(const mlf_handle* h, int32_t* rows) {
+  if (!h || !rows) return MLF_EINVAL;
+  *rows = h->ahead;
+  return MLF_OK;
+}
+
 mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* seg_h) {
   if (!h || reps < 1) return MLF_EINVAL;
   if (!h->initialised) return fail(h, MLF_EINVAL, "autotune before init");
@@ -1234,23 +1274,27 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
   int dev = 0, ncu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int keep_w = h->block_w, keep_h = h->seg_h;
-  std::vector<std::pair<int, int>> cand;
+  const int keep_w = h->block_w, keep_h = h->seg_h, keep_a = h->ahead;
+  // candidates (block width, segment height, rows in flight)
+  typedef std::array<int, 3> Cand;
+  std::vector<Cand> cand;
   const int fixed[] = {2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64, 96, 128};
-  for (int w : {64, 128, 192, 256, 512}) {
-    if (w > max_block_w(p)) continue;
-    h->block_w = w;
-    const int nstrip = mlf::strip_count(p.nx, w);
-    for (int sh : fixed)
-      if (sh <= p.ny) cand.emplace_back(w, sh);
-    // heights that fill 1..4 whole dispatch rounds
-    const int slots = std::max(1, step_occupancy(h)) * std::max(1, ncu);
-    for (int rounds = 1; rounds <= 4; ++rounds) {
-      const int segs = std::max(1, rounds * slots / nstrip);
-      const int sh = std::max(1, (p.ny + segs - 1) / segs);
-      cand.emplace_back(w, std::min(sh, p.ny));
+  for (int ah = 1; ah <= (prefetch_ok(p) ? 2 : 1); ++ah)
+    for (int w : {64, 128, 192, 256, 512}) {
+      if (w > max_block_w(p)) continue;
+      h->block_w = w;
+      h->ahead = ah;
+      const int nstrip = mlf::strip_count(p.nx, w);
+      for (int sh : fixed)
+        if (sh <= p.ny) cand.push_back({w, sh, ah});
+      // heights that fill 1..4 whole dispatch rounds
+      const int slots = std::max(1, step_occupancy(h)) * std::max(1, ncu);
+      for (int rounds = 1; rounds <= 4; ++rounds) {
+        const int segs = std::max(1, rounds * slots / nstrip);
+        const int sh = std::max(1, (p.ny + segs - 1) / segs);
+        cand.push_back({w, std::min(sh, p.ny), ah});
+      }
     }
-  }
   std::sort(cand.begin(), cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   hipEvent_t e0, e1;
@@ -1259,9 +1303,10 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
   mlf_status st = MLF_OK;
   // ms per launch of candidate c over n launches (current -> other buffer,
   // never swapped: the state is left unchanged)
-  auto time_of = [&](const std::pair<int, int>& c, int n, float* ms) {
-    h->block_w = c.first;
-    h->seg_h = c.second;
+  auto time_of = [&](const Cand& c, int n, float* ms) {
+    h->block_w = c[0];
+    h->seg_h = c[1];
+    h->ahead = c[2];
     if ((st = hip_check(h, launch_step(h, h->pop[h->cur], h->pop[h->cur ^ 1]), "autotune launch")) != MLF_OK)
       return false;
     if ((st = hip_check(h, hipEventRecord(e0, h->stream), "hipEventRecord")) != MLF_OK) return false;
@@ -1277,13 +1322,13 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
   // a first pass over every candidate, then the four fastest re-timed in two
   // interleaved rounds of 4 x reps launches (the minimum counts): single
   // short timings are noisy at the few-percent level that separates shapes
-  std::vector<std::pair<float, std::pair<int, int>>> timed;
+  std::vector<std::pair<float, Cand>> timed;
   for (const auto& c : cand) {
     float ms = 0.f;
     if (!time_of(c, reps, &ms)) break;
     timed.emplace_back(ms, c);
   }
-  int bw = keep_w, bh = keep_h;
+  int bw = keep_w, bh = keep_h, ba = keep_a;
   if (st == MLF_OK && !timed.empty()) {
     std::sort(timed.begin(), timed.end());
     timed.resize(std::min<size_t>(timed.size(), 4));
@@ -1294,13 +1339,15 @@ mlf_status mlf_autotune(mlf_handle* h, int32_t reps, int32_t* block_w, int32_t* 
         if (time_of(timed[i].second, 4 * reps, &ms)) best[i] = std::min(best[i], ms);
       }
     const size_t k = (size_t)(std::min_element(best.begin(), best.end()) - best.begin());
-    bw = timed[k].second.first;
-    bh = timed[k].second.second;
+    bw = timed[k].second[0];
+    bh = timed[k].second[1];
+    ba = timed[k].second[2];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->block_w = (st == MLF_OK) ? bw : keep_w;
   h->seg_h = (st == MLF_OK) ? bh : keep_h;
+  h->ahead = (st == MLF_OK) ? ba : keep_a;
   if (st != MLF_OK) return st;
   if (block_w) *block_w = bw;
   if (seg_h) *seg_h = bh;

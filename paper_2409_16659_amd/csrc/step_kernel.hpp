@@ -527,10 +527,13 @@ __device__ inline void node_collide(const StepConsts<C>& kc, const C (&dh2)[NL],
 }
 
 // One tile (strip x segment) of one step: the whole workgroup marches the
-// segment's rows.  `tile` is uniform and < kc.nstrip * kc.nseg.
-template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
+// segment's rows.  `tile` is uniform and < kc.nstrip * kc.nseg.  AHEAD rows
+// of populations are in flight while a row is processed (2 only with
+// tau = 1); the arithmetic, and so every result, is the same for both.
+template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB, int AHEAD = 1>
 __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
                                  const StepConsts<C>& kc, int tile) {
+  static_assert(AHEAD == 1 || (AHEAD == 2 && TAU1), "two rows ahead needs tau = 1");
   const int W = blockDim.x;
   const int tid = threadIdx.x;
   const int strip = tile % kc.nstrip;
@@ -574,12 +577,13 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
   C dh0[NL], qx0[NL], qy0[NL];
   C dh1[NL], qx1[NL], qy1[NL];
   C dh2[NL], qx2[NL], qy2[NL];
-  // populations of the current row and the prefetched next row (ping-pong)
-  C fa[NL][kQ], fb[NL][kQ];
+  // populations of the current row and of the AHEAD prefetched rows
+  // (ping-pong for one; three buffers rotated for two)
+  C fa[NL][kQ], fb[NL][kQ], fe[NL][kQ];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) fa[i][k] = fb[i][k] = C(0);
+    for (int k = 0; k < kQ; ++k) fa[i][k] = fb[i][k] = fe[i][k] = C(0);
     dh0[i] = dh1[i] = dh2[i] = C(0);
     qx0[i] = qx1[i] = qx2[i] = C(0);
     qy0[i] = qy1[i] = qy2[i] = C(0);
@@ -674,10 +678,10 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
       }
       if (act1 && bad) kc.flag[0] = bad;
     }
-    // Prefetch the next row only after this row's registers are consumed: the
-    // loads then stay in flight across both barriers and the stores of P3,
-    // and the wait at the next P1 covers these loads but not those stores.
-    load_row(r + dir, it + 1 < niter, fn);
+    // Prefetch row it + AHEAD only after this row's registers are consumed:
+    // the loads then stay in flight across both barriers and the stores of
+    // P3, and the wait at P1 covers the loads of its own row only.
+    load_row(r + AHEAD * dir, it + AHEAD < niter, fn);
     __syncthreads();
     // ---- P2: pressures of row r - dir ---------------------------------------
     if (it >= 2 && act2) {
@@ -765,6 +769,17 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
           for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
       }
       store_row(st_ok, oS, oC, oN, oR, fo);
+    } else if constexpr (AHEAD == 2) {
+      // warm-up rows issue dropped stores where later rows store, so the
+      // row loop is entered with the pending sequence of every later
+      // iteration (loads of rows it and it + 1, each followed by a row's
+      // stores)
+      C zero[NL][kQ];
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) zero[i][k] = C(0);
+      store_row(false, 0, 0, 0, 0, zero);
     }
     // rotate the moment pipeline
 #pragma unroll
@@ -779,6 +794,24 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
   };
 
   load_row(rstart, true, fa);
+  if constexpr (AHEAD == 2) {
+    // rows 0 and 1 in flight; iteration k reads buffer k % 3 (fa, fb, fe)
+    // and loads row k + 2 into buffer (k + 2) % 3, the one read at k - 1
+    load_row(rstart + dir, 1 < niter, fb);
+    body(std::false_type{}, 0, fa, fe);
+    body(std::false_type{}, 1, fb, fa);
+    body(std::false_type{}, 2, fe, fb);
+    body(std::false_type{}, 3, fa, fe);
+    int it = 4;
+    for (; it + 2 < niter; it += 3) {
+      body(std::true_type{}, it, fb, fa);
+      body(std::true_type{}, it + 1, fe, fb);
+      body(std::true_type{}, it + 2, fa, fe);
+    }
+    if (it < niter) body(std::true_type{}, it, fb, fa);
+    if (it + 1 < niter) body(std::true_type{}, it + 1, fe, fb);
+    return;
+  }
   int it = 0;
   if constexpr (TAU1) {
     // warm-up rows (niter >= 5 always): P1 and P2 only
@@ -814,12 +847,12 @@ constexpr int step_max_lanes() {
   return (sizeof(C) == 8 && NL == 4) ? 256 : 512;
 }
 
-template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB>
+template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB, int AHEAD>
 __global__ void __launch_bounds__((step_max_lanes<C, NL>()))
 step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
   const int tile = tile_of_block(blockIdx.x, gridDim.x);
   if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)
-  step_tile<R, S, C, NL, TAU1, EA, EB>(src, dst, kc, tile);
+  step_tile<R, S, C, NL, TAU1, EA, EB, AHEAD>(src, dst, kc, tile);
 }
 
 // ---- batches of independent films -----------------------------------------

@@ -94,6 +94,8 @@ def load_library():
         "mlf_save": (st, [H, C.c_void_p, C.POINTER(C.c_size_t)]),
         "mlf_load": (st, [H, C.c_void_p, C.c_size_t]),
         "mlf_set_launch": (st, [H, C.c_int32, C.c_int32]),
+        "mlf_set_prefetch": (st, [H, C.c_int32]),
+        "mlf_get_prefetch": (st, [H, C.POINTER(C.c_int32)]),
         "mlf_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_capture": (st, [H, C.c_int32]),
@@ -435,6 +437,14 @@ class Film:
 
     def set_launch(self, block_w=0, seg_h=0):
         self._check(self.lib.mlf_set_launch(self.h, int(block_w), int(seg_h)), "mlf_set_launch")
+
+    def set_prefetch(self, rows=0):
+        self._check(self.lib.mlf_set_prefetch(self.h, int(rows)), "mlf_set_prefetch")
+
+    def get_prefetch(self) -> int:
+        v = C.c_int32()
+        self._check(self.lib.mlf_get_prefetch(self.h, C.byref(v)), "mlf_get_prefetch")
+        return v.value
 
     def autotune(self, reps=5):
         """Pick the fastest launch shape on the current state (unchanged)."""

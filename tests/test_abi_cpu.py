@@ -201,6 +201,31 @@ def test_set_launch_512_lanes():
             lib.mlf_destroy(h)
 
 
+def test_set_prefetch_validation():
+    """Two rows in flight need a D2Q9 film with tau = 1 and non-FP64
+    storage; 0 selects the default of one row; other values are refused."""
+    cases = [("f32", 1.0, 2, True), ("f16mix", 1.0, 2, True), ("f64", 1.0, 2, False), ("f32", 0.8, 2, False),
+             ("f64", 0.8, 1, True), ("f32", 1.0, 3, False), ("f32", 1.0, -1, False)]
+    for prec, tau, rows, ok in cases:
+        film = inputs.film_params(2, 64, 16, gamma=[0.01] * 2, mu=[0.01] * 2, hstar=0.1, tau=tau)
+        lib, h = _fake_handle(film, prec)
+        try:
+            v = C.c_int32()
+            assert lib.mlf_get_prefetch(h, C.byref(v)) == 0 and v.value == 1
+            rc = lib.mlf_set_prefetch(h, rows)
+            assert (rc == 0) == ok, (prec, tau, rows)
+            lib.mlf_get_prefetch(h, C.byref(v))
+            assert v.value == (rows if ok else 1)
+            if not ok:
+                assert lib.mlf_last_error(h)
+            assert lib.mlf_set_prefetch(h, 0) == 0
+            lib.mlf_get_prefetch(h, C.byref(v))
+            assert v.value == 1
+        finally:
+            lib.mlf_destroy(h)
+    assert lib.mlf_get_prefetch(None, C.byref(C.c_int32())) != 0
+
+
 def test_surrogate_sizes_and_validation():
     from oracle import nop
 

@@ -45,11 +45,13 @@ def err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def run_pair(mlf, oracle_mod, film, h0, steps, precision="f64", launch=None, ux=None, uy=None):
-    say(f"case N={film['n_layers']} {film['nx']}x{film['ny']} {precision} steps={steps} launch={launch}")
+def run_pair(mlf, oracle_mod, film, h0, steps, precision="f64", launch=None, ux=None, uy=None, prefetch=0):
+    say(f"case N={film['n_layers']} {film['nx']}x{film['ny']} {precision} steps={steps} launch={launch} "
+        f"prefetch={prefetch}")
     g = mlf.Film(film, precision)
     if launch:
         g.set_launch(*launch)
+    g.set_prefetch(prefetch)
     g.init(h0, ux, uy)
     o = oracle_mod.Oracle(film)
     o.init(h0, ux, uy)
@@ -202,11 +204,19 @@ def bench_launch():
     return bench.profiled_launch("film3_2d_1024", "f32") or (192, 8)
 
 
+def bench_prefetch(workload):
+    """Rows in flight the benchmark sets for an FP32 workload."""
+    import bench
+
+    return bench.profiled_prefetch(workload, "f32")
+
+
 def test_fp32_three_layer_full_size(mlf, oracle_mod):
     """Full 1024x1024 3-layer workload in the benchmark's launch shape,
     against the oracle over 20 steps."""
     film, h0, _ = inputs.workload("film3_2d_1024")
-    g, o = run_pair(mlf, oracle_mod, film, h0, 20, "f32", launch=bench_launch())
+    g, o = run_pair(mlf, oracle_mod, film, h0, 20, "f32", launch=bench_launch(),
+                    prefetch=bench_prefetch("film3_2d_1024"))
     check(g, o, 1e-5, 1e-4)
 
 
@@ -218,7 +228,7 @@ def test_fp32_three_layer_hbm_point(mlf, oracle_mod):
 
     film, h0, _ = inputs.workload("film3_2d_4096")
     launch = bench.profiled_launch("film3_2d_4096", "f32") or (512, 6)
-    g, o = run_pair(mlf, oracle_mod, film, h0, 6, "f32", launch=launch)
+    g, o = run_pair(mlf, oracle_mod, film, h0, 6, "f32", launch=launch, prefetch=bench_prefetch("film3_2d_4096"))
     check(g, o, 1e-5, 1e-4)
 
 
@@ -252,6 +262,7 @@ def test_full_size_parity_horizon_vs_oracle(mlf, prec, tol_h, tol_u, tol_pert, t
     g = mlf.Film(film, prec)
     if launch:
         g.set_launch(*launch)
+        g.set_prefetch(bench_prefetch("film3_2d_1024"))
     g.init(h0)
     g.step(10_000)
     h, ux, uy = g.read()
@@ -272,16 +283,19 @@ def test_full_size_parity_horizon_vs_oracle(mlf, prec, tol_h, tol_u, tol_pert, t
 
 # ------------------------------------------------------------ properties --
 def test_launch_shape_independence(mlf):
-    """Per-node arithmetic has a fixed order, so every launch shape gives
-    bit-identical results (a race or halo bug would break this)."""
+    """Per-node arithmetic has a fixed order, so every launch shape and
+    prefetch depth gives bit-identical results (a race or halo bug would
+    break this)."""
     for prec in ("f64", "f32"):
         film = small_film(3, 300, 45, seed=16)
         h0 = noisy(3, 300, 45, seed=17)
         ref = None
-        for launch in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 45), (512, 4), (512, 45), (128, 3)]:
+        shapes = [(64, 1), (64, 7), (128, 16), (256, 5), (256, 45), (512, 4), (512, 45), (128, 3)]
+        for launch in shapes + ([(64, 1, 2), (192, 6, 2), (512, 45, 2)] if prec == "f32" else []):
             say(f"shape {prec} {launch}")
             g = mlf.Film(film, prec)
-            g.set_launch(*launch)
+            g.set_launch(*launch[:2])
+            g.set_prefetch(launch[2] if len(launch) > 2 else 1)
             g.init(h0)
             g.step(40)
             f = g.populations()
@@ -294,15 +308,17 @@ def test_launch_shape_independence(mlf):
 def test_wide_strip_launch_shapes(mlf):
     """512-lane strips on a film wider than one of them (1100 columns: three
     strips of at most 508 columns) give the same populations as 64- and
-    192-lane strips."""
+    192-lane strips, also with two rows in flight (FP32)."""
     film = small_film(2, 1100, 24, seed=40)
     h0 = noisy(2, 1100, 24, seed=41)
     for prec in ("f64", "f32"):
         ref = None
-        for launch in [(64, 3), (192, 24), (512, 5), (512, 24)]:
+        extra = [(512, 5, 2), (256, 24, 2)] if prec == "f32" else []
+        for launch in [(64, 3), (192, 24), (512, 5), (512, 24)] + extra:
             say(f"wide shape {prec} {launch}")
             g = mlf.Film(film, prec)
-            g.set_launch(*launch)
+            g.set_launch(*launch[:2])
+            g.set_prefetch(launch[2] if len(launch) > 2 else 1)
             g.init(h0)
             g.step(30)
             f = g.populations()
@@ -479,6 +495,7 @@ def test_autotune_keeps_state(mlf):
         say(f"   autotune {prec}: {bw}x{sh}")
         assert bw in (64, 128, 192, 256, 512) and 1 <= sh <= 90
         assert a.get_launch() == (bw, sh)
+        assert a.get_prefetch() == 1 if prec == "f64" else a.get_prefetch() in (1, 2)
         assert a.steps_done == 5
         assert np.array_equal(a.populations(), f0)
         a.step(10)

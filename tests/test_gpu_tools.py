@@ -187,6 +187,7 @@ def test_full_size_rupture_fp32_matches_fp64(mlf):
             break
     s = mlf.Film(film, "f32", check_every=1000)
     s.set_launch(*launch)
+    s.set_prefetch(bench.profiled_prefetch("film3_2d_1024", "f32"))
     s.init(h0)
     s_mass0 = s.mass()
     steps, layer = s.step_until(cap, every)
