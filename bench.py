@@ -277,7 +277,9 @@ def ingest_profile(a):
 def bench_batch(args):
     """Batched scan: summed layer-node updates per second of one launch per
     step over all films, and the same films run back to back through the
-    single-film kernel (each film all its steps, best case for reuse)."""
+    single-film kernel (each film all its steps, best case for reuse; in
+    the batch's launch shape and in the films' default shapes, the faster
+    counting)."""
     import numpy as np
     import torch
 
@@ -290,7 +292,7 @@ def bench_batch(args):
     b = mlfilm.Batch([f for f, _ in films], "f32")
     for i, (_, h0) in enumerate(films):
         b.init(i, h0)
-    launch = b.autotune(reps=2)
+    launch = (*b.autotune(reps=2), b.get_prefetch())
     if args.graph_steps:
         b.capture(args.graph_steps)
     print(f"[bench] batch of {len(films)} films, {n_lu / 1e6:.1f} M LU/step, launch {launch}, "
@@ -308,23 +310,32 @@ def bench_batch(args):
     assert all(np.all(np.isfinite(b.mass(i))) for i in range(len(films)))
     del b
 
-    # the same films, one single-film kernel launch per film and step
-    gs = []
-    for f, h0 in films:
-        g = mlfilm.Film(f, "f32", check_every=-1)
-        g.set_launch(launch[0], launch[1])
-        g.init(h0)
-        gs.append(g)
-    for g in gs:
-        g.step(warm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g in gs:
-        g.step(steps)
-    torch.cuda.synchronize()
-    wall_p = time.perf_counter() - t0
-    print(f"[bench] plain back-to-back: {wall_p:.3f} s", file=sys.stderr, flush=True)
-    del gs
+    # the same films, one single-film kernel launch per film and step: in
+    # the batch's launch shape and rows in flight, and in each film's default
+    # shape (library default); the faster one is the baseline
+    def plain(batch_shape):
+        gs = []
+        for f, h0 in films:
+            g = mlfilm.Film(f, "f32", check_every=-1)
+            if batch_shape:
+                g.set_launch(launch[0], launch[1])
+                g.set_prefetch(launch[3])
+            g.init(h0)
+            gs.append(g)
+        for g in gs:
+            g.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in gs:
+            g.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    walls = {"batch": plain(True), "default": plain(False)}
+    plain_shape = min(walls, key=walls.get)
+    wall_p = walls[plain_shape]
+    print(f"[bench] plain back-to-back: {walls['batch']:.3f} s in the batch's shape, {walls['default']:.3f} s in "
+          f"each film's default shape", file=sys.stderr, flush=True)
 
     value = n_lu * steps / wall_b
     achieved = 72 * n_lu / (kern_ms * 1e-3) / 1e9
@@ -336,7 +347,8 @@ def bench_batch(args):
         "config": {"workload": f"batch_scan_{len(films)}", "films": len(films), "lu_per_step": n_lu,
                    "launch": list(launch), "graph_steps": args.graph_steps},
         "plain": {"value": n_lu * steps / wall_p, "unit": "LU/s", "ms_per_step": wall_p * 1e3 / steps,
-                  "launches_per_step": len(films)},
+                  "launches_per_step": len(films), "launch": plain_shape,
+                  "ms_per_step_by_launch": {k: v * 1e3 / steps for k, v in walls.items()}},
         "speedup_vs_plain": wall_p / wall_b,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_lu": 72,

@@ -342,9 +342,18 @@ mlf_status mlf_batch_step_until(mlf_batch* b, int64_t max_steps, int32_t check_e
 mlf_status mlf_batch_set_launch(mlf_batch* b, int32_t block_w, int32_t seg_h, int32_t persistent);
 mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* seg_h, int32_t* persistent);
 
-/* Autotuner over block_w x seg_h x persistent, `reps` timed launches each
- * from the current buffer into the other (state unchanged); keeps the
- * fastest.  Drops a captured graph.  Synchronises. */
+/* Rows of populations in flight in the batch kernel, as mlf_set_prefetch
+ * for a single film (2 only for D2Q9 batches with tau == 1 and storage
+ * other than MLF_F64; results do not depend on it).  Drops a captured
+ * graph.  rows must not be NULL for the getter. */
+mlf_status mlf_batch_set_prefetch(mlf_batch* b, int32_t rows);
+mlf_status mlf_batch_get_prefetch(const mlf_batch* b, int32_t* rows);
+
+/* Autotuner over block_w x seg_h x persistent x rows in flight (1, and 2
+ * where mlf_batch_set_prefetch allows it), `reps` timed launches each from
+ * the current buffer into the other (state unchanged); keeps the fastest
+ * (read the depth with mlf_batch_get_prefetch).  Drops a captured graph.
+ * Synchronises. */
 mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int32_t* seg_h, int32_t* persistent);
 
 /* Steps the batch has taken since it was created (-1 for NULL). */

@@ -1822,6 +1822,7 @@ struct mlf_batch {
   unsigned char* scratch;
   hipStream_t stream;
   int block_w, seg_h, persistent;
+  int ahead;  // rows of populations in flight in the batch kernel (1 or 2)
   int max_nl;
   int n_items;
   bool table_dirty;
@@ -1935,9 +1936,9 @@ mlf_status upload_table(mlf_batch* b) {
   return batch_double(b) ? upload_table_t<double>(b) : upload_table_t<float>(b);
 }
 
-template <typename R, typename S, typename C, bool T1, int EA, int EB>
-hipError_t launch_batch_t(const mlf_batch* b, int flip, int* occ) {
-  auto kern = mlf::batch_kernel<R, S, C, T1, EA, EB>;
+template <typename R, typename S, typename C, bool T1, int EA, int EB, int AH>
+hipError_t launch_batch_ah(const mlf_batch* b, int flip, int* occ) {
+  auto kern = mlf::batch_kernel<R, S, C, T1, EA, EB, AH>;
   const size_t lds = (size_t)8 * b->max_nl * b->block_w * sizeof(C);
   if (occ) {
     int nb = 0;
@@ -1960,6 +1961,13 @@ hipError_t launch_batch_t(const mlf_batch* b, int flip, int* occ) {
                      reinterpret_cast<const int2*>(b->scratch + kBatchItemOff), b->n_items, b->pop[0], b->pop[1],
                      flip);
   return hipGetLastError();
+}
+
+template <typename R, typename S, typename C, bool T1, int EA, int EB>
+hipError_t launch_batch_t(const mlf_batch* b, int flip, int* occ) {
+  if constexpr (T1 && sizeof(C) == 4)
+    if (b->ahead == 2) return launch_batch_ah<R, S, C, T1, EA, EB, 2>(b, flip, occ);
+  return launch_batch_ah<R, S, C, T1, EA, EB, 1>(b, flip, occ);
 }
 
 template <typename R, typename S, typename C>
@@ -2103,6 +2111,7 @@ mlf_status mlf_batch_create(const mlf_params* films, int32_t n, void* pop_a, voi
   b->block_w = 256;
   b->seg_h = 8;
   b->persistent = 0;
+  b->ahead = 1;
   if (batch_items(b, b->block_w, b->seg_h) * (long long)sizeof(int2) > (long long)kBatchItemBytes ||
       (size_t)n * batch_table_entry(b) > kBatchTableBytes) {
     for (mlf_handle* g : b->film) mlf_destroy(g);
@@ -2405,6 +2414,22 @@ mlf_status mlf_batch_set_launch(mlf_batch* b, int32_t block_w, int32_t seg_h, in
   return MLF_OK;
 }
 
+mlf_status mlf_batch_set_prefetch(mlf_batch* b, int32_t rows) {
+  if (!b) return MLF_EINVAL;
+  if (rows < 0 || rows > 2) return bfail(b, MLF_EINVAL, "prefetch rows must be 0, 1 or 2");
+  if (rows == 2 && !prefetch_ok(b->p0))
+    return bfail(b, MLF_EINVAL, "two rows ahead needs D2Q9 films with tau = 1 and non-FP64 storage");
+  b->ahead = rows == 0 ? 1 : rows;
+  drop_graph(b);
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_get_prefetch(const mlf_batch* b, int32_t* rows) {
+  if (!b || !rows) return MLF_EINVAL;
+  *rows = b->ahead;
+  return MLF_OK;
+}
+
 mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* seg_h, int32_t* persistent) {
   if (!b) return MLF_EINVAL;
   if (block_w) *block_w = b->block_w;
@@ -2424,24 +2449,27 @@ mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int3
     return MLF_OK;
   }
   drop_graph(b);
-  const int keep_w = b->block_w, keep_h = b->seg_h, keep_p = b->persistent;
+  const int keep_w = b->block_w, keep_h = b->seg_h, keep_p = b->persistent, keep_a = b->ahead;
   struct Cand {
-    int w, h, p;
+    int w, h, p, a;
   };
   std::vector<Cand> cand;
-  for (int w : {64, 128, 192, 256})
-    for (int h : {2, 4, 6, 8, 12, 16, 24, 32, 64})
-      for (int pp : {0, 1})
-        if (batch_items(b, w, h) * (long long)sizeof(int2) <= (long long)kBatchItemBytes) cand.push_back({w, h, pp});
+  for (int a = 1; a <= (prefetch_ok(b->p0) ? 2 : 1); ++a)
+    for (int w : {64, 128, 192, 256})
+      for (int h : {2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96})
+        for (int pp : {0, 1})
+          if (batch_items(b, w, h) * (long long)sizeof(int2) <= (long long)kBatchItemBytes)
+            cand.push_back({w, h, pp, a});
   hipEvent_t e0, e1;
   BHIPCHK(hipEventCreate(&e0));
   BHIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  Cand pick{keep_w, keep_h, keep_p};
+  Cand pick{keep_w, keep_h, keep_p, keep_a};
   for (const Cand& c : cand) {
     b->block_w = c.w;
     b->seg_h = c.h;
     b->persistent = c.p;
+    b->ahead = c.a;
     if ((st = upload_table(b)) != MLF_OK) break;
     // current -> other buffer, never swapped: the state is left unchanged
     if ((st = bhip(b, launch_batch(b, b->cur), "autotune launch")) != MLF_OK) break;
@@ -2463,10 +2491,12 @@ mlf_status mlf_batch_autotune(mlf_batch* b, int32_t reps, int32_t* block_w, int3
     b->block_w = pick.w;
     b->seg_h = pick.h;
     b->persistent = pick.p;
+    b->ahead = pick.a;
   } else {
     b->block_w = keep_w;
     b->seg_h = keep_h;
     b->persistent = keep_p;
+    b->ahead = keep_a;
   }
   b->table_dirty = true;
   mlf_status up = upload_table(b);

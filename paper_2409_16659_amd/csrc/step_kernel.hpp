@@ -872,8 +872,8 @@ struct BatchFilm {
 // gridDim.x < n_items the workgroups are persistent and take items
 // w = r * gridDim.x + tile_of_block(blockIdx.x, gridDim.x), r = 0, 1, ...;
 // either way consecutive items run on one XCD.  `flip` selects the source
-// buffer (0: a -> b, 1: b -> a).
-template <typename R, typename S, typename C, bool TAU1, int EA, int EB>
+// buffer (0: a -> b, 1: b -> a); AHEAD rows in flight as in step_tile.
+template <typename R, typename S, typename C, bool TAU1, int EA, int EB, int AHEAD>
 __global__ void __launch_bounds__(256)
 batch_kernel(const BatchFilm<C>* __restrict__ films, const int2* __restrict__ items, int n_items,
              unsigned char* __restrict__ buf_a, unsigned char* __restrict__ buf_b, int flip) {
@@ -884,10 +884,10 @@ batch_kernel(const BatchFilm<C>* __restrict__ films, const int2* __restrict__ it
     const unsigned char* src = (flip ? buf_b : buf_a) + bf.offset;
     unsigned char* dst = (flip ? buf_a : buf_b) + bf.offset;
     switch (bf.nl) {
-      case 1: step_tile<R, S, C, 1, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
-      case 2: step_tile<R, S, C, 2, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
-      case 3: step_tile<R, S, C, 3, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
-      default: step_tile<R, S, C, 4, TAU1, EA, EB>(src, dst, bf.kc, item.y); break;
+      case 1: step_tile<R, S, C, 1, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
+      case 2: step_tile<R, S, C, 2, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
+      case 3: step_tile<R, S, C, 3, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
+      default: step_tile<R, S, C, 4, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
     }
     __syncthreads();  // LDS rings are reused by the next item
   }

@@ -120,6 +120,8 @@ def load_library():
                                              C.POINTER(C.c_void_p)]),
         "mlf_batch_read_device_all": (st, [H, C.POINTER(C.c_void_p)]),
         "mlf_batch_set_launch": (st, [H, C.c_int32, C.c_int32, C.c_int32]),
+        "mlf_batch_set_prefetch": (st, [H, C.c_int32]),
+        "mlf_batch_get_prefetch": (st, [H, C.POINTER(C.c_int32)]),
         "mlf_batch_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_batch_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
@@ -651,6 +653,14 @@ class Batch:
     def set_launch(self, block_w=0, seg_h=0, persistent=0):
         self._check(self.lib.mlf_batch_set_launch(self.h, int(block_w), int(seg_h), int(persistent)),
                     "mlf_batch_set_launch")
+
+    def set_prefetch(self, rows=0):
+        self._check(self.lib.mlf_batch_set_prefetch(self.h, int(rows)), "mlf_batch_set_prefetch")
+
+    def get_prefetch(self) -> int:
+        v = C.c_int32()
+        self._check(self.lib.mlf_batch_get_prefetch(self.h, C.byref(v)), "mlf_batch_get_prefetch")
+        return v.value
 
     def get_launch(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

@@ -82,6 +82,30 @@ def test_batch_matches_single_films(mlf, prec, persistent):
         assert np.array_equal(uxb, uxs) and np.array_equal(uyb, uys), i
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16mix"])
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_batch_two_rows_ahead_matches_single_films(mlf, prec, persistent):
+    """Two rows in flight in the batch kernel (tall segments, where it
+    pays) give every film the populations of its single-film run with one
+    row in flight."""
+    films = scan(8, seed=11)
+    launch = (192, 24)
+    b = mlf.Batch([f for f, _ in films], prec)
+    b.set_launch(*launch, persistent)
+    b.set_prefetch(2)
+    assert b.get_prefetch() == 2
+    for i, (_, h0) in enumerate(films):
+        b.init(i, h0)
+    steps = 21
+    b.step(steps)
+    say(f"batch {prec} persistent={persistent} two rows ahead: {len(films)} films")
+    for i, (film, h0) in enumerate(films):
+        hb, uxb, uyb = b.read(i)
+        hs, uxs, uys = single(mlf, film, h0, prec, launch, steps)
+        assert np.array_equal(hb, hs), i
+        assert np.array_equal(uxb, uxs) and np.array_equal(uyb, uys), i
+
+
 def test_batch_fp64_against_oracle(mlf, oracle_mod):
     films = scan(3, seed=7, side_max=96)
     # one film with slip lengths next to no-slip films
@@ -152,8 +176,9 @@ def test_batch_autotune_keeps_state(mlf):
     a.step(4)
     before = [a.read(i)[0] for i in range(len(films))]
     bw, sh, pers = a.autotune(reps=1)
-    say(f"   batch autotune: {bw}x{sh} persistent={pers}")
+    say(f"   batch autotune: {bw}x{sh} persistent={pers} rows ahead {a.get_prefetch()}")
     assert (bw, sh, pers) == a.get_launch()
+    assert a.get_prefetch() in (1, 2)
     assert a.steps_done == 4
     for i in range(len(films)):
         assert np.array_equal(a.read(i)[0], before[i])
