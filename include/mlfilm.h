@@ -79,10 +79,12 @@ typedef enum {
 /* Lattice.  D1Q3 (velocities 0, +1, -1; 3-point stencils) is the pseudo-1D
  * form of the scheme: it needs ny == 1 and F64 or F32 storage
  * (EUNSUPPORTED otherwise) and stores three planes (rest, +x, -x).  In
- * exact arithmetic it equals D2Q9 on a film one row high.  A D1Q3 film whose
- * state fits one workgroup's LDS (5 N nx values of the storage type within
- * 64 KiB, nx <= 1024) runs many steps per kernel launch with the film held
- * on chip; larger ones take one launch per step. */
+ * exact arithmetic it equals D2Q9 on a film one row high.  D1Q3 films run
+ * many steps per kernel launch with the film held on chip: up to 128 nodes
+ * in one workgroup; longer ones (any length) in tiles of 32 nodes, one
+ * workgroup each, that also hold 48 nodes on either side and run 16 steps
+ * per launch.  In a batch each D1Q3 film must fit one workgroup's LDS
+ * (5 N nx values of the storage type within 64 KiB, nx <= 1024). */
 typedef enum { MLF_D2Q9 = 0, MLF_D1Q3 = 1 } mlf_lattice;
 
 typedef struct mlf_params {

@@ -17,7 +17,7 @@
 // when a population is read), so a post-collision value is written back to
 // its own column.
 //
-// Two kernels:
+// Kernels:
 //  * d1q3_resident: one workgroup per film runs many steps per launch with
 //    the whole film in LDS (populations, interface deviations, pressures):
 //    three barriers per step and no global traffic between the first load
@@ -26,9 +26,9 @@
 //  * d1q3_resident_batch: the same for many films at once, one workgroup
 //    per film (the droplet sweeps of the paper's Sec. IV.B are batches of
 //    such strips).
-//  * d1q3_step: one step per launch for films too large for one
-//    workgroup's LDS; a workgroup of 256 lanes covers 252 nodes plus two
-//    halo nodes on each side.
+//  * d1q3_tiled: a film longer than one tile split over several
+//    workgroups, each holding its tile plus the halo that its steps per
+//    launch need, so that each wave has a SIMD to itself.
 #pragma once
 
 #include "step_kernel.hpp"
@@ -210,7 +210,6 @@ __device__ inline void d1_scatter(C* d, long long plane, int x, const C (&fo)[NL
 
 constexpr int kD1Threads = 512;      // largest resident workgroup (256 VGPRs a lane)
 constexpr int kD1MaxPerThread = 2;   // nodes per lane: nx <= 1024
-constexpr int kD1StepThreads = 256;  // one-step kernel: 252 nodes + 2 + 2 halo
 
 // Bytes of LDS the resident kernel needs for a film of nx nodes.
 template <typename C>
@@ -319,54 +318,114 @@ __global__ void __launch_bounds__(kD1Threads) d1q3_resident_batch(const BatchFil
   }
 }
 
-// One step for a film of any length: workgroup b covers nodes
-// [252 b, 252 b + 252) and lanes 0..255 map to nodes 252 b - 2 + lane.
+// ---- the resident step on a film split over several workgroups ----------
+//
+// A node's populations after a step depend on those of the nodes up to
+// kD1Reach columns away before it (streaming into the moments, the
+// neighbours' interface deviations in the pressure, the neighbours'
+// pressures in the force).  A workgroup that holds its `core` nodes plus
+// kD1Reach * s nodes on each side runs s steps alone: what the cut edges of
+// its tile compute wrongly moves inwards kD1Reach nodes a step and never
+// reaches the core.  One node per lane, each workgroup on its own CU; the
+// halo nodes are computed redundantly.  Per-node arithmetic is that of
+// d1_resident_run: results are bit-identical to it.
+constexpr int kD1Reach = 3;
+constexpr int kD1TileThreads = 128;  // lanes = tile nodes
+constexpr int kD1TileSteps = 16;     // steps per launch
+constexpr int kD1TileCore = kD1TileThreads - 2 * kD1Reach * kD1TileSteps;
+static_assert(kD1TileCore > 0, "tile too narrow for its halo");
+
+template <typename C>
+__host__ __device__ constexpr size_t d1_tile_lds(int nl) {
+  return (size_t)5 * nl * kD1TileThreads * sizeof(C);
+}
+
+// `steps` (1..kD1TileSteps) steps of a film whose nodes are split into tiles
+// of `core` nodes (the last one may hold fewer), one workgroup of
+// kD1TileThreads lanes each; src -> dst in the layout of d1_resident_run.
+// The guard checks each node in the tile that owns it.
 template <typename C, int NL, bool TAU1, int EA, int EB>
-__global__ void __launch_bounds__(kD1StepThreads) d1q3_step(const C* __restrict__ src, C* __restrict__ dst,
-                                                            StepConsts<C> kc) {
-  constexpr int kOut = kD1StepThreads - 4;
-  __shared__ C sz[kD1StepThreads][NL];
-  __shared__ C sp[kD1StepThreads][NL];
+__global__ void __launch_bounds__(kD1TileThreads) d1q3_tiled(const C* __restrict__ src, C* __restrict__ dst,
+                                                             StepConsts<C> kc, int steps, int core) {
+  extern __shared__ unsigned char smem_raw[];
   const int nx = kc.nx;
-  const int lane = threadIdx.x;
-  const int x0 = blockIdx.x * kOut;
-  const int x = wrap(x0 - 2 + lane, nx);
+  const int halo = kD1Reach * steps;
+  const int w = core + 2 * halo;  // tile nodes, <= kD1TileThreads (host-checked)
+  const int x0 = blockIdx.x * core;
+  const int ncore = min(core, nx - x0);
+  C* sf = reinterpret_cast<C*>(smem_raw);  // [3][w][NL]
+  C* sz = sf + 3 * w * NL;                 // [w][NL]
+  C* sp = sz + w * NL;                     // [w][NL]
   const long long plane = kc.plane;
+  const int l = threadIdx.x;  // the lane's tile node
+  const bool live = l < w;
+  const bool owned = l >= halo && l < halo + ncore;
+  for (int e = l; e < w * NL; e += kD1TileThreads) {
+    const int c = e / NL, i = e - c * NL;
+    int g = (x0 - halo + c) % nx;  // periodic; x0 - halo + c >= -halo
+    if (g < 0) g += nx;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sf[(k * w + c) * NL + i] = src[k * plane * NL + (long long)g * NL + i];
+  }
+  __syncthreads();
+  const int lm = max(l - 1, 0), lp = min(l + 1, w - 1);  // clamped at the cut edges
+  int bad = 0;
   C f[NL][3];
-  d1_gather<C, NL>(src, plane, x, nx, f);
-  {
-    C dh[NL], q[NL], dz[NL];
-    d1_moments<C, NL>(f, dh, q);
-    d1_interfaces<C, NL>(dh, dz);
+  for (int s = 0; s < steps; ++s) {
+    if (live) {
+      // pre-collision populations: plane k keeps at node x the population
+      // of node x + c_k
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sz[lane][i] = dz[i];
-  }
-  __syncthreads();
-  if (lane >= 1 && lane < kD1StepThreads - 1) {
-    C zm[NL], zc[NL], zp[NL], p[NL];
+      for (int i = 0; i < NL; ++i) {
+        f[i][0] = sf[(0 * w + l) * NL + i];
+        f[i][1] = sf[(1 * w + lm) * NL + i];
+        f[i][2] = sf[(2 * w + lp) * NL + i];
+      }
+      C dh[NL], q[NL], dz[NL];
+      d1_moments<C, NL>(f, dh, q);
+      d1_interfaces<C, NL>(dh, dz);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      zm[i] = sz[lane - 1][i];
-      zc[i] = sz[lane][i];
-      zp[i] = sz[lane + 1][i];
+      for (int i = 0; i < NL; ++i) sz[l * NL + i] = dz[i];
     }
-    d1_pressure<C, NL, EA, EB>(kc, zm, zc, zp, p);
+    __syncthreads();
+    if (live) {
+      C zm[NL], zc[NL], zp[NL], p[NL];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sp[lane][i] = p[i];
-  }
-  __syncthreads();
-  const int xo = x0 - 2 + lane;  // unwrapped node of this lane
-  if (lane >= 2 && lane < kD1StepThreads - 2 && xo < nx) {
-    C pm[NL], pp[NL], fo[NL][3];
+      for (int i = 0; i < NL; ++i) {
+        zm[i] = sz[lm * NL + i];
+        zc[i] = sz[l * NL + i];
+        zp[i] = sz[lp * NL + i];
+      }
+      d1_pressure<C, NL, EA, EB>(kc, zm, zc, zp, p);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      pm[i] = sp[lane - 1][i];
-      pp[i] = sp[lane + 1][i];
+      for (int i = 0; i < NL; ++i) sp[l * NL + i] = p[i];
     }
-    const int bad = d1_collide<C, NL, TAU1>(kc, f, pm, pp, fo);
-    if (bad) kc.flag[0] = bad;
-    d1_scatter<C, NL>(dst, plane, xo, fo);
+    __syncthreads();
+    if (live) {
+      C pm[NL], pp[NL], fo[NL][3];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        pm[i] = sp[lm * NL + i];
+        pp[i] = sp[lp * NL + i];
+      }
+      const int b = d1_collide<C, NL, TAU1>(kc, f, pm, pp, fo);
+      if (owned) bad = b > bad ? b : bad;
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        sf[(0 * w + l) * NL + i] = fo[i][0];
+        sf[(1 * w + l) * NL + i] = fo[i][1];
+        sf[(2 * w + l) * NL + i] = fo[i][2];
+      }
+    }
+    __syncthreads();
   }
+  for (int e = l; e < ncore * NL; e += kD1TileThreads) {
+    const int c = e / NL, i = e - c * NL;
+    const long long g = x0 + c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dst[k * plane * NL + g * NL + i] = sf[(k * w + halo + c) * NL + i];
+  }
+  if (bad) kc.flag[0] = bad;
 }
 
 }  // namespace mlf

@@ -804,28 +804,30 @@ bool d1_resident(const mlf_params& p) {
 
 int d1_threads(int nx) { return std::min(mlf::kD1Threads, std::max(64, (nx + 63) / 64 * 64)); }
 
+// Single D1Q3 films longer than one tile run tiled over several workgroups
+// (kD1TileSteps steps per launch); shorter ones are held by one workgroup of
+// at most two waves.
+bool d1_tiled(const mlf_params& p) { return p.lattice == MLF_D1Q3 && p.nx > mlf::kD1TileThreads; }
+
 template <typename C, int NL, bool T1, int EA, int EB>
 hipError_t d1_launch_nl(mlf_handle* h, int steps) {
   mlf::StepConsts<C> kc = make_consts<C>(h);
   const mlf_params& p = h->p;
-  if (d1_resident(p)) {
-    const C* src = static_cast<const C*>(h->pop[h->cur]);
-    C* dst = static_cast<C*>(h->pop[h->cur ^ 1]);
-    const size_t lds = mlf::d1_resident_lds<C>(p.nx, NL);
-    hipLaunchKernelGGL((mlf::d1q3_resident<C, NL, T1, EA, EB>), dim3(1), dim3((unsigned)d1_threads(p.nx)), lds,
-                       h->stream, src, dst, kc, steps);
+  const C* src = static_cast<const C*>(h->pop[h->cur]);
+  C* dst = static_cast<C*>(h->pop[h->cur ^ 1]);
+  if (d1_tiled(p)) {
+    if (steps < 1 || steps > mlf::kD1TileSteps) return hipErrorInvalidValue;
+    const int tiles = (p.nx + mlf::kD1TileCore - 1) / mlf::kD1TileCore;
+    hipLaunchKernelGGL((mlf::d1q3_tiled<C, NL, T1, EA, EB>), dim3((unsigned)tiles), dim3(mlf::kD1TileThreads),
+                       mlf::d1_tile_lds<C>(NL), h->stream, src, dst, kc, steps, mlf::kD1TileCore);
     h->cur ^= 1;
     return hipGetLastError();
   }
-  const unsigned grid = (unsigned)((p.nx + mlf::kD1StepThreads - 5) / (mlf::kD1StepThreads - 4));
-  for (int s = 0; s < steps; ++s) {
-    hipLaunchKernelGGL((mlf::d1q3_step<C, NL, T1, EA, EB>), dim3(grid), dim3(mlf::kD1StepThreads), 0, h->stream,
-                       static_cast<const C*>(h->pop[h->cur]), static_cast<C*>(h->pop[h->cur ^ 1]), kc);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    h->cur ^= 1;
-  }
-  return hipSuccess;
+  const size_t lds = mlf::d1_resident_lds<C>(p.nx, NL);
+  hipLaunchKernelGGL((mlf::d1q3_resident<C, NL, T1, EA, EB>), dim3(1), dim3((unsigned)d1_threads(p.nx)), lds,
+                     h->stream, src, dst, kc, steps);
+  h->cur ^= 1;
+  return hipGetLastError();
 }
 
 template <typename C, bool T1, int EA, int EB>
@@ -838,7 +840,8 @@ hipError_t d1_launch_t(mlf_handle* h, int steps) {
   }
 }
 
-// Advances a D1Q3 film by `steps` (1..kD1MaxStepsPerLaunch); flips h->cur.
+// Advances a D1Q3 film by `steps` (1..kD1MaxStepsPerLaunch; 1..kD1TileSteps
+// when tiled); flips h->cur.
 template <typename C>
 hipError_t d1_advance_c(mlf_handle* h, int steps) {
   const bool t1 = h->p.tau == 1.0;
@@ -1444,7 +1447,9 @@ mlf_status mlf_step(mlf_handle* h, int64_t nsteps) {
   if (h->p.lattice == MLF_D1Q3 || row) {
     int64_t left = nsteps, since = 0;
     while (left > 0) {
-      int64_t chunk = std::min<int64_t>(left, row && row_tiled(h->p) ? mlf::kRowTileSteps : kD1MaxStepsPerLaunch);
+      const int64_t per_launch = row ? (row_tiled(h->p) ? mlf::kRowTileSteps : kD1MaxStepsPerLaunch)
+                                     : (d1_tiled(h->p) ? mlf::kD1TileSteps : kD1MaxStepsPerLaunch);
+      int64_t chunk = std::min<int64_t>(left, per_launch);
       if (every > 0) chunk = std::min<int64_t>(chunk, every - since);
       HIPCHK(row ? row_advance(h, (int)chunk) : d1_advance(h, (int)chunk));
       left -= chunk;

@@ -1,6 +1,7 @@
 """D1Q3 films (pseudo-1D, ny == 1) on the GPU against the oracle's D1Q3
-path: the resident kernel (whole film in LDS, many steps per launch) and
-the one-step kernel for films too long for one workgroup.
+path: the resident kernels, which hold the film in LDS for many steps per
+launch (one workgroup for up to 128 nodes; tiles of 32 nodes with 48-node
+halos, 16 steps per launch, for longer films), and batches of strips.
 
 Gates as for D2Q9: FP64 e_h <= 1e-12, e_U <= 1e-10, FP32 e_h <= 1e-5,
 e_U <= 1e-4; populations against the oracle's; results independent of how
@@ -76,7 +77,7 @@ def check(g, o, tol_h, tol_u):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4])
-@pytest.mark.parametrize("nx", [1, 2, 3, 7, 64, 333, 700])
+@pytest.mark.parametrize("nx", [1, 2, 3, 7, 64, 128, 129, 333, 700])
 def test_fp64_against_oracle(mlf, oracle_mod, n, nx):
     film, h0 = strip(n, nx, seed=10 * n + nx)
     g, o = pair(mlf, oracle_mod, film, h0, 300)
@@ -87,9 +88,8 @@ def test_fp64_against_oracle(mlf, oracle_mod, n, nx):
 
 
 @pytest.mark.parametrize("n", [2, 4])
-def test_fp64_long_strip_one_step_kernel(mlf, oracle_mod, n):
-    """Longer than one workgroup holds: one launch per step, 252 nodes per
-    workgroup with a ragged last one."""
+def test_fp64_long_strip_tiled(mlf, oracle_mod, n):
+    """A long strip: 94 tiles of 32 nodes with a ragged last one (25)."""
     film, h0 = strip(n, 3001, seed=5 + n)
     g, o = pair(mlf, oracle_mod, film, h0, 120)
     check(g, o, 1e-12, 1e-10)
@@ -180,6 +180,26 @@ def test_guard_and_unsupported(mlf):
     with pytest.raises(mlf.MlfError) as e:
         g.capture(8)
     assert e.value.status == "EUNSUPPORTED"
+
+
+@pytest.mark.parametrize("col", [0, 31, 32, 399])
+def test_tiled_guard_at_tile_edges(mlf, col):
+    """A non-positive height at the first or last node of a tile, or at the
+    strip's wrap-around edge, trips the guard of the tiled kernel; the
+    healthy strip runs on without a false alarm from the halos."""
+    film, h0 = strip(2, 400, seed=8)
+    g = mlf.Film(film, "f64", lattice="d1q3", check_every=20)
+    g.init(h0)
+    g.step(20)
+    f = g.populations()
+    f[0, 0, 0, col] = -5.0
+    g.set_populations(f)
+    with pytest.raises(mlf.MlfError) as e:
+        g.step(20)
+    assert e.value.status in ("ENONPOSITIVE", "ENONFINITE")
+    ok = mlf.Film(film, "f64", lattice="d1q3", check_every=20)
+    ok.init(h0)
+    ok.step(200)
 
 
 BATCH_STRIPS = [(1, 64), (2, 333), (3, 500), (4, 96), (2, 5), (4, 400), (3, 1)]
