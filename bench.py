@@ -280,6 +280,12 @@ def bench_batch(args):
     single-film kernel (each film all its steps, best case for reuse; in
     the batch's launch shape and in the films' default shapes, the faster
     counting)."""
+    print(json.dumps(batch_point(args, args.batch_steps, max(2, args.warmup // 2 * 2))), flush=True)
+
+
+def batch_point(args, steps, warm):
+    """The batched scan's bench line (see bench_batch) for `steps` timed
+    steps after `warm` warm-up steps."""
     import numpy as np
     import torch
 
@@ -288,7 +294,6 @@ def bench_batch(args):
     assert torch.cuda.is_available(), "bench needs a GPU"
     films = inputs.batch_scan(count=args.batch_films, seed=3)
     n_lu = sum(f["n_layers"] * f["nx"] * f["ny"] for f, _ in films)
-    steps, warm = args.batch_steps, max(2, args.warmup // 2 * 2)
     b = mlfilm.Batch([f for f, _ in films], "f32")
     for i, (_, h0) in enumerate(films):
         b.init(i, h0)
@@ -354,7 +359,7 @@ def bench_batch(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_lu": 72,
                      "kernel_ms": kern_ms},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_surrogate(args):
@@ -486,6 +491,31 @@ def bench_conv_kernels(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_block(args):
+    """The batched scan (256 uneven films, FP32, one launch per step) in
+    the default line: LU/s, its speedup over the films stepped one launch
+    each, and its HBM fraction."""
+    b = batch_point(args, args.extra_batch_steps, 20)
+    r = b["roofline"]
+    return {"workload": b["config"]["workload"], "value": b["value"], "unit": "LU/s", "steps": b["steps"],
+            "ms_per_step": b["ms_per_step"], "launch": b["config"]["launch"],
+            "plain_ms_per_step": b["plain"]["ms_per_step"], "plain_launch": b["plain"]["launch"],
+            "speedup_vs_plain": b["speedup_vs_plain"],
+            "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": r["peak"], "unit": "GB/s",
+                         "frac": r["frac"], "kernel_ms": r["kernel_ms"]}}
+
+
+def pseudo1d_block(args):
+    """The two-layer 512 x 1 film (FP64) in the default line: microseconds
+    per step on D2Q9 and on D1Q3, the film held in LDS (no HBM roofline)."""
+    out = {"workload": "film2_pseudo1d_512", "storage": "f64", "steps": 20000}
+    for lat in ("d2q9", "d1q3"):
+        pt = film_point("film2_pseudo1d_512", "f64", args, 20000, 2000, lat)
+        out[f"{lat}_us_per_step"] = pt["wall"] * 1e6 / 20000
+        out[f"{lat}_kernel_us_per_step"] = pt["kern_ms"] * 1e3
+    return out
+
+
 def film_point(workload, prec, args, steps, warmup, lattice="d2q9"):
     """Time `steps` steps of one workload after `warmup` steps: LU/s over
     the wall clock, and the step kernel's average launch duration from HIP
@@ -583,6 +613,10 @@ def main():
                          "(graph-captured, autotuned) against the same films stepped back to back "
                          "through the single-film kernel")
     ap.add_argument("--batch-films", type=int, default=256)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default line without its `batched` (256-film scan, --extra-batch-steps steps) and "
+                         "`pseudo1d` (512 x 1 two-layer film, D2Q9 and D1Q3) blocks")
+    ap.add_argument("--extra-batch-steps", type=int, default=300)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--graph-steps", type=int, default=100, help="steps per captured graph (even; 0: none)")
     ap.add_argument("--surrogate", action="store_true",
@@ -689,6 +723,9 @@ def main():
             out["roofline_hbm"] = roofline_block(ph, hp, hprec, hws, hcopy)
             out["roofline_hbm"]["lu_per_s"] = ph["n_lu"] * args.hbm_steps / ph["wall"]
             out["roofline_hbm"]["steps"] = args.hbm_steps
+    if not args.no_extras and args.workload == "film3_2d_1024" and args.lattice == "d2q9":
+        out["batched"] = batched_block(args)
+        out["pseudo1d"] = pseudo1d_block(args)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(film, pt["h0"], args.cpu_seconds, args.lattice,
                                            args.cpu_single_seconds)
