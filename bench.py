@@ -649,7 +649,7 @@ def main():
         return ingest_profile(args)
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
