@@ -66,7 +66,8 @@ typedef enum {
  * In the all-16-bit formats a height change per step below half an ulp of
  * the stored deviation is lost (slow dynamics stall); the MIX formats keep
  * the rest population, which carries the height, in FP32 (40 instead of 36
- * bytes per layer-node update). */
+ * bytes per layer-node update), and mlf_set_rounding can round the rest
+ * population stochastically instead. */
 typedef enum {
   MLF_F64 = 0,
   MLF_F32 = 1,
@@ -227,6 +228,23 @@ mlf_status mlf_get_launch(const mlf_handle* h, int32_t* block_w, int32_t* seg_h)
  * mlf_get_prefetch writes the current value (rows must not be NULL). */
 mlf_status mlf_set_prefetch(mlf_handle* h, int32_t rows);
 mlf_status mlf_get_prefetch(const mlf_handle* h, int32_t* rows);
+
+/* Rounding of the stored rest population (the population that carries a
+ * layer's height change).  MLF_ROUND_NEAREST (default): round to nearest.
+ * MLF_ROUND_STOCHASTIC_REST (D2Q9 films with MLF_F16 or MLF_BF16 storage
+ * only, else MLF_EINVAL): each node's rest population of each layer is
+ * rounded to the representable value below or above it, the upper one with
+ * probability equal to its distance from the lower one over their gap, so
+ * that height changes below half an ulp accumulate on average instead of
+ * being lost.  The draws are a counter-based hash of (node, layer, step
+ * count): results are reproducible and independent of the launch shape,
+ * but differ from round-to-nearest ones.  A film with stochastic rounding
+ * cannot be captured into a graph (MLF_EUNSUPPORTED from mlf_capture).
+ * Drops a captured graph.  mlf_get_rounding writes the current mode (mode
+ * must not be NULL). */
+typedef enum { MLF_ROUND_NEAREST = 0, MLF_ROUND_STOCHASTIC_REST = 1 } mlf_rounding;
+mlf_status mlf_set_rounding(mlf_handle* h, int32_t mode);
+mlf_status mlf_get_rounding(const mlf_handle* h, int32_t* mode);
 
 /* Autotuner: times candidate launch shapes on the current state and keeps
  * the fastest (written to block_w / seg_h if not NULL).  Each candidate is

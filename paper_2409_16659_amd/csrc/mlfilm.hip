@@ -525,6 +525,7 @@ struct mlf_handle {
   int64_t steps;
   int block_w, seg_h;
   int ahead;  // rows of populations in flight in the step kernel (1 or 2)
+  int sr;     // stochastic rounding of the rest plane (16-bit storage)
   bool initialised;
   hipGraphExec_t graph;  // captured step loop (constants baked in), or null
   int graph_steps, graph_parity;
@@ -695,6 +696,8 @@ mlf::StepConsts<C> make_consts(const mlf_handle* h) {
   k.ea = p.exp_a;
   k.eb = p.exp_b;
   k.flag = flag_ptr(const_cast<mlf_handle*>(h));
+  k.sr_on = h->sr;
+  k.sr_step = (unsigned)h->steps;
   return k;
 }
 
@@ -1195,6 +1198,7 @@ mlf_status mlf_create(const mlf_params* p, void* pop_a, void* pop_b, void* scrat
   h->graph_parity = 0;
   default_launch(p, &h->block_w, &h->seg_h);
   h->ahead = 1;
+  h->sr = 0;
   *out = h;
   return MLF_OK;
 }
@@ -1261,6 +1265,24 @@ mlf_status mlf_set_prefetch(mlf_handle* h, int32_t rows) {
 mlf_status mlf_get_prefetch(const mlf_handle* h, int32_t* rows) {
   if (!h || !rows) return MLF_EINVAL;
   *rows = h->ahead;
+  return MLF_OK;
+}
+
+mlf_status mlf_set_rounding(mlf_handle* h, int32_t mode) {
+  if (!h) return MLF_EINVAL;
+  if (mode != MLF_ROUND_NEAREST && mode != MLF_ROUND_STOCHASTIC_REST)
+    return fail(h, MLF_EINVAL, "unknown rounding mode");
+  if (mode == MLF_ROUND_STOCHASTIC_REST &&
+      !(h->p.lattice == MLF_D2Q9 && (h->p.precision == MLF_F16 || h->p.precision == MLF_BF16)))
+    return fail(h, MLF_EINVAL, "stochastic rounding needs a D2Q9 film with MLF_F16 or MLF_BF16 storage");
+  drop_single_graph(h);
+  h->sr = mode == MLF_ROUND_STOCHASTIC_REST;
+  return MLF_OK;
+}
+
+mlf_status mlf_get_rounding(const mlf_handle* h, int32_t* mode) {
+  if (!h || !mode) return MLF_EINVAL;
+  *mode = h->sr ? MLF_ROUND_STOCHASTIC_REST : MLF_ROUND_NEAREST;
   return MLF_OK;
 }
 
@@ -1494,6 +1516,8 @@ mlf_status mlf_capture(mlf_handle* h, int32_t steps) {
   if (!h->initialised) return fail(h, MLF_EINVAL, "mlf_capture before mlf_init");
   if (h->p.lattice == MLF_D1Q3)
     return fail(h, MLF_EUNSUPPORTED, "D1Q3 films run many steps per launch; no graph needed");
+  if (h->sr)
+    return fail(h, MLF_EUNSUPPORTED, "stochastic rounding draws on the step count, which a graph would freeze");
   if (!h->stream) return fail(h, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;

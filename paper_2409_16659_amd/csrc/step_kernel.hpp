@@ -96,6 +96,8 @@ struct StepConsts {
   int slip_on;                       // any slip length != 0
   C slip[kMaxLayers];                // slip lengths beta_i
   int* flag;                         // guard flag (0 ok, 1 h<=0, 2 non-finite)
+  int sr_on;                         // stochastic rounding of a 16-bit rest plane
+  unsigned sr_step;                  // step count of this launch (its random draws)
 };
 
 // Storage access through raw buffer descriptors: one descriptor per group of
@@ -173,6 +175,47 @@ __device__ inline float half_bits_to_f32(uint32_t b) {
 __device__ inline uint32_t f32_to_half_bits(float v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
 __device__ inline float bf16_bits_to_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
 __device__ inline uint32_t f32_to_bf16_bits(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+
+// 32-bit integer mixer (C. Wellons' "lowbias32": xorshift-multiply rounds).
+__host__ __device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Uniform draw in [0, 1) (24 bits) for layer `layer` of node `node` at step
+// `step`: a counter-based hash, so the draw depends on where and when it is
+// taken, not on the launch shape.
+__device__ inline float sr_uniform(uint32_t node, int layer, uint32_t step) {
+  const uint32_t h = mix32(mix32(node * 4u + (uint32_t)layer) ^ mix32(step + 0x9e3779b9u));
+  return (float)(h >> 8) * 0x1p-24f;
+}
+
+// Stochastic rounding of v to the 16-bit type T: the representable value
+// just below or just above v, the upper one with probability equal to v's
+// distance from the lower one over their gap, so the rounding error has
+// zero mean.  Values T holds exactly are returned unchanged.
+template <typename T>
+__device__ inline float sr_round(float v, float u) {
+  constexpr bool kHalf = std::is_same_v<T, _Float16>;
+  const uint32_t b = kHalf ? f32_to_half_bits(v) : f32_to_bf16_bits(v);  // nearest
+  const float n = kHalf ? half_bits_to_f32(b) : bf16_bits_to_f32(b);
+  if (!(n != v) || !(v - v == 0.f)) return n;  // exact, or not finite
+  // the neighbour of n on v's side (sign-magnitude bit patterns)
+  const bool neg = (b & 0x8000u) != 0;
+  uint32_t o;
+  if (n < v)
+    o = neg ? (b == 0x8000u ? 0x0001u : b - 1) : b + 1;
+  else
+    o = neg ? b + 1 : (b == 0u ? 0x8001u : b - 1);
+  const float m = kHalf ? half_bits_to_f32(o) : bf16_bits_to_f32(o);
+  const float lo = n < m ? n : m, hi = n < m ? m : n;
+  const float p = (v - lo) / (hi - lo);
+  return u < p ? hi : lo;
+}
 
 // The NL populations of one direction at one node (layers next to each
 // other), converted to the arithmetic type C.
@@ -767,6 +810,17 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
         for (int i = 0; i < NL; ++i)
 #pragma unroll
           for (int k = 0; k < kQ; ++k) fo[i][k] += (C(1) - kc.omega) * fy[i][k];
+      }
+      if constexpr (Elem<R>::kScaled) {
+        // stochastic rounding of the stored rest population: rounded here
+        // in the scaled form the store writes, so that store_row's own
+        // conversion is exact (the scales are powers of two)
+        if (kc.sr_on) {
+          const uint32_t node = (uint32_t)y * (uint32_t)kc.nx + (uint32_t)x;
+#pragma unroll
+          for (int i = 0; i < NL; ++i)
+            fo[i][0] = sr_round<R>(fo[i][0] * kc.scale[i], sr_uniform(node, i, kc.sr_step)) * kc.iscale[i];
+        }
       }
       store_row(st_ok, oS, oC, oN, oR, fo);
     } else if constexpr (AHEAD == 2) {

@@ -96,6 +96,8 @@ def load_library():
         "mlf_set_launch": (st, [H, C.c_int32, C.c_int32]),
         "mlf_set_prefetch": (st, [H, C.c_int32]),
         "mlf_get_prefetch": (st, [H, C.POINTER(C.c_int32)]),
+        "mlf_set_rounding": (st, [H, C.c_int32]),
+        "mlf_get_rounding": (st, [H, C.POINTER(C.c_int32)]),
         "mlf_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_capture": (st, [H, C.c_int32]),
@@ -447,6 +449,15 @@ class Film:
         v = C.c_int32()
         self._check(self.lib.mlf_get_prefetch(self.h, C.byref(v)), "mlf_get_prefetch")
         return v.value
+
+    def set_rounding(self, stochastic: bool):
+        """Stochastic rounding of the rest population (f16 / bf16 storage)."""
+        self._check(self.lib.mlf_set_rounding(self.h, 1 if stochastic else 0), "mlf_set_rounding")
+
+    def get_rounding(self) -> bool:
+        v = C.c_int32()
+        self._check(self.lib.mlf_get_rounding(self.h, C.byref(v)), "mlf_get_rounding")
+        return v.value == 1
 
     def autotune(self, reps=5):
         """Pick the fastest launch shape on the current state (unchanged)."""

@@ -226,6 +226,26 @@ def test_set_prefetch_validation():
     assert lib.mlf_get_prefetch(None, C.byref(C.c_int32())) != 0
 
 
+def test_set_rounding_validation():
+    """Stochastic rounding of the rest plane is for D2Q9 films with f16 or
+    bf16 storage only; other modes are refused; 0 restores the default."""
+    for prec, ok in [("f16", True), ("bf16", True), ("f16mix", False), ("f32", False), ("f64", False)]:
+        film = inputs.film_params(2, 64, 16, gamma=[0.01] * 2, mu=[0.01] * 2, hstar=0.1)
+        lib, h = _fake_handle(film, prec)
+        try:
+            v = C.c_int32()
+            assert lib.mlf_get_rounding(h, C.byref(v)) == 0 and v.value == 0
+            assert (lib.mlf_set_rounding(h, 1) == 0) == ok, prec
+            lib.mlf_get_rounding(h, C.byref(v))
+            assert v.value == (1 if ok else 0)
+            assert lib.mlf_set_rounding(h, 2) != 0
+            assert lib.mlf_set_rounding(h, 0) == 0
+            lib.mlf_get_rounding(h, C.byref(v))
+            assert v.value == 0
+        finally:
+            lib.mlf_destroy(h)
+
+
 def test_surrogate_sizes_and_validation():
     from oracle import nop
 
