@@ -369,6 +369,17 @@ mlf_status mlf_batch_get_launch(const mlf_batch* b, int32_t* block_w, int32_t* s
 mlf_status mlf_batch_set_prefetch(mlf_batch* b, int32_t rows);
 mlf_status mlf_batch_get_prefetch(const mlf_batch* b, int32_t* rows);
 
+/* Rounding of the stored rest population for every film of the batch, as
+ * mlf_set_rounding for a single film (MLF_ROUND_STOCHASTIC_REST only for
+ * D2Q9 batches with MLF_F16 or MLF_BF16 storage, else MLF_EINVAL).  The
+ * draws use each film's node indices and the batch's step count, so a film
+ * stepped in a batch equals the same film stepped alone from the same step
+ * count, bit for bit.  A batch with stochastic rounding cannot be captured
+ * (MLF_EUNSUPPORTED from mlf_batch_capture).  Drops a captured graph.
+ * mode must not be NULL for the getter. */
+mlf_status mlf_batch_set_rounding(mlf_batch* b, int32_t mode);
+mlf_status mlf_batch_get_rounding(const mlf_batch* b, int32_t* mode);
+
 /* Autotuner over block_w x seg_h x persistent x rows in flight (1, and 2
  * where mlf_batch_set_prefetch allows it), `reps` timed launches each from
  * the current buffer into the other (state unchanged); keeps the fastest

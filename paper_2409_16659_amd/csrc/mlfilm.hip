@@ -1988,7 +1988,7 @@ hipError_t launch_batch_ah(const mlf_batch* b, int flip, int* occ) {
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)b->block_w), lds, b->stream,
                      reinterpret_cast<const mlf::BatchFilm<C>*>(b->scratch + kBatchTableOff),
                      reinterpret_cast<const int2*>(b->scratch + kBatchItemOff), b->n_items, b->pop[0], b->pop[1],
-                     flip);
+                     flip, (uint32_t)b->steps);
   return hipGetLastError();
 }
 
@@ -2303,6 +2303,8 @@ mlf_status mlf_batch_capture(mlf_batch* b, int32_t steps) {
   if (b->p0.lattice == MLF_D1Q3)
     return bfail(b, MLF_EUNSUPPORTED, "D1Q3 batches run many steps per launch; no graph needed");
   if (!b->stream) return bfail(b, MLF_EUNSUPPORTED, "graph capture needs a non-default stream");
+  if (!b->film.empty() && b->film[0]->sr)
+    return bfail(b, MLF_EUNSUPPORTED, "stochastic rounding draws from the step count, which a graph would freeze");
   mlf_status st = batch_ready(b);
   if (st != MLF_OK) return st;
   BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
@@ -2456,6 +2458,25 @@ mlf_status mlf_batch_set_prefetch(mlf_batch* b, int32_t rows) {
 mlf_status mlf_batch_get_prefetch(const mlf_batch* b, int32_t* rows) {
   if (!b || !rows) return MLF_EINVAL;
   *rows = b->ahead;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_set_rounding(mlf_batch* b, int32_t mode) {
+  if (!b) return MLF_EINVAL;
+  if (mode != MLF_ROUND_NEAREST && mode != MLF_ROUND_STOCHASTIC_REST)
+    return bfail(b, MLF_EINVAL, "unknown rounding mode");
+  if (mode == MLF_ROUND_STOCHASTIC_REST &&
+      !(b->p0.lattice == MLF_D2Q9 && (b->p0.precision == MLF_F16 || b->p0.precision == MLF_BF16)))
+    return bfail(b, MLF_EINVAL, "stochastic rounding needs D2Q9 films with MLF_F16 or MLF_BF16 storage");
+  drop_graph(b);
+  for (mlf_handle* h : b->film) h->sr = mode == MLF_ROUND_STOCHASTIC_REST;
+  b->table_dirty = true;
+  return MLF_OK;
+}
+
+mlf_status mlf_batch_get_rounding(const mlf_batch* b, int32_t* mode) {
+  if (!b || !mode) return MLF_EINVAL;
+  *mode = (!b->film.empty() && b->film[0]->sr) ? MLF_ROUND_STOCHASTIC_REST : MLF_ROUND_NEAREST;
   return MLF_OK;
 }
 

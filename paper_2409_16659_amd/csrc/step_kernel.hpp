@@ -573,9 +573,11 @@ __device__ inline void node_collide(const StepConsts<C>& kc, const C (&dh2)[NL],
 // segment's rows.  `tile` is uniform and < kc.nstrip * kc.nseg.  AHEAD rows
 // of populations are in flight while a row is processed (2 only with
 // tau = 1); the arithmetic, and so every result, is the same for both.
+// `sr_step` is the film's step count, the counter of its stochastic-rounding
+// draws (read only when kc.sr_on).
 template <typename R, typename S, typename C, int NL, bool TAU1, int EA, int EB, int AHEAD = 1>
 __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-                                 const StepConsts<C>& kc, int tile) {
+                                 const StepConsts<C>& kc, int tile, uint32_t sr_step) {
   static_assert(AHEAD == 1 || (AHEAD == 2 && TAU1), "two rows ahead needs tau = 1");
   const int W = blockDim.x;
   const int tid = threadIdx.x;
@@ -819,7 +821,7 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
           const uint32_t node = (uint32_t)y * (uint32_t)kc.nx + (uint32_t)x;
 #pragma unroll
           for (int i = 0; i < NL; ++i)
-            fo[i][0] = sr_round<R>(fo[i][0] * kc.scale[i], sr_uniform(node, i, kc.sr_step)) * kc.iscale[i];
+            fo[i][0] = sr_round<R>(fo[i][0] * kc.scale[i], sr_uniform(node, i, sr_step)) * kc.iscale[i];
         }
       }
       store_row(st_ok, oS, oC, oN, oR, fo);
@@ -906,7 +908,7 @@ __global__ void __launch_bounds__((step_max_lanes<C, NL>()))
 step_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, const StepConsts<C> kc) {
   const int tile = tile_of_block(blockIdx.x, gridDim.x);
   if (tile >= kc.nstrip * kc.nseg) return;  // padding workgroup (uniform)
-  step_tile<R, S, C, NL, TAU1, EA, EB, AHEAD>(src, dst, kc, tile);
+  step_tile<R, S, C, NL, TAU1, EA, EB, AHEAD>(src, dst, kc, tile, kc.sr_step);
 }
 
 // ---- batches of independent films -----------------------------------------
@@ -926,11 +928,13 @@ struct BatchFilm {
 // gridDim.x < n_items the workgroups are persistent and take items
 // w = r * gridDim.x + tile_of_block(blockIdx.x, gridDim.x), r = 0, 1, ...;
 // either way consecutive items run on one XCD.  `flip` selects the source
-// buffer (0: a -> b, 1: b -> a); AHEAD rows in flight as in step_tile.
+// buffer (0: a -> b, 1: b -> a); AHEAD rows in flight as in step_tile;
+// `step` is the batch's step count (every film's stochastic-rounding
+// counter, so that a film draws as it would stepped alone).
 template <typename R, typename S, typename C, bool TAU1, int EA, int EB, int AHEAD>
 __global__ void __launch_bounds__(256)
 batch_kernel(const BatchFilm<C>* __restrict__ films, const int2* __restrict__ items, int n_items,
-             unsigned char* __restrict__ buf_a, unsigned char* __restrict__ buf_b, int flip) {
+             unsigned char* __restrict__ buf_a, unsigned char* __restrict__ buf_b, int flip, uint32_t step) {
   const int slot = tile_of_block(blockIdx.x, gridDim.x);
   for (int w = slot; w < n_items; w += gridDim.x) {
     const int2 item = items[w];
@@ -938,10 +942,10 @@ batch_kernel(const BatchFilm<C>* __restrict__ films, const int2* __restrict__ it
     const unsigned char* src = (flip ? buf_b : buf_a) + bf.offset;
     unsigned char* dst = (flip ? buf_a : buf_b) + bf.offset;
     switch (bf.nl) {
-      case 1: step_tile<R, S, C, 1, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
-      case 2: step_tile<R, S, C, 2, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
-      case 3: step_tile<R, S, C, 3, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
-      default: step_tile<R, S, C, 4, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y); break;
+      case 1: step_tile<R, S, C, 1, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y, step); break;
+      case 2: step_tile<R, S, C, 2, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y, step); break;
+      case 3: step_tile<R, S, C, 3, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y, step); break;
+      default: step_tile<R, S, C, 4, TAU1, EA, EB, AHEAD>(src, dst, bf.kc, item.y, step); break;
     }
     __syncthreads();  // LDS rings are reused by the next item
   }

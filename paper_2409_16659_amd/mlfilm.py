@@ -124,6 +124,8 @@ def load_library():
         "mlf_batch_set_launch": (st, [H, C.c_int32, C.c_int32, C.c_int32]),
         "mlf_batch_set_prefetch": (st, [H, C.c_int32]),
         "mlf_batch_get_prefetch": (st, [H, C.POINTER(C.c_int32)]),
+        "mlf_batch_set_rounding": (st, [H, C.c_int32]),
+        "mlf_batch_get_rounding": (st, [H, C.POINTER(C.c_int32)]),
         "mlf_batch_get_launch": (st, [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mlf_batch_autotune": (st, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
@@ -672,6 +674,16 @@ class Batch:
         v = C.c_int32()
         self._check(self.lib.mlf_batch_get_prefetch(self.h, C.byref(v)), "mlf_batch_get_prefetch")
         return v.value
+
+    def set_rounding(self, stochastic: bool):
+        """Stochastic rounding of every film's rest population (f16 / bf16
+        storage); a film draws as it would stepped alone."""
+        self._check(self.lib.mlf_batch_set_rounding(self.h, 1 if stochastic else 0), "mlf_batch_set_rounding")
+
+    def get_rounding(self) -> bool:
+        v = C.c_int32()
+        self._check(self.lib.mlf_batch_get_rounding(self.h, C.byref(v)), "mlf_batch_get_rounding")
+        return v.value == 1
 
     def get_launch(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

@@ -246,6 +246,32 @@ def test_set_rounding_validation():
             lib.mlf_destroy(h)
 
 
+def test_batch_set_rounding_validation():
+    """The batch form of the rounding mode: f16 / bf16 D2Q9 batches only,
+    unknown modes refused, 0 restores the default (no device access)."""
+    film = inputs.film_params(2, 64, 16, gamma=[0.01] * 2, mu=[0.01] * 2, hstar=0.1)
+    lib = mlfilm.load_library()
+    for prec, ok in [("f16", True), ("bf16", True), ("f16mix", False), ("f32", False)]:
+        ps = (mlfilm.Params * 2)(*[mlfilm.make_params(film, prec)] * 2)
+        b = C.c_void_p()
+        assert lib.mlf_batch_create(ps, 2, C.c_void_p(1 << 20), C.c_void_p(1 << 28), C.c_void_p(1 << 29),
+                                    None, C.byref(b)) == 0
+        try:
+            v = C.c_int32()
+            assert lib.mlf_batch_get_rounding(b, C.byref(v)) == 0 and v.value == 0
+            assert (lib.mlf_batch_set_rounding(b, 1) == 0) == ok, prec
+            lib.mlf_batch_get_rounding(b, C.byref(v))
+            assert v.value == (1 if ok else 0)
+            assert lib.mlf_batch_set_rounding(b, 3) != 0
+            assert lib.mlf_batch_set_rounding(b, 0) == 0
+            lib.mlf_batch_get_rounding(b, C.byref(v))
+            assert v.value == 0
+            assert lib.mlf_batch_get_rounding(b, None) != 0
+        finally:
+            lib.mlf_batch_destroy(b)
+    assert lib.mlf_batch_set_rounding(None, 1) != 0
+
+
 def test_surrogate_sizes_and_validation():
     from oracle import nop
 

@@ -106,6 +106,47 @@ def test_batch_two_rows_ahead_matches_single_films(mlf, prec, persistent):
         assert np.array_equal(uxb, uxs) and np.array_equal(uyb, uys), i
 
 
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_batch_stochastic_rounding_matches_single_films(mlf, prec):
+    """Stochastic rounding of the rest plane draws on each film's node
+    index, layer and step count: every film of a batch is bit-identical to
+    the same film stepped alone with stochastic rounding (and differs from
+    round-to-nearest); a batch with it refuses graph capture."""
+    films = scan(6, seed=17)
+    launch = (128, 6)
+    b = mlf.Batch([f for f, _ in films], prec)
+    r = mlf.Batch([f for f, _ in films], prec)
+    for bb in (b, r):
+        bb.set_launch(*launch, 0)
+        for i, (_, h0) in enumerate(films):
+            bb.init(i, h0)
+    assert not b.get_rounding()
+    b.set_rounding(True)
+    assert b.get_rounding() and not r.get_rounding()
+    steps = 29
+    b.step(steps)
+    r.step(steps)
+    say(f"batch {prec} stochastic rounding: {len(films)} films, launch {b.get_launch()}")
+    differs = 0
+    for i, (film, h0) in enumerate(films):
+        g = mlf.Film(film, prec)
+        g.set_launch(*launch)
+        g.set_rounding(True)
+        g.init(h0)
+        g.step(steps)
+        hs, uxs, uys = g.read()
+        hb, uxb, uyb = b.read(i)
+        assert np.array_equal(hb, hs), i
+        assert np.array_equal(uxb, uxs) and np.array_equal(uyb, uys), i
+        differs += not np.array_equal(hb, r.read(i)[0])
+    assert differs == len(films)
+    with pytest.raises(mlf.MlfError) as ex:
+        b.capture(8)
+    assert ex.value.status == "EUNSUPPORTED"
+    b.set_rounding(False)
+    b.capture(8)   # round-to-nearest batches capture again
+
+
 def test_batch_fp64_against_oracle(mlf, oracle_mod):
     films = scan(3, seed=7, side_max=96)
     # one film with slip lengths next to no-slip films
