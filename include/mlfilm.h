@@ -236,8 +236,9 @@ mlf_status mlf_get_prefetch(const mlf_handle* h, int32_t* rows);
  * rounded to the representable value below or above it, the upper one with
  * probability equal to its distance from the lower one over their gap, so
  * that height changes below half an ulp accumulate on average instead of
- * being lost.  The draws are a counter-based hash of (node, layer, step
- * count): results are reproducible and independent of the launch shape,
+ * being lost.  The draws are 16-bit uniforms, two per counter-based hash
+ * of (node, pair of layers, step count): results are reproducible and
+ * independent of the launch shape,
  * but differ from round-to-nearest ones.  A film with stochastic rounding
  * cannot be captured into a graph (MLF_EUNSUPPORTED from mlf_capture).
  * Drops a captured graph.  mlf_get_rounding writes the current mode (mode

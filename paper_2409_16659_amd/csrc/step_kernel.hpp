@@ -186,20 +186,24 @@ __host__ __device__ inline uint32_t mix32(uint32_t x) {
   return x;
 }
 
-// Uniform draw in [0, 1) (24 bits) for layer `layer` of node `node` at step
-// `step`: a counter-based hash, so the draw depends on where and when it is
-// taken, not on the launch shape.
-__device__ inline float sr_uniform(uint32_t node, int layer, uint32_t step) {
-  const uint32_t h = mix32(mix32(node * 4u + (uint32_t)layer) ^ mix32(step + 0x9e3779b9u));
-  return (float)(h >> 8) * 0x1p-24f;
+// Random bits of pair `pair` of layers (2 pair and 2 pair + 1 take the low
+// and high 16 bits) of node `node` at the step whose key is `step_key`
+// (mix32 of the step count, the same for the whole launch): a counter-based
+// hash, so the draws depend on where and when they are taken, not on the
+// launch shape.
+__device__ inline uint32_t sr_bits(uint32_t node, int pair, uint32_t step_key) {
+  return mix32((node * 2u + (uint32_t)pair) ^ step_key);
 }
 
-// Stochastic rounding of v to the 16-bit type T: the representable value
-// just below or just above v, the upper one with probability equal to v's
-// distance from the lower one over their gap, so the rounding error has
-// zero mean.  Values T holds exactly are returned unchanged.
+// Stochastic rounding of v to the 16-bit type T with the 16-bit uniform
+// k16: the representable value just below or just above v, the upper one
+// with probability equal to v's distance from the lower one over their gap
+// (to 2^-16), so the rounding error has zero mean.  The gap is a power of
+// two, so (k16 2^-16) gap and v - lo are exact in FP32 (away from the
+// 16-bit type's smallest subnormals) and the comparison needs no division.
+// Values T holds exactly are returned unchanged.
 template <typename T>
-__device__ inline float sr_round(float v, float u) {
+__device__ inline float sr_round(float v, uint32_t k16) {
   constexpr bool kHalf = std::is_same_v<T, _Float16>;
   const uint32_t b = kHalf ? f32_to_half_bits(v) : f32_to_bf16_bits(v);  // nearest
   const float n = kHalf ? half_bits_to_f32(b) : bf16_bits_to_f32(b);
@@ -213,8 +217,7 @@ __device__ inline float sr_round(float v, float u) {
     o = neg ? b + 1 : (b == 0u ? 0x8001u : b - 1);
   const float m = kHalf ? half_bits_to_f32(o) : bf16_bits_to_f32(o);
   const float lo = n < m ? n : m, hi = n < m ? m : n;
-  const float p = (v - lo) / (hi - lo);
-  return u < p ? hi : lo;
+  return (float)k16 * 0x1p-16f * (hi - lo) < v - lo ? hi : lo;
 }
 
 // The NL populations of one direction at one node (layers next to each
@@ -819,9 +822,14 @@ __device__ inline void step_tile(const unsigned char* __restrict__ src, unsigned
         // conversion is exact (the scales are powers of two)
         if (kc.sr_on) {
           const uint32_t node = (uint32_t)y * (uint32_t)kc.nx + (uint32_t)x;
+          const uint32_t key = mix32(sr_step + 0x9e3779b9u);
+          uint32_t bits[(NL + 1) / 2];
+#pragma unroll
+          for (int j = 0; j < (NL + 1) / 2; ++j) bits[j] = sr_bits(node, j, key);
 #pragma unroll
           for (int i = 0; i < NL; ++i)
-            fo[i][0] = sr_round<R>(fo[i][0] * kc.scale[i], sr_uniform(node, i, sr_step)) * kc.iscale[i];
+            fo[i][0] = sr_round<R>(fo[i][0] * kc.scale[i], (bits[i / 2] >> (16 * (i % 2))) & 0xffffu) *
+                       kc.iscale[i];
         }
       }
       store_row(st_ok, oS, oC, oN, oR, fo);
