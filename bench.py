@@ -530,6 +530,8 @@ def film_point(workload, prec, args, steps, warmup, lattice="d2q9"):
     d1 = lattice == "d1q3"
     g = mlfilm.Film(film, prec, check_every=-1, lattice=lattice)
     g.init(h0)
+    if args.rounding == "stochastic" and workload == args.workload:
+        g.set_rounding(True)  # before the autotuner, which then times this path
     pl = None if (args.autotune or d1) else profiled_launch(workload, prec)
     if d1:
         source = "fixed (D1Q3 kernels)"
@@ -599,6 +601,8 @@ def main():
                     help="rows in flight in the step kernel with --block-w/--seg-h (0: default, 1 or 2); "
                          "with --ingest-kt: the profiled run's value")
     ap.add_argument("--autotune", action="store_true", help="always run the autotuner")
+    ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
+                    help="rounding of the stored rest population of --workload (stochastic: f16 / bf16 storage)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU-baseline budget on all host threads; 0 disables the CPU baseline")
     ap.add_argument("--cpu-single-seconds", type=float, default=8.0,
@@ -702,6 +706,8 @@ def main():
                    "storage": prec, "lattice": args.lattice.upper(), "tau": film["tau"],
                    "launch": list(pt["launch"]), "launch_source": pt["source"]},
     }
+    if args.rounding != "nearest":
+        out["config"]["rounding"] = args.rounding
     if resident:
         out["roofline"] = None
         out["note"] = (f"{args.lattice.upper()} pseudo-1D film held in LDS for many steps per launch: "
